@@ -1,0 +1,37 @@
+"""FP64 CPU oracle of the partitioned LMMSE channel estimator.
+
+TEST INFRASTRUCTURE ONLY.  Nothing on the product path imports, links or runs
+anything in this package: only the tests, the smoke check and the benchmark's
+CPU-baseline leg do.  It shares no code with the HIP library.
+
+Everything here is plain NumPy/SciPy in complex128, written step by step from
+the paper (Sec. IV-A: LS eq. 8-9, LMMSE eq. 12-15, fixed design eq. 16 /
+r_d and eq. 17; Sec. IV-B: partitioning of the correlation matrix into small
+overlapping or non-overlapping blocks, Tables I-II) plus the readings of the
+points the paper leaves open, which are listed in each function.
+"""
+from .lmmse import (  # noqa: F401
+    apply_filters,
+    block_filters,
+    comb_group_table,
+    cover_code,
+    despread,
+    discrepancy_db,
+    estimate,
+    expected_mse,
+    full_lmmse_filter,
+    nmse,
+    nmse_db,
+    r_exponential,
+    r_exponential_cont,
+    r_uniform,
+    sample_covariance,
+    toeplitz_from_r,
+    window_starts,
+)
+from .grad import (  # noqa: F401
+    dr_exponential_dtau,
+    grad_fixed_design,
+    grad_sample_cov,
+    mse_loss_and_grad,
+)
