@@ -1,0 +1,223 @@
+/*
+ * lmmse.h - C ABI of the partitioned LMMSE channel estimator for gfx950.
+ *
+ * The estimator follows Sec. IV of the paper: least-squares estimates at the
+ * pilots (eq. 8-9), an LMMSE weighting of them (eq. 12) with the weight of
+ * eq. 13 / eq. 17 computed from a subcarrier correlation (eq. 14-16), and the
+ * dimension reduction of Sec. IV-B that partitions the N x N correlation into
+ * small blocks with overlapping or non-overlapping input windows
+ * (Tables I-II).
+ *
+ * Problem layout (all device buffers are caller-owned, complex numbers are
+ * interleaved (re, im), subcarrier index fastest):
+ *   y_pilot  complex64 [S][M][K][N]  received pilot symbols: slot s, antenna m,
+ *                                    pilot OFDM symbol t (K of them), subcarrier n
+ *   pilots   complex64 [K][N]        unit-modulus pilot x_k[n] of user k
+ *   h_ls     complex64 [S][M][K][N]  LS estimate (user k third)
+ *   h_hat    complex64 [S][M][K][N]  LMMSE estimate
+ * User k sends c[k,t] x_k[n] on pilot symbol t, c[k,t] = exp(-j 2 pi k t / K)
+ * (a K x K DFT cover code), so LS despreading is
+ *   h_ls[s,m,k,n] = conj(x_k[n]) (1/K) sum_t conj(c[k,t]) y[s,m,t,n]
+ * and the LS noise variance is lam = sigma2 / K, which the filters use where
+ * eq. 13 writes sigma^2 / sigma_s^2.
+ *
+ * Block plan: output block b = subcarriers [b*B, (b+1)*B) is estimated from
+ * the window [start_b, start_b + Wn) with
+ *   start_b = clamp(b*B - (Wn-B)/2, 0, N - Wn)
+ * i.e. the window is centred on its block and shifted (never truncated) at
+ * the band edges, as in Tables I-II.  Wn == B is the non-overlapping
+ * partition, B == Wn == N the full-band LMMSE of eq. 13.  Requirements:
+ * N % B == 0, (Wn - B) even, B <= Wn <= N.
+ *
+ * Correlation sources:
+ *   LMMSE_R_UNIFORM      fixed design of eq. 16 with assumed channel length L
+ *                        (in samples, relative to N_fft):
+ *                        r_d = (1 - exp(-j2 pi L d/N_fft)) / (j2 pi L d/N_fft)
+ *   LMMSE_R_EXPONENTIAL  fixed design from the exponential power-delay
+ *                        profile of Sec. IV-A on integer taps l < taps:
+ *                        r_d = sum_l p_l exp(-j2 pi l d/N_fft), p_l ~ e^{-l/tau}
+ *   LMMSE_R_SAMPLE       raw sample covariance over the M antennas, per
+ *                        (slot, user, window): R = (1/M) sum_m h h^H
+ *   LMMSE_R_USER         filters supplied by the caller (lmmse_set_filters)
+ * For a fixed design every block whose window sits at the same offset
+ * start_b - b*B shares one filter ("class"); there are at most 3 classes
+ * when the halo (Wn-B)/2 is at most B (first, interior, last block).
+ *
+ * Precision: filters are designed in FP64 (Cholesky of R_II + lam I and two
+ * triangular solves).  The filtering GEMM runs in FP32 on the matrix cores
+ * (LMMSE_FP32), or as split products hi*hi + hi*lo + lo*hi with FP32
+ * accumulation in BF16 (LMMSE_BF16X3) or FP16 (LMMSE_FP16X3).
+ *
+ * Errors: every call returns an lmmse_status.  No exception crosses the ABI.
+ * Device-side conditions (a non-positive pivot in a factorisation) are
+ * recorded in a plan-owned status word, read by lmmse_sync_status.
+ * Threading: a plan is not thread-safe; distinct plans are independent.
+ * Streams: kernels run on the stream passed in (a hipStream_t, 0 = default
+ * stream); calls return without synchronising unless stated.
+ */
+#ifndef LMMSE_H
+#define LMMSE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum lmmse_status {
+    LMMSE_OK = 0,
+    LMMSE_ERR_INVALID_ARG = 1,   /* null pointer, bad size, bad enum         */
+    LMMSE_ERR_UNSUPPORTED = 2,   /* plan shape the library does not handle   */
+    LMMSE_ERR_WORKSPACE = 3,     /* workspace missing or too small           */
+    LMMSE_ERR_HIP = 4,           /* a HIP runtime call failed                */
+    LMMSE_ERR_NOT_PD = 5,        /* R_II + lam I not positive definite       */
+    LMMSE_ERR_NOT_READY = 6,     /* no filters designed or set yet           */
+    LMMSE_ERR_NO_DEVICE = 7      /* no usable gfx950 device                  */
+} lmmse_status;
+
+typedef enum lmmse_rsource {
+    LMMSE_R_UNIFORM = 0,
+    LMMSE_R_EXPONENTIAL = 1,
+    LMMSE_R_SAMPLE = 2,
+    LMMSE_R_USER = 3
+} lmmse_rsource;
+
+typedef enum lmmse_precision {
+    LMMSE_FP32 = 0,
+    LMMSE_BF16X3 = 1,
+    LMMSE_FP16X3 = 2
+} lmmse_precision;
+
+/* Plan descriptor.  Sizes are counts; tau_rms and L are in samples. */
+typedef struct lmmse_plan_desc {
+    int M;           /* BS antennas                                  (>= 1) */
+    int K;           /* users = pilot OFDM symbols                   (1..64) */
+    int N;           /* used subcarriers                                    */
+    int N_fft;       /* FFT size (>= N)                                     */
+    int B;           /* output block size                                   */
+    int Wn;          /* input window size                                   */
+    int rsource;     /* lmmse_rsource                                       */
+    int precision;   /* lmmse_precision                                     */
+    int max_slots;   /* largest S any call on this plan will pass  (>= 1)   */
+    int taps;        /* LMMSE_R_EXPONENTIAL: number of integer taps (>= 1)   */
+    double tau_rms;  /* LMMSE_R_EXPONENTIAL: profile decay (> 0)            */
+    double L;        /* LMMSE_R_UNIFORM: assumed channel length (> 0)       */
+    double sigma2;   /* design noise variance per resource element (> 0)    */
+} lmmse_plan_desc;
+
+typedef struct lmmse_plan *lmmse_plan_t;
+
+/* ---- host-only calls (no device needed) -------------------------------- */
+
+/* Static text for a status code; never NULL. */
+const char *lmmse_status_string(int status);
+
+/* ABI version: major * 10000 + minor * 100 + patch. */
+int lmmse_version(void);
+
+/* Checks a descriptor without touching a device.  Returns LMMSE_OK,
+ * LMMSE_ERR_INVALID_ARG (nonsensical values) or LMMSE_ERR_UNSUPPORTED. */
+int lmmse_plan_validate(const lmmse_plan_desc *desc);
+
+/* Block plan of Sec. IV-B (see top of file).  starts and offsets receive
+ * N/B ints each, classes N/B ints with the filter class of every block;
+ * *n_classes receives the number of distinct window offsets.  Any output
+ * pointer may be NULL.  Host memory. */
+int lmmse_block_plan(int N, int B, int Wn, int *starts, int *offsets,
+                     int *classes, int *n_classes);
+
+/* Workspace bytes lmmse_estimate / lmmse_backward need for `slots` slots
+ * (0 for paths that need none).  Host memory output. */
+int lmmse_workspace_size(const lmmse_plan_desc *desc, int slots, size_t *bytes);
+
+/* ---- plan lifetime ------------------------------------------------------ */
+
+/* Validates desc, allocates the plan's device buffers (filter bank, FP64
+ * factors, status word) on the current device and, for the fixed designs,
+ * builds the filters from desc (synchronously).  *out is set only on
+ * success.  Errors: INVALID_ARG, UNSUPPORTED, NO_DEVICE, HIP, NOT_PD. */
+int lmmse_plan_create(const lmmse_plan_desc *desc, lmmse_plan_t *out);
+
+/* Frees the plan and its device memory (synchronises the device first). */
+int lmmse_plan_destroy(lmmse_plan_t plan);
+
+/* Copies the descriptor the plan was created with (tau_rms / sigma2 updated
+ * by the last lmmse_set_design). */
+int lmmse_plan_get_desc(lmmse_plan_t plan, lmmse_plan_desc *out);
+
+/* ---- filter design (eq. 13 / eq. 17 per block, FP64) --------------------- */
+
+/* Rebuilds a fixed design (UNIFORM or EXPONENTIAL) with a new tau_rms
+ * (EXPONENTIAL only; ignored for UNIFORM) and design noise sigma2, on
+ * `stream`: r_d, A = R_II + lam I, Cholesky, two triangular solves per
+ * class, then the FP32 / split copies.  Asynchronous.  A failed
+ * factorisation is reported by lmmse_sync_status. */
+int lmmse_set_design(lmmse_plan_t plan, double tau_rms, double sigma2, void *stream);
+
+/* Installs caller filters (LMMSE_R_USER plans): w is device complex128
+ * [n_classes][B][Wn], row-major per filter, class order as lmmse_block_plan
+ * numbers them.  Asynchronous (reads w on `stream`). */
+int lmmse_set_filters(lmmse_plan_t plan, const void *w, void *stream);
+
+/* Copies the current FP64 filters of a fixed-design or user plan to device
+ * complex128 [n_classes][B][Wn].  Asynchronous. */
+int lmmse_get_filters(lmmse_plan_t plan, void *w_out, void *stream);
+
+/* ---- forward path ------------------------------------------------------- */
+
+/* LS despreading only (eq. 8-9 with the cover code): y_pilot -> h_ls. */
+int lmmse_despread(lmmse_plan_t plan, int slots, const void *y_pilot,
+                   const void *pilots, void *h_ls, void *stream);
+
+/* Filtering only (eq. 12 per block) with the plan's fixed or user filters:
+ * h_ls -> h_hat, at the plan's precision. */
+int lmmse_apply(lmmse_plan_t plan, int slots, const void *h_ls, void *h_hat,
+                void *stream);
+
+/* Sample covariance per (slot, user, window), a Hermitian rank-M update
+ * accumulated in FP32 and stored as complex128 [S][K][N/B][Wn][Wn]. */
+int lmmse_covariance(lmmse_plan_t plan, int slots, const void *h_ls,
+                     void *r_win, void *stream);
+
+/* Batched FP64 block filters from window correlations r_win (complex128
+ * [S][K][N/B][Wn][Wn], e.g. from lmmse_covariance): for block b,
+ * W = R[off_b : off_b + B, :] (R + (sigma2/K) I)^-1, stored as complex128
+ * [S][K][N/B][B][Wn]. */
+int lmmse_sample_filters(lmmse_plan_t plan, int slots, const void *r_win,
+                         double sigma2, void *w_out, void *stream);
+
+/* The whole estimator, estimate(y_pilot, pilots, sigma2, block plan) -> h_hat.
+ * Fixed/user designs: a fused despread + filter launch with the plan's
+ * filters (redesigned first if sigma2 differs from the design's).
+ * Sample covariance: despread, covariance, FP64 block design with lam =
+ * sigma2 / K, filter.  ws: device workspace of lmmse_workspace_size bytes
+ * (may be NULL when that size is 0). */
+int lmmse_estimate(lmmse_plan_t plan, int slots, const void *y_pilot,
+                   const void *pilots, double sigma2, void *h_hat,
+                   void *ws, size_t ws_bytes, void *stream);
+
+/* ---- backward path ------------------------------------------------------- */
+
+/* Gradients of a real loss through the estimator, given g = dL/dRe(h_hat) +
+ * j dL/dIm(h_hat) (complex64 [S][M][K][N]).  Writes d_hls (same layout) and,
+ * when the pointers are non-NULL, the host doubles *d_tau (EXPONENTIAL
+ * design only; NaN otherwise) and *d_sigma2 (fixed and sample designs);
+ * requesting them synchronises `stream`.  For the sample covariance, d_hls
+ * includes the path through R. ws: lmmse_workspace_size bytes. */
+int lmmse_backward(lmmse_plan_t plan, int slots, const void *h_ls,
+                   const void *g, void *d_hls, double *d_tau, double *d_sigma2,
+                   void *ws, size_t ws_bytes, void *stream);
+
+/* ---- status ------------------------------------------------------------- */
+
+/* Synchronises `stream`, returns LMMSE_OK or the first device-detected error
+ * since the last call (then clears it); *info (may be NULL) receives the
+ * index of the failing matrix (slot * K * N/B + user * N/B + block for the
+ * sample path, the class for fixed designs) or -1. */
+int lmmse_sync_status(lmmse_plan_t plan, void *stream, int *info);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LMMSE_H */

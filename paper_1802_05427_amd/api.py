@@ -1,0 +1,217 @@
+"""Thin Python binding of the C ABI over torch tensors.
+
+Argument marshalling only: shapes, dtypes and devices are checked, device
+pointers and the current HIP stream are passed to liblmmse.so, and every step
+of the estimator runs in the library's kernels.  Torch supplies device memory
+(including the workspace) and the stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+
+import torch
+
+from . import _lib
+from ._lib import PlanDesc, check
+
+_RSOURCE = {"uniform": _lib.R_UNIFORM, "exp": _lib.R_EXPONENTIAL,
+            "sample": _lib.R_SAMPLE, "user": _lib.R_USER}
+_PREC = {"fp32": _lib.FP32, "bf16x3": _lib.BF16X3, "fp16x3": _lib.FP16X3}
+
+
+def make_desc(M, K, N, N_fft, B, Wn, rsource="exp", precision="fp32", max_slots=1,
+              taps=1, tau_rms=1.0, L=1.0, sigma2=0.1) -> PlanDesc:
+    return PlanDesc(M=int(M), K=int(K), N=int(N), N_fft=int(N_fft), B=int(B), Wn=int(Wn),
+                    rsource=_RSOURCE[rsource] if isinstance(rsource, str) else int(rsource),
+                    precision=_PREC[precision] if isinstance(precision, str) else int(precision),
+                    max_slots=int(max_slots), taps=int(taps), tau_rms=float(tau_rms),
+                    L=float(L), sigma2=float(sigma2))
+
+
+def block_plan(N: int, B: int, Wn: int):
+    """(starts, offsets, classes, n_classes) of the block plan (host only)."""
+    lib = _lib.load()
+    nb = N // B if B > 0 else 0
+    s = (ctypes.c_int * max(nb, 1))()
+    o = (ctypes.c_int * max(nb, 1))()
+    c = (ctypes.c_int * max(nb, 1))()
+    n = ctypes.c_int(0)
+    check(lib.lmmse_block_plan(N, B, Wn, s, o, c, ctypes.byref(n)), "lmmse_block_plan")
+    return list(s[:nb]), list(o[:nb]), list(c[:nb]), n.value
+
+
+def workspace_size(desc: PlanDesc, slots: int) -> int:
+    lib = _lib.load()
+    b = ctypes.c_size_t(0)
+    check(lib.lmmse_workspace_size(ctypes.byref(desc), int(slots), ctypes.byref(b)),
+          "lmmse_workspace_size")
+    return b.value
+
+
+def _stream_ptr(stream=None) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """An estimator plan on the current GPU (see include/lmmse.h)."""
+
+    def __init__(self, **kw):
+        self._lib = _lib.load()
+        self.desc = make_desc(**kw)
+        h = ctypes.c_void_p()
+        check(self._lib.lmmse_plan_create(ctypes.byref(self.desc), ctypes.byref(h)),
+              "lmmse_plan_create")
+        self._h = h
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.starts, self.offsets, self.classes, self.n_classes = block_plan(
+            self.desc.N, self.desc.B, self.desc.Wn)
+        self._ws = None
+
+    # ---- lifetime
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.lmmse_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # ---- helpers
+    @property
+    def nb(self) -> int:
+        return self.desc.N // self.desc.B
+
+    def _check_cols(self, t: torch.Tensor, name: str) -> int:
+        d = self.desc
+        if t.dtype != torch.complex64 or t.device.type != "cuda" or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous complex64 CUDA tensor")
+        if t.dim() != 4 or tuple(t.shape[1:]) != (d.M, d.K, d.N):
+            raise ValueError(f"{name} must be [S, {d.M}, {d.K}, {d.N}], got {tuple(t.shape)}")
+        if t.shape[0] > d.max_slots:
+            raise ValueError(f"{name}: {t.shape[0]} slots exceed max_slots={d.max_slots}")
+        return int(t.shape[0])
+
+    def _check_pilots(self, p: torch.Tensor):
+        d = self.desc
+        if (p.dtype != torch.complex64 or p.device.type != "cuda" or not p.is_contiguous()
+                or tuple(p.shape) != (d.K, d.N)):
+            raise ValueError(f"pilots must be a contiguous complex64 CUDA [{d.K}, {d.N}] tensor")
+
+    def workspace_bytes(self, slots: int) -> int:
+        return workspace_size(self.desc, slots)
+
+    def _workspace(self, slots: int) -> tuple[ctypes.c_void_p, int]:
+        need = self.workspace_bytes(slots)
+        if need == 0:
+            return ctypes.c_void_p(0), 0
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        return _ptr(self._ws), int(self._ws.numel())
+
+    # ---- design
+    def set_design(self, tau_rms: float, sigma2: float, stream=None):
+        check(self._lib.lmmse_set_design(self._h, float(tau_rms), float(sigma2), _stream_ptr(stream)),
+              "lmmse_set_design")
+
+    def set_filters(self, w: torch.Tensor, stream=None):
+        d = self.desc
+        if (w.dtype != torch.complex128 or w.device.type != "cuda" or not w.is_contiguous()
+                or tuple(w.shape) != (self.n_classes, d.B, d.Wn)):
+            raise ValueError(f"w must be a contiguous complex128 CUDA [{self.n_classes}, {d.B}, {d.Wn}] tensor")
+        check(self._lib.lmmse_set_filters(self._h, _ptr(w), _stream_ptr(stream)), "lmmse_set_filters")
+
+    def get_filters(self, stream=None) -> torch.Tensor:
+        d = self.desc
+        w = torch.empty((self.n_classes, d.B, d.Wn), dtype=torch.complex128, device=self.device)
+        check(self._lib.lmmse_get_filters(self._h, _ptr(w), _stream_ptr(stream)), "lmmse_get_filters")
+        return w
+
+    # ---- forward
+    def despread(self, y, pilots, out=None, stream=None) -> torch.Tensor:
+        S = self._check_cols(y, "y")
+        self._check_pilots(pilots)
+        out = torch.empty_like(y) if out is None else out
+        self._check_cols(out, "out")
+        check(self._lib.lmmse_despread(self._h, S, _ptr(y), _ptr(pilots), _ptr(out), _stream_ptr(stream)),
+              "lmmse_despread")
+        return out
+
+    def apply(self, h_ls, out=None, stream=None) -> torch.Tensor:
+        S = self._check_cols(h_ls, "h_ls")
+        out = torch.empty_like(h_ls) if out is None else out
+        self._check_cols(out, "out")
+        check(self._lib.lmmse_apply(self._h, S, _ptr(h_ls), _ptr(out), _stream_ptr(stream)), "lmmse_apply")
+        return out
+
+    def covariance(self, h_ls, out=None, stream=None) -> torch.Tensor:
+        S = self._check_cols(h_ls, "h_ls")
+        d = self.desc
+        shape = (S, d.K, self.nb, d.Wn, d.Wn)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.complex128, device=self.device)
+        elif tuple(out.shape) != shape or out.dtype != torch.complex128 or not out.is_contiguous():
+            raise ValueError(f"out must be a contiguous complex128 {shape} tensor")
+        check(self._lib.lmmse_covariance(self._h, S, _ptr(h_ls), _ptr(out), _stream_ptr(stream)),
+              "lmmse_covariance")
+        return out
+
+    def sample_filters(self, r_win, sigma2: float, out=None, stream=None) -> torch.Tensor:
+        d = self.desc
+        if r_win.dtype != torch.complex128 or r_win.dim() != 5 or not r_win.is_contiguous() \
+                or tuple(r_win.shape[1:]) != (d.K, self.nb, d.Wn, d.Wn):
+            raise ValueError("r_win must be a contiguous complex128 [S, K, N/B, Wn, Wn] tensor")
+        S = int(r_win.shape[0])
+        shape = (S, d.K, self.nb, d.B, d.Wn)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.complex128, device=self.device)
+        check(self._lib.lmmse_sample_filters(self._h, S, _ptr(r_win), float(sigma2), _ptr(out),
+                                             _stream_ptr(stream)), "lmmse_sample_filters")
+        return out
+
+    def estimate(self, y, pilots, sigma2: float, out=None, stream=None) -> torch.Tensor:
+        """estimate(y_pilot, pilots, sigma2, block plan) -> h_hat."""
+        S = self._check_cols(y, "y")
+        self._check_pilots(pilots)
+        out = torch.empty_like(y) if out is None else out
+        self._check_cols(out, "out")
+        ws, wsb = self._workspace(S)
+        check(self._lib.lmmse_estimate(self._h, S, _ptr(y), _ptr(pilots), float(sigma2), _ptr(out),
+                                       ws, wsb, _stream_ptr(stream)), "lmmse_estimate")
+        return out
+
+    # ---- backward
+    def backward(self, h_ls, g, want_params: bool = True, out=None, stream=None):
+        """Returns (d_hls, d_tau, d_sigma2); the scalars are None unless requested."""
+        S = self._check_cols(h_ls, "h_ls")
+        self._check_cols(g, "g")
+        out = torch.empty_like(h_ls) if out is None else out
+        ws, wsb = self._workspace(S)
+        dt = ctypes.c_double(math.nan)
+        ds = ctypes.c_double(math.nan)
+        check(self._lib.lmmse_backward(self._h, S, _ptr(h_ls), _ptr(g), _ptr(out),
+                                       ctypes.byref(dt) if want_params else None,
+                                       ctypes.byref(ds) if want_params else None,
+                                       ws, wsb, _stream_ptr(stream)), "lmmse_backward")
+        if want_params:
+            return out, dt.value, ds.value
+        return out, None, None
+
+    def sync_status(self, stream=None):
+        info = ctypes.c_int(-1)
+        st = self._lib.lmmse_sync_status(self._h, _stream_ptr(stream), ctypes.byref(info))
+        return st, info.value

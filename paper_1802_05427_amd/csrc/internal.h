@@ -1,0 +1,91 @@
+// Internal declarations shared by the host API and the HIP kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "../../include/lmmse.h"
+
+namespace lmmse {
+
+// Sizes of the filter layouts the GEMM kernels read.
+//  * FP32 "A-ready" bank: for each class, groups g of 8 complex window rows
+//    (16 reals), rows r of the real embedding padded to Rpad = 16*ceil(2B/16),
+//    4 lanes q, 4 floats:  bank[((c*G8 + g)*Rpad + r)*4 + q] (float4) holds
+//    Wr[r][16g + 4q + i], i = 0..3, where Wr is the 2B x 2Wn real embedding
+//    of the complex filter (rows 2a, 2a+1 = Re, Im of output a; columns
+//    2j, 2j+1 = Re, Im of input j).
+//  * split bank: for each class, groups of 16 complex rows (32 reals), rows
+//    r < Rpad, 4 lanes kq, 8 halves:  hi/lo[(((c*G16 + g)*Rpad + r)*4 + kq)*8 + e]
+//    = Wr[r][32g + 8kq + e].
+struct Plan {
+    lmmse_plan_desc d{};
+    int device = 0;
+    int nb = 0;          // number of blocks N/B
+    int halo = 0;        // (Wn-B)/2
+    int n_classes = 0;
+    int RT = 0;          // 16-row MFMA tiles per workgroup row group
+    int rgroups = 0;     // row groups per block: RT*16*rgroups = Rpad >= 2B
+    int Rpad = 0;        // padded real rows of a filter (RT*16*rgroups)
+    int G8 = 0;          // ceil(Wn/8)
+    int G16 = 0;         // ceil(Wn/16)
+    std::vector<int> h_starts, h_offsets, h_classes, h_class_off;
+    int* d_starts = nullptr;     // [nb]
+    int* d_classes = nullptr;    // [nb]
+    int* d_class_off = nullptr;  // [n_classes]
+    double2* w64 = nullptr;      // [n_classes][B][Wn] FP64 filters
+    double2* fmat = nullptr;     // [Wn][Wn] work: A^-1 R_II  (fixed design)
+    double2* chol = nullptr;     // [Wn][Wn] Cholesky factor of R_II + lam I
+    double2* rd = nullptr;       // [2][Wn] r_d and dr_d/dtau, d = 0..Wn-1
+    float4* wf32 = nullptr;      // FP32 bank
+    uint16_t* whi = nullptr;     // split bank, hi part
+    uint16_t* wlo = nullptr;     // split bank, lo part
+    float2* twiddle = nullptr;   // [K] exp(+j 2 pi r / K)
+    int* status = nullptr;       // [2] device status word: code, info
+    double* dscal = nullptr;     // [4] device scratch for the design backward
+    bool ready = false;
+    double design_sigma2 = 0.0;
+    double design_tau = 0.0;
+    float lo_scale = 1.0f;       // split-bank lo scale (FP16: 2^11)
+};
+
+size_t fixed_bank_f32_elems(const Plan& p);    // float4 elements
+size_t split_bank_elems(const Plan& p);        // uint16 elements per part
+
+// ---- launchers (return hipError_t of the launch) ----
+hipError_t launch_despread(const Plan& p, int slots, const float2* y, const float2* pilots,
+                           float2* hls, hipStream_t st);
+hipError_t launch_apply_f32(const Plan& p, int slots, const float2* x, const float2* pilots,
+                            bool fused, float2* out, hipStream_t st);
+hipError_t launch_apply_split(const Plan& p, int slots, const float2* x, const float2* pilots,
+                              bool fused, float2* out, hipStream_t st);
+bool apply_fusable(const Plan& p);
+
+// Fixed design: r_d (and d r_d / d tau) on the device, A = R_II + lam I,
+// Cholesky, F = A^-1 R_II, then class filters W_c = (F^H)[off_c rows].
+hipError_t launch_fixed_design(Plan& p, double tau, double sigma2, hipStream_t st);
+// Convert p.w64 into the FP32 and split banks.
+hipError_t launch_pack_banks(Plan& p, hipStream_t st);
+
+// Sample-covariance path.
+hipError_t launch_covariance(const Plan& p, int slots, const float2* hls, double2* r_win,
+                             hipStream_t st);
+hipError_t launch_batched_filters(const Plan& p, int nmat, double2* a_work, double2* rhs_work,
+                                  const double2* r_win, double lam, double2* w_out,
+                                  hipStream_t st);
+hipError_t launch_sample_estimate(const Plan& p, int slots, const float2* hls, double lam,
+                                  float2* out, void* ws, hipStream_t st);
+size_t sample_workspace_bytes(const lmmse_plan_desc& d, int slots);
+
+// Backward.
+size_t backward_workspace_bytes(const lmmse_plan_desc& d, int slots);
+hipError_t launch_backward_fixed(Plan& p, int slots, const float2* hls, const float2* g,
+                                 float2* dhls, bool want_params, void* ws, hipStream_t st);
+hipError_t launch_backward_sample(Plan& p, int slots, const float2* hls, const float2* g,
+                                  float2* dhls, double lam, bool want_sigma, void* ws,
+                                  hipStream_t st);
+
+}  // namespace lmmse

@@ -1,0 +1,435 @@
+// Host side of the C ABI declared in include/lmmse.h: argument checks, the
+// block plan, plan-owned device memory and dispatch to the kernel launchers.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+using namespace lmmse;
+
+// The opaque handle of the C ABI is the plan itself.
+struct lmmse_plan : lmmse::Plan {};
+
+namespace {
+
+constexpr int kMaxK = 64;
+constexpr int kMaxWindow = 4096;     // FP64 design: pivot column cached in 64 KB of LDS
+constexpr int kRTs[] = {1, 2, 4, 8, 9, 13, 15, 17};
+
+#define LMMSE_HIP_TRY(expr)                       \
+    do {                                          \
+        hipError_t _e = (expr);                   \
+        if (_e != hipSuccess) return LMMSE_ERR_HIP; \
+    } while (0)
+
+int block_plan_impl(int N, int B, int Wn, std::vector<int>& starts, std::vector<int>& offs,
+                    std::vector<int>& cls, std::vector<int>& class_off) {
+    if (N <= 0 || B <= 0 || Wn <= 0) return LMMSE_ERR_INVALID_ARG;
+    if (N % B != 0 || Wn < B || Wn > N || ((Wn - B) & 1)) return LMMSE_ERR_UNSUPPORTED;
+    const int nb = N / B, halo = (Wn - B) / 2;
+    starts.assign(nb, 0);
+    offs.assign(nb, 0);
+    cls.assign(nb, 0);
+    class_off.clear();
+    for (int b = 0; b < nb; ++b) {
+        const int s = std::min(std::max(b * B - halo, 0), N - Wn);
+        starts[b] = s;
+        offs[b] = b * B - s;
+        auto it = std::find(class_off.begin(), class_off.end(), offs[b]);
+        if (it == class_off.end()) {
+            cls[b] = (int)class_off.size();
+            class_off.push_back(offs[b]);
+        } else {
+            cls[b] = (int)(it - class_off.begin());
+        }
+    }
+    return LMMSE_OK;
+}
+
+int validate(const lmmse_plan_desc* d) {
+    if (!d) return LMMSE_ERR_INVALID_ARG;
+    if (d->M < 1 || d->K < 1 || d->N < 1 || d->N_fft < d->N || d->B < 1 || d->Wn < 1 ||
+        d->max_slots < 1)
+        return LMMSE_ERR_INVALID_ARG;
+    if (d->rsource < LMMSE_R_UNIFORM || d->rsource > LMMSE_R_USER) return LMMSE_ERR_INVALID_ARG;
+    if (d->precision < LMMSE_FP32 || d->precision > LMMSE_FP16X3) return LMMSE_ERR_INVALID_ARG;
+    if (d->rsource == LMMSE_R_EXPONENTIAL &&
+        (d->taps < 1 || d->taps > d->N_fft || !(d->tau_rms > 0.0) || !std::isfinite(d->tau_rms)))
+        return LMMSE_ERR_INVALID_ARG;
+    if (d->rsource == LMMSE_R_UNIFORM && (!(d->L > 0.0) || !std::isfinite(d->L)))
+        return LMMSE_ERR_INVALID_ARG;
+    if ((d->rsource == LMMSE_R_UNIFORM || d->rsource == LMMSE_R_EXPONENTIAL) &&
+        (!(d->sigma2 > 0.0) || !std::isfinite(d->sigma2)))
+        return LMMSE_ERR_INVALID_ARG;
+    if (d->K > kMaxK) return LMMSE_ERR_UNSUPPORTED;
+    if (d->N % d->B != 0 || d->Wn < d->B || d->Wn > d->N || ((d->Wn - d->B) & 1))
+        return LMMSE_ERR_UNSUPPORTED;
+    if (d->Wn > kMaxWindow) return LMMSE_ERR_UNSUPPORTED;
+    const long long cols = (long long)d->max_slots * d->M * d->K;
+    if (cols * d->N >= (1LL << 40)) return LMMSE_ERR_UNSUPPORTED;
+    if (d->rsource == LMMSE_R_SAMPLE && d->Wn > 256) return LMMSE_ERR_UNSUPPORTED;
+    return LMMSE_OK;
+}
+
+void choose_row_tiles(int B, int& RT, int& rgroups) {
+    const int T = (2 * B + 15) / 16;
+    long long best_pad = -1;
+    for (int rt : kRTs) {
+        const int g = (T + rt - 1) / rt;
+        const long long padded = (long long)g * rt;
+        if (best_pad < 0 || padded < best_pad || (padded == best_pad && g < rgroups)) {
+            best_pad = padded;
+            RT = rt;
+            rgroups = g;
+        }
+    }
+}
+
+bool fixed_source(int rs) { return rs == LMMSE_R_UNIFORM || rs == LMMSE_R_EXPONENTIAL; }
+
+template <typename T>
+int dev_alloc(T*& p, size_t count) {
+    p = nullptr;
+    if (count == 0) return LMMSE_OK;
+    if (hipMalloc((void**)&p, count * sizeof(T)) != hipSuccess) {
+        p = nullptr;
+        return LMMSE_ERR_HIP;
+    }
+    return LMMSE_OK;
+}
+
+void free_plan(lmmse_plan* p) {
+    if (!p) return;
+    void* ptrs[] = {p->d_starts, p->d_classes, p->d_class_off, p->w64, p->fmat, p->chol, p->rd,
+                    p->wf32,     p->whi,       p->wlo,         p->twiddle, p->status, p->dscal};
+    for (void* q : ptrs)
+        if (q) (void)hipFree(q);
+    delete p;
+}
+
+int check_device() {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n < 1) return LMMSE_ERR_NO_DEVICE;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return LMMSE_ERR_NO_DEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return LMMSE_ERR_NO_DEVICE;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return LMMSE_ERR_NO_DEVICE;
+    return LMMSE_OK;
+}
+
+size_t hls_bytes(const lmmse_plan_desc& d, int slots) {
+    return (size_t)slots * d.M * d.K * d.N * sizeof(float2);
+}
+
+}  // namespace
+
+namespace lmmse {
+
+size_t fixed_bank_f32_elems(const Plan& p) { return (size_t)p.n_classes * p.G8 * p.Rpad * 4; }
+size_t split_bank_elems(const Plan& p) { return (size_t)p.n_classes * p.G16 * p.Rpad * 32; }
+
+}  // namespace lmmse
+
+extern "C" {
+
+const char* lmmse_status_string(int s) {
+    switch (s) {
+        case LMMSE_OK: return "ok";
+        case LMMSE_ERR_INVALID_ARG: return "invalid argument";
+        case LMMSE_ERR_UNSUPPORTED: return "unsupported plan shape";
+        case LMMSE_ERR_WORKSPACE: return "workspace missing or too small";
+        case LMMSE_ERR_HIP: return "HIP runtime error";
+        case LMMSE_ERR_NOT_PD: return "matrix not positive definite";
+        case LMMSE_ERR_NOT_READY: return "filters not designed or set";
+        case LMMSE_ERR_NO_DEVICE: return "no gfx950 device";
+        default: return "unknown status";
+    }
+}
+
+int lmmse_version(void) { return 10000; }
+
+int lmmse_plan_validate(const lmmse_plan_desc* desc) { return validate(desc); }
+
+int lmmse_block_plan(int N, int B, int Wn, int* starts, int* offsets, int* classes, int* n_classes) {
+    std::vector<int> s, o, c, co;
+    const int rc = block_plan_impl(N, B, Wn, s, o, c, co);
+    if (rc != LMMSE_OK) return rc;
+    for (size_t b = 0; b < s.size(); ++b) {
+        if (starts) starts[b] = s[b];
+        if (offsets) offsets[b] = o[b];
+        if (classes) classes[b] = c[b];
+    }
+    if (n_classes) *n_classes = (int)co.size();
+    return LMMSE_OK;
+}
+
+int lmmse_workspace_size(const lmmse_plan_desc* desc, int slots, size_t* bytes) {
+    const int v = validate(desc);
+    if (v != LMMSE_OK) return v;
+    if (!bytes || slots < 0 || slots > desc->max_slots) return LMMSE_ERR_INVALID_ARG;
+    size_t need = 0;
+    Plan tmp;
+    tmp.d = *desc;
+    if (desc->rsource == LMMSE_R_SAMPLE) {
+        need = sample_workspace_bytes(*desc, slots);
+    } else if (!apply_fusable(tmp)) {
+        need = hls_bytes(*desc, slots);
+    }
+    need = std::max(need, backward_workspace_bytes(*desc, slots));
+    *bytes = need;
+    return LMMSE_OK;
+}
+
+int lmmse_plan_create(const lmmse_plan_desc* desc, lmmse_plan_t* out) {
+    if (!out) return LMMSE_ERR_INVALID_ARG;
+    const int v = validate(desc);
+    if (v != LMMSE_OK) return v;
+    const int dv = check_device();
+    if (dv != LMMSE_OK) return dv;
+
+    lmmse_plan* p = new (std::nothrow) lmmse_plan();
+    if (!p) return LMMSE_ERR_HIP;
+    p->d = *desc;
+    (void)hipGetDevice(&p->device);
+    std::vector<int> offs;
+    block_plan_impl(desc->N, desc->B, desc->Wn, p->h_starts, p->h_offsets, p->h_classes,
+                    p->h_class_off);
+    p->nb = desc->N / desc->B;
+    p->halo = (desc->Wn - desc->B) / 2;
+    p->n_classes = (int)p->h_class_off.size();
+    choose_row_tiles(desc->B, p->RT, p->rgroups);
+    p->Rpad = p->RT * 16 * p->rgroups;
+    p->G8 = (desc->Wn + 7) / 8;
+    p->G16 = (desc->Wn + 15) / 16;
+    p->lo_scale = desc->precision == LMMSE_FP16X3 ? 2048.0f : 1.0f;
+    p->design_tau = desc->tau_rms;
+    p->design_sigma2 = desc->sigma2;
+
+    const int Wn = desc->Wn, K = desc->K;
+    const bool has_bank = desc->rsource != LMMSE_R_SAMPLE;
+    int rc = LMMSE_OK;
+    auto fail = [&](int code) {
+        free_plan(p);
+        return code;
+    };
+    if ((rc = dev_alloc(p->d_starts, p->nb)) || (rc = dev_alloc(p->d_classes, p->nb)) ||
+        (rc = dev_alloc(p->d_class_off, p->n_classes)) || (rc = dev_alloc(p->twiddle, K)) ||
+        (rc = dev_alloc(p->status, 2)) || (rc = dev_alloc(p->dscal, 4)) ||
+        (rc = dev_alloc(p->rd, 2 * (size_t)Wn)))
+        return fail(rc);
+    if (has_bank) {
+        if ((rc = dev_alloc(p->w64, (size_t)p->n_classes * desc->B * Wn)) ||
+            (rc = dev_alloc(p->fmat, (size_t)Wn * Wn)) || (rc = dev_alloc(p->chol, (size_t)Wn * Wn)) ||
+            (rc = dev_alloc(p->wf32, fixed_bank_f32_elems(*p))))
+            return fail(rc);
+        if (desc->precision != LMMSE_FP32 &&
+            ((rc = dev_alloc(p->whi, split_bank_elems(*p))) ||
+             (rc = dev_alloc(p->wlo, split_bank_elems(*p)))))
+            return fail(rc);
+    }
+    std::vector<float2> tw(K);
+    for (int r = 0; r < K; ++r) {
+        const double a = 2.0 * M_PI * r / K;
+        tw[r] = make_float2((float)std::cos(a), (float)std::sin(a));
+    }
+    int zero[2] = {0, 0};
+    if (hipMemcpy(p->d_starts, p->h_starts.data(), p->nb * sizeof(int), hipMemcpyHostToDevice) ||
+        hipMemcpy(p->d_classes, p->h_classes.data(), p->nb * sizeof(int), hipMemcpyHostToDevice) ||
+        hipMemcpy(p->d_class_off, p->h_class_off.data(), p->n_classes * sizeof(int),
+                  hipMemcpyHostToDevice) ||
+        hipMemcpy(p->twiddle, tw.data(), K * sizeof(float2), hipMemcpyHostToDevice) ||
+        hipMemcpy(p->status, zero, sizeof(zero), hipMemcpyHostToDevice))
+        return fail(LMMSE_ERR_HIP);
+    if (has_bank) {
+        const size_t bytes = fixed_bank_f32_elems(*p) * sizeof(float4);
+        if (hipMemset(p->wf32, 0, bytes) != hipSuccess) return fail(LMMSE_ERR_HIP);
+    }
+    if (fixed_source(desc->rsource)) {
+        if (launch_fixed_design(*p, desc->tau_rms, desc->sigma2, 0) != hipSuccess ||
+            hipDeviceSynchronize() != hipSuccess)
+            return fail(LMMSE_ERR_HIP);
+        int st[2];
+        if (hipMemcpy(st, p->status, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(LMMSE_ERR_HIP);
+        if (st[0] != 0) return fail(st[0]);
+        p->ready = true;
+    }
+    *out = p;
+    return LMMSE_OK;
+}
+
+int lmmse_plan_destroy(lmmse_plan_t plan) {
+    if (!plan) return LMMSE_ERR_INVALID_ARG;
+    (void)hipDeviceSynchronize();
+    free_plan(plan);
+    return LMMSE_OK;
+}
+
+int lmmse_plan_get_desc(lmmse_plan_t plan, lmmse_plan_desc* out) {
+    if (!plan || !out) return LMMSE_ERR_INVALID_ARG;
+    *out = plan->d;
+    out->tau_rms = plan->design_tau;
+    out->sigma2 = plan->design_sigma2;
+    return LMMSE_OK;
+}
+
+int lmmse_set_design(lmmse_plan_t plan, double tau_rms, double sigma2, void* stream) {
+    if (!plan) return LMMSE_ERR_INVALID_ARG;
+    if (!fixed_source(plan->d.rsource)) return LMMSE_ERR_UNSUPPORTED;
+    if (!(sigma2 > 0.0) || !std::isfinite(sigma2)) return LMMSE_ERR_INVALID_ARG;
+    if (plan->d.rsource == LMMSE_R_EXPONENTIAL && (!(tau_rms > 0.0) || !std::isfinite(tau_rms)))
+        return LMMSE_ERR_INVALID_ARG;
+    const double tau = plan->d.rsource == LMMSE_R_EXPONENTIAL ? tau_rms : plan->design_tau;
+    LMMSE_HIP_TRY(launch_fixed_design(*plan, tau, sigma2, (hipStream_t)stream));
+    plan->design_tau = tau;
+    plan->design_sigma2 = sigma2;
+    plan->ready = true;
+    return LMMSE_OK;
+}
+
+int lmmse_set_filters(lmmse_plan_t plan, const void* w, void* stream) {
+    if (!plan || !w) return LMMSE_ERR_INVALID_ARG;
+    if (plan->d.rsource != LMMSE_R_USER) return LMMSE_ERR_UNSUPPORTED;
+    const size_t bytes = (size_t)plan->n_classes * plan->d.B * plan->d.Wn * sizeof(double2);
+    LMMSE_HIP_TRY(hipMemcpyAsync(plan->w64, w, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    LMMSE_HIP_TRY(launch_pack_banks(*plan, (hipStream_t)stream));
+    plan->ready = true;
+    return LMMSE_OK;
+}
+
+int lmmse_get_filters(lmmse_plan_t plan, void* w_out, void* stream) {
+    if (!plan || !w_out) return LMMSE_ERR_INVALID_ARG;
+    if (plan->d.rsource == LMMSE_R_SAMPLE) return LMMSE_ERR_UNSUPPORTED;
+    if (!plan->ready) return LMMSE_ERR_NOT_READY;
+    const size_t bytes = (size_t)plan->n_classes * plan->d.B * plan->d.Wn * sizeof(double2);
+    LMMSE_HIP_TRY(hipMemcpyAsync(w_out, plan->w64, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return LMMSE_OK;
+}
+
+int lmmse_despread(lmmse_plan_t plan, int slots, const void* y, const void* pilots, void* h_ls,
+                   void* stream) {
+    if (!plan || !y || !pilots || !h_ls) return LMMSE_ERR_INVALID_ARG;
+    if (slots < 0 || slots > plan->d.max_slots) return LMMSE_ERR_INVALID_ARG;
+    LMMSE_HIP_TRY(launch_despread(*plan, slots, (const float2*)y, (const float2*)pilots,
+                                  (float2*)h_ls, (hipStream_t)stream));
+    return LMMSE_OK;
+}
+
+static int apply_dispatch(lmmse_plan_t plan, int slots, const float2* x, const float2* pilots,
+                          bool fused, float2* out, hipStream_t st) {
+    if (plan->d.precision == LMMSE_FP32)
+        LMMSE_HIP_TRY(launch_apply_f32(*plan, slots, x, pilots, fused, out, st));
+    else
+        LMMSE_HIP_TRY(launch_apply_split(*plan, slots, x, pilots, fused, out, st));
+    return LMMSE_OK;
+}
+
+int lmmse_apply(lmmse_plan_t plan, int slots, const void* h_ls, void* h_hat, void* stream) {
+    if (!plan || !h_ls || !h_hat) return LMMSE_ERR_INVALID_ARG;
+    if (slots < 0 || slots > plan->d.max_slots) return LMMSE_ERR_INVALID_ARG;
+    if (plan->d.rsource == LMMSE_R_SAMPLE) return LMMSE_ERR_UNSUPPORTED;
+    if (!plan->ready) return LMMSE_ERR_NOT_READY;
+    return apply_dispatch(plan, slots, (const float2*)h_ls, nullptr, false, (float2*)h_hat,
+                          (hipStream_t)stream);
+}
+
+int lmmse_covariance(lmmse_plan_t plan, int slots, const void* h_ls, void* r_win, void* stream) {
+    if (!plan || !h_ls || !r_win) return LMMSE_ERR_INVALID_ARG;
+    if (slots < 0 || slots > plan->d.max_slots) return LMMSE_ERR_INVALID_ARG;
+    if (plan->d.Wn > 256) return LMMSE_ERR_UNSUPPORTED;
+    LMMSE_HIP_TRY(launch_covariance(*plan, slots, (const float2*)h_ls, (double2*)r_win,
+                                    (hipStream_t)stream));
+    return LMMSE_OK;
+}
+
+int lmmse_sample_filters(lmmse_plan_t plan, int slots, const void* r_win, double sigma2,
+                         void* w_out, void* stream) {
+    if (!plan || !r_win || !w_out) return LMMSE_ERR_INVALID_ARG;
+    if (slots < 0 || slots > plan->d.max_slots) return LMMSE_ERR_INVALID_ARG;
+    if (!(sigma2 >= 0.0) || !std::isfinite(sigma2)) return LMMSE_ERR_INVALID_ARG;
+    if (plan->d.Wn > 256) return LMMSE_ERR_UNSUPPORTED;
+    const int nmat = slots * plan->d.K * plan->nb;
+    LMMSE_HIP_TRY(launch_batched_filters(*plan, nmat, nullptr, nullptr, (const double2*)r_win,
+                                         sigma2 / plan->d.K, (double2*)w_out, (hipStream_t)stream));
+    return LMMSE_OK;
+}
+
+int lmmse_estimate(lmmse_plan_t plan, int slots, const void* y, const void* pilots, double sigma2,
+                   void* h_hat, void* ws, size_t ws_bytes, void* stream) {
+    if (!plan || !y || !pilots || !h_hat) return LMMSE_ERR_INVALID_ARG;
+    if (slots < 0 || slots > plan->d.max_slots) return LMMSE_ERR_INVALID_ARG;
+    if (!(sigma2 > 0.0) || !std::isfinite(sigma2)) return LMMSE_ERR_INVALID_ARG;
+    size_t need = 0;
+    lmmse_workspace_size(&plan->d, slots, &need);
+    const hipStream_t st = (hipStream_t)stream;
+    if (plan->d.rsource == LMMSE_R_SAMPLE) {
+        if (need && (!ws || ws_bytes < sample_workspace_bytes(plan->d, slots)))
+            return LMMSE_ERR_WORKSPACE;
+        plan->design_sigma2 = sigma2;   // the backward of this estimate uses it
+        float2* hls = (float2*)ws;
+        LMMSE_HIP_TRY(launch_despread(*plan, slots, (const float2*)y, (const float2*)pilots, hls, st));
+        LMMSE_HIP_TRY(launch_sample_estimate(*plan, slots, hls, sigma2 / plan->d.K, (float2*)h_hat,
+                                             (char*)ws + hls_bytes(plan->d, slots), st));
+        return LMMSE_OK;
+    }
+    if (fixed_source(plan->d.rsource) && sigma2 != plan->design_sigma2) {
+        const int rc = lmmse_set_design(plan, plan->design_tau, sigma2, stream);
+        if (rc != LMMSE_OK) return rc;
+    }
+    if (!plan->ready) return LMMSE_ERR_NOT_READY;
+    if (apply_fusable(*plan))
+        return apply_dispatch(plan, slots, (const float2*)y, (const float2*)pilots, true,
+                              (float2*)h_hat, st);
+    if (!ws || ws_bytes < hls_bytes(plan->d, slots)) return LMMSE_ERR_WORKSPACE;
+    LMMSE_HIP_TRY(launch_despread(*plan, slots, (const float2*)y, (const float2*)pilots, (float2*)ws, st));
+    return apply_dispatch(plan, slots, (const float2*)ws, nullptr, false, (float2*)h_hat, st);
+}
+
+int lmmse_backward(lmmse_plan_t plan, int slots, const void* h_ls, const void* g, void* d_hls,
+                   double* d_tau, double* d_sigma2, void* ws, size_t ws_bytes, void* stream) {
+    if (!plan || !h_ls || !g || !d_hls) return LMMSE_ERR_INVALID_ARG;
+    if (slots < 0 || slots > plan->d.max_slots) return LMMSE_ERR_INVALID_ARG;
+    const size_t need = backward_workspace_bytes(plan->d, slots);
+    if (need && (!ws || ws_bytes < need)) return LMMSE_ERR_WORKSPACE;
+    const hipStream_t st = (hipStream_t)stream;
+    const bool want = d_tau || d_sigma2;
+    double h[4] = {NAN, NAN, NAN, NAN};
+    if (plan->d.rsource == LMMSE_R_SAMPLE) {
+        LMMSE_HIP_TRY(launch_backward_sample(*plan, slots, (const float2*)h_ls, (const float2*)g,
+                                             (float2*)d_hls, plan->design_sigma2 / plan->d.K, want,
+                                             ws, st));
+    } else {
+        if (!plan->ready) return LMMSE_ERR_NOT_READY;
+        LMMSE_HIP_TRY(launch_backward_fixed(*plan, slots, (const float2*)h_ls, (const float2*)g,
+                                            (float2*)d_hls, want && plan->d.rsource != LMMSE_R_USER,
+                                            ws, st));
+    }
+    if (want) {
+        LMMSE_HIP_TRY(hipStreamSynchronize(st));
+        if (plan->d.rsource != LMMSE_R_USER)
+            LMMSE_HIP_TRY(hipMemcpy(h, plan->dscal, 2 * sizeof(double), hipMemcpyDeviceToHost));
+        if (d_tau) *d_tau = plan->d.rsource == LMMSE_R_EXPONENTIAL ? h[0] : NAN;
+        if (d_sigma2) *d_sigma2 = plan->d.rsource == LMMSE_R_USER ? NAN : h[1] / plan->d.K;
+    }
+    return LMMSE_OK;
+}
+
+int lmmse_sync_status(lmmse_plan_t plan, void* stream, int* info) {
+    if (!plan) return LMMSE_ERR_INVALID_ARG;
+    LMMSE_HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    int st[2] = {0, -1};
+    LMMSE_HIP_TRY(hipMemcpy(st, plan->status, sizeof(st), hipMemcpyDeviceToHost));
+    if (info) *info = st[0] ? st[1] : -1;
+    if (st[0]) {
+        int zero[2] = {0, 0};
+        LMMSE_HIP_TRY(hipMemcpy(plan->status, zero, sizeof(zero), hipMemcpyHostToDevice));
+    }
+    return st[0];
+}
+
+}  // extern "C"
