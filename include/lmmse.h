@@ -48,6 +48,8 @@
  * (LMMSE_FP32), or as split products hi*hi + hi*lo + lo*hi with FP32
  * accumulation in BF16 (LMMSE_BF16X3) or FP16 (LMMSE_FP16X3).
  *
+ * Calls with slots == 0 launch nothing and accept NULL data pointers.
+ *
  * Errors: every call returns an lmmse_status.  No exception crosses the ABI.
  * Device-side conditions (a non-positive pivot in a factorisation) are
  * recorded in a plan-owned status word, read by lmmse_sync_status.

@@ -8,19 +8,23 @@
 // contraction order: within a group of 16 reals (8 complex window rows), lane
 // (i16, q) holds reals 4q..4q+3 of its row / column in one float4 and feeds
 // element i of it to k-step i, for both operands.  The product is unchanged
-// (the contraction order is only permuted), and every operand load is a
-// 16-byte vector load.
+// (only the contraction order is permuted) and every operand read is a
+// 16-byte LDS read.
 //
-// One wave (64 lanes) = one workgroup computes, for one block b and one row
-// group, RT 16-row tiles x CT 16-column tiles.  Filters ("A") are read from
-// the pre-laid-out bank in L2; H_LS columns ("B") come straight from HBM
-// (unfused) or from LDS after an in-register despread of the pilot symbols
-// (fused: the wave first reads y[s, m, 0..K-1, window chunk] for the antennas
-// of its 16*CT columns, undoes the cover code with a K-point DFT, multiplies
-// by conj(x_k[n]) / K and stages the LS values in LDS).  The block index runs
-// fastest over consecutive tiles and tiles are remapped so that each XCD
-// processes a contiguous range: neighbouring (overlapping) windows of a column
-// tile are read by the same L2.
+// A workgroup computes one block b, one row group (RT 16-row tiles) and 192
+// columns.  Its waves are specialised: 4 MFMA waves (wave w owns columns
+// [48w, 48w+48), 3 column tiles) and 4 loader waves (6 MFMA waves of 2
+// tiles and 2 loader waves for RT > 13).  The window is streamed
+// in chunks of 16 complex rows through two LDS buffers: while the MFMA waves
+// run RT x 3 x 8 MFMAs on chunk c, the loader waves copy the filter rows of
+// chunk c+1 (shared by all MFMA waves) and produce its LS values in the other
+// buffer; one barrier per chunk hands the buffers over.  LS values come from
+// H_LS (unfused) or are made on the fly from the pilot symbols (fused: one
+// thread per (antenna, subcarrier) reads y[s,m,0..K-1,n], undoes the cover
+// code with a K-point DFT and multiplies by conj(x_k[n]) / K).  The block index
+// runs fastest over consecutive tiles and tiles are remapped so that each XCD
+// takes a contiguous range: the overlapping windows of neighbouring blocks of
+// a column group are read through the same L2.
 #include "dft.h"
 #include "internal.h"
 
@@ -53,26 +57,166 @@ __device__ __forceinline__ float f4c(const float4& v, int i) {
     return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
 }
 
-template <int RT, int CT>
-__device__ __forceinline__ void mfma_group(floatx4 (&acc)[RT][CT], const float4 (&av)[RT],
-                                           const float4 (&xv)[CT]) {
+constexpr int kCols = 192;             // columns per workgroup (= MFMA waves x CT x 16)
+constexpr int kXS = 18;                // LDS column stride in complex (16 rows + pad)
+constexpr int kXBuf = kCols * kXS / 2; // float4 per LS buffer
+
+// Registers one loader thread holds for one chunk (window rows [16cc, 16cc+16)):
+// its share of the chunk's filter rows and of the raw inputs.
+template <int RT, int KF, int NL>
+struct ChunkRegs {
+    static constexpr int TW = (2 * RT * 64 + NL - 1) / NL;
+    static constexpr int NPAIR = KF == 0 ? kCols * 16 : (kCols / KF) * 16;
+    static constexpr int TX = (NPAIR + NL - 1) / NL;
+    static constexpr int KV = KF == 0 ? 1 : KF;
+    float4 w[TW];
+    float2 v[TX][KV];
+};
+
+// Issue the global loads of chunk cc (no LDS traffic, no waits).
+template <int RT, int KF, int NL>
+__device__ __forceinline__ void load_chunk(const ApplyArgs& a, int lt, int cc, int s0, long long c0,
+                                           const float4* wsrc, ChunkRegs<RT, KF, NL>& R) {
+    using CR = ChunkRegs<RT, KF, NL>;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int u = 0; u < CR::TW; ++u) {
+        const int i = lt + u * NL;
+        const int gg = i / (RT * 64), rem = i - gg * (RT * 64);
+        const int g = 2 * cc + gg;
+        R.w[u] = (i < 2 * RT * 64 && g < a.G8) ? wsrc[(size_t)g * a.Rpad * 4 + rem]
+                                                 : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
+    for (int u = 0; u < CR::TX; ++u) {
+        const int i = lt + u * NL;
+        const int cq = i >> 4, r = i & 15;
+        const int j = cc * 16 + r;
+        if constexpr (KF == 0) {
+            const long long col = c0 + cq;
+            R.v[u][0] = (i < CR::NPAIR && j < a.Wn && col < a.ncols) ? a.x[col * a.N + s0 + j]
+                                                                    : make_float2(0.f, 0.f);
+        } else {
+            const long long ant = c0 / KF + cq;
+            const bool live = i < CR::NPAIR && j < a.Wn && ant < a.ncols / KF;
+            const float2* yp = a.x + ant * KF * (long long)a.N + s0 + j;
 #pragma unroll
-            for (int ct = 0; ct < CT; ++ct)
-                acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(f4c(av[rt], i), f4c(xv[ct], i),
-                                                                   acc[rt][ct], 0, 0, 0);
+            for (int tt = 0; tt < KF; ++tt)
+                R.v[u][tt] = live ? yp[(long long)tt * a.N] : make_float2(0.f, 0.f);
+        }
+    }
 }
 
-template <int RT, int CT>
-__device__ __forceinline__ void store_tiles(const ApplyArgs& a, const floatx4 (&acc)[RT][CT],
-                                            long long c0, int b, int rg, int l16, int q) {
+// Turn the loaded registers of chunk cc into LDS operands: filter rows as
+// they are, LS values straight (unfused) or after despreading (fused).
+template <int RT, int KF, int NL>
+__device__ __forceinline__ void store_chunk(const ApplyArgs& a, int lt, int cc, int s0,
+                                            const ChunkRegs<RT, KF, NL>& R, float4* ws4, float4* xs4) {
+    using CR = ChunkRegs<RT, KF, NL>;
+    float2* xs2 = reinterpret_cast<float2*>(xs4);
+#pragma unroll
+    for (int u = 0; u < CR::TW; ++u) {
+        const int i = lt + u * NL;
+        if (i < 2 * RT * 64) ws4[i] = R.w[u];
+    }
+#pragma unroll
+    for (int u = 0; u < CR::TX; ++u) {
+        const int i = lt + u * NL;
+        if (i >= CR::NPAIR) continue;
+        const int cq = i >> 4, r = i & 15;
+        if constexpr (KF == 0) {
+            xs2[cq * kXS + r] = R.v[u][0];
+        } else {
+            const int j = cc * 16 + r;
+            float2* dst = xs2 + cq * KF * kXS + r;
+            float2 z[KF];
+            Dft<KF>::run(R.v[u], z, nullptr);
+            const bool live = j < a.Wn;
+            const int n = live ? s0 + j : 0;
+#pragma unroll
+            for (int k = 0; k < KF; ++k) {
+                const float2 h = cmulc(z[k], a.pilots[(long long)k * a.N + n]);
+                dst[k * kXS] = live ? make_float2(h.x * a.invK, h.y * a.invK) : make_float2(0.f, 0.f);
+            }
+        }
+    }
+}
+
+// RT row tiles x CT column tiles per MFMA wave, MW MFMA waves (CT * MW = 12),
+// 8 - MW loader waves.  Loader and MFMA waves run separate loops (the branch
+// is uniform per wave) that pass the same number of barriers, so their
+// registers do not overlap.  A loader thread issues all global loads of its
+// share of a chunk before it stores any of it.
+template <int RT, int CT, int MW, int KF>
+__global__ __launch_bounds__(512) void apply_f32_kernel(ApplyArgs a) {
+    constexpr int NL = 64 * (8 - MW);
+    static_assert(16 * CT * MW == kCols, "workgroup column count");
+    __shared__ float4 xs4[2 * kXBuf];          // LS chunks: [buf][col][16 rows]
+    __shared__ float4 ws4[2 * 2 * RT * 64];    // filter chunks: [buf][g][row][q]
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l16 = lane & 15, q = lane >> 4;
+    long long t = xcd_remap(blockIdx.x, a.n_tiles);
+    const int rg = (int)(t % a.rgroups);
+    t /= a.rgroups;
+    const int b = (int)(t % a.nb);
+    const long long c0 = (t / a.nb) * kCols;
+    const int s0 = a.starts[b], cls = a.classes[b];
+    const float4* wsrc = a.wbank + ((size_t)cls * a.G8 * a.Rpad + (size_t)rg * RT * 16) * 4;
+    const int nchunks = (a.Wn + 15) >> 4;
+
+    if (wave >= MW) {
+        const int lt = tid - 64 * MW;
+        ChunkRegs<RT, KF, NL> cr;
+        load_chunk<RT, KF, NL>(a, lt, 0, s0, c0, wsrc, cr);
+        store_chunk<RT, KF, NL>(a, lt, 0, s0, cr, ws4, xs4);
+        __syncthreads();
+        for (int cc = 0; cc < nchunks; ++cc) {
+            const int nb2 = (cc + 1) & 1;
+            if (cc + 1 < nchunks) {
+                load_chunk<RT, KF, NL>(a, lt, cc + 1, s0, c0, wsrc, cr);
+                store_chunk<RT, KF, NL>(a, lt, cc + 1, s0, cr, ws4 + nb2 * 2 * RT * 64,
+                                        xs4 + nb2 * kXBuf);
+            }
+            __syncthreads();
+        }
+        return;
+    }
+
+    floatx4 acc[RT][CT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+    __syncthreads();
+    for (int cc = 0; cc < nchunks; ++cc) {
+        const int buf = cc & 1;
+        const float4* wb = ws4 + buf * 2 * RT * 64;
+        const float4* xb = xs4 + buf * kXBuf;
+#pragma unroll
+        for (int gg = 0; gg < 2; ++gg) {
+            float4 av[RT], xv[CT];
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) av[rt] = wb[gg * RT * 64 + (rt * 16 + l16) * 4 + q];
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+                xv[ct] = xb[((wave * CT + ct) * 16 + l16) * (kXS / 2) + 4 * gg + q];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                    for (int ct = 0; ct < CT; ++ct)
+                        acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                            f4c(av[rt], i), f4c(xv[ct], i), acc[rt][ct], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+
+    // lane (l16, q) of tile (rt, ct) holds real rows 16rt + 4q .. +3 of its
+    // column: complex outputs o, o+1 of the block
     const bool vec = a.vec_store != 0;
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
-        const long long col = c0 + ct * 16 + l16;
+        const long long col = c0 + (wave * CT + ct) * 16 + l16;
         if (col >= a.ncols) continue;
         float2* op = a.out + col * a.N + (long long)b * a.B;
 #pragma unroll
@@ -92,119 +236,6 @@ __device__ __forceinline__ void store_tiles(const ApplyArgs& a, const floatx4 (&
         }
     }
 }
-
-template <int RT, int CT>
-__global__ __launch_bounds__(64) void apply_f32_kernel(ApplyArgs a) {
-    const int lane = threadIdx.x, l16 = lane & 15, q = lane >> 4;
-    long long t = xcd_remap(blockIdx.x, a.n_tiles);
-    const int rg = (int)(t % a.rgroups);
-    t /= a.rgroups;
-    const int b = (int)(t % a.nb);
-    const long long c0 = (t / a.nb) * (16 * CT);
-    const int s0 = a.starts[b], cls = a.classes[b];
-
-    floatx4 acc[RT][CT];
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-        for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
-
-    const float4* wp = a.wbank + ((size_t)cls * a.G8 * a.Rpad + (size_t)rg * RT * 16 + l16) * 4 + q;
-    const float2* xp[CT];
-    bool cv[CT];
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct) {
-        const long long col = c0 + ct * 16 + l16;
-        cv[ct] = col < a.ncols;
-        xp[ct] = a.x + (cv[ct] ? col : 0) * a.N + s0;
-    }
-    for (int g = 0; g < a.G8; ++g) {
-        float4 av[RT];
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt) av[rt] = wp[((size_t)g * a.Rpad + rt * 16) * 4];
-        float4 xv[CT];
-        const int j = 8 * g + 2 * q;
-#pragma unroll
-        for (int ct = 0; ct < CT; ++ct) {
-            float2 u0 = make_float2(0.f, 0.f), u1 = make_float2(0.f, 0.f);
-            if (cv[ct] && j < a.Wn) u0 = xp[ct][j];
-            if (cv[ct] && j + 1 < a.Wn) u1 = xp[ct][j + 1];
-            xv[ct] = make_float4(u0.x, u0.y, u1.x, u1.y);
-        }
-        mfma_group<RT, CT>(acc, av, xv);
-    }
-    store_tiles<RT, CT>(a, acc, c0, b, rg, l16, q);
-}
-
-template <int RT, int CT, int KF>
-__global__ __launch_bounds__(64) void apply_f32_fused_kernel(ApplyArgs a) {
-    static_assert((16 * CT) % KF == 0, "tile must hold whole antennas");
-    constexpr int NA = 16 * CT / KF;   // antennas per tile
-    constexpr int XS = 18;             // LDS column stride in complex (16 rows + pad)
-    __shared__ float4 xs4[16 * CT * XS / 2];
-    float2* xs2 = reinterpret_cast<float2*>(xs4);
-
-    const int lane = threadIdx.x, l16 = lane & 15, q = lane >> 4;
-    long long t = xcd_remap(blockIdx.x, a.n_tiles);
-    const int rg = (int)(t % a.rgroups);
-    t /= a.rgroups;
-    const int b = (int)(t % a.nb);
-    const long long c0 = (t / a.nb) * (16 * CT);
-    const int s0 = a.starts[b], cls = a.classes[b];
-    const long long ant0 = c0 / KF, n_ant = a.ncols / KF;
-
-    floatx4 acc[RT][CT];
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-        for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
-
-    const float4* wp = a.wbank + ((size_t)cls * a.G8 * a.Rpad + (size_t)rg * RT * 16 + l16) * 4 + q;
-    const int nchunks = (a.Wn + 15) >> 4;
-    for (int cc = 0; cc < nchunks; ++cc) {
-        // despread 16 window rows of every antenna of the tile into LDS
-        for (int pi = lane; pi < NA * 16; pi += 64) {
-            const int aa = pi >> 4, r = pi & 15;
-            const int j = cc * 16 + r;
-            const long long ant = ant0 + aa;
-            float2* dst = xs2 + aa * KF * XS + r;
-            if (j < a.Wn && ant < n_ant) {
-                const int n = s0 + j;
-                const float2* yp = a.x + ant * KF * (long long)a.N + n;
-                float2 v[KF], z[KF];
-#pragma unroll
-                for (int tt = 0; tt < KF; ++tt) v[tt] = yp[(long long)tt * a.N];
-                Dft<KF>::run(v, z, nullptr);
-#pragma unroll
-                for (int k = 0; k < KF; ++k) {
-                    const float2 h = cmulc(z[k], a.pilots[(long long)k * a.N + n]);
-                    dst[k * XS] = make_float2(h.x * a.invK, h.y * a.invK);
-                }
-            } else {
-#pragma unroll
-                for (int k = 0; k < KF; ++k) dst[k * XS] = make_float2(0.f, 0.f);
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int gg = 0; gg < 2; ++gg) {
-            const int g = 2 * cc + gg;
-            if (g < a.G8) {
-                float4 av[RT];
-#pragma unroll
-                for (int rt = 0; rt < RT; ++rt) av[rt] = wp[((size_t)g * a.Rpad + rt * 16) * 4];
-                float4 xv[CT];
-#pragma unroll
-                for (int ct = 0; ct < CT; ++ct) xv[ct] = xs4[(ct * 16 + l16) * (XS / 2) + 4 * gg + q];
-                mfma_group<RT, CT>(acc, av, xv);
-            }
-        }
-        __syncthreads();
-    }
-    store_tiles<RT, CT>(a, acc, c0, b, rg, l16, q);
-}
-
-static constexpr int kCT = 3;
 
 bool apply_fusable(const Plan& p) {
     const int K = p.d.K;
@@ -230,43 +261,34 @@ hipError_t launch_apply_f32(const Plan& p, int slots, const float2* x, const flo
     a.rgroups = p.rgroups;
     a.invK = 1.0f / (float)p.d.K;
     a.vec_store = (((a.N | a.B) & 1) == 0 && ((uintptr_t)out & 15) == 0) ? 1 : 0;
-    const long long ctiles = (a.ncols + 16 * kCT - 1) / (16 * kCT);
+    const long long ctiles = (a.ncols + kCols - 1) / kCols;
     a.n_tiles = ctiles * p.nb * p.rgroups;
     if (a.n_tiles == 0) return hipSuccess;
-    const dim3 grid((unsigned)a.n_tiles), block(64);
-    if (!fused) {
-        switch (p.RT) {
-#define LMMSE_AF(R)                                                                     \
-    case R:                                                                             \
-        hipLaunchKernelGGL((apply_f32_kernel<R, kCT>), grid, block, 0, st, a);           \
-        break;
-            LMMSE_AF(1) LMMSE_AF(2) LMMSE_AF(4) LMMSE_AF(8) LMMSE_AF(9) LMMSE_AF(13)
-            LMMSE_AF(15) LMMSE_AF(17)
-#undef LMMSE_AF
-            default:
-                return hipErrorInvalidValue;
-        }
-        return hipGetLastError();
-    }
-#define LMMSE_AFF(R, KK)                                                                \
-    case R:                                                                             \
-        hipLaunchKernelGGL((apply_f32_fused_kernel<R, kCT, KK>), grid, block, 0, st, a); \
+    const dim3 grid((unsigned)a.n_tiles);
+    const int kf = fused ? p.d.K : 0;
+    // tall row groups use 6 MFMA waves of 2 column tiles to stay in registers
+#define LMMSE_AF(R, KK)                                                                       \
+    case R:                                                                                   \
+        if constexpr (R <= 13)                                                                \
+            hipLaunchKernelGGL((apply_f32_kernel<R, 3, 4, KK>), grid, dim3(512), 0, st, a);  \
+        else                                                                                  \
+            hipLaunchKernelGGL((apply_f32_kernel<R, 2, 6, KK>), grid, dim3(512), 0, st, a);  \
         break;
 #define LMMSE_AFK(KK)                                                                    \
     case KK:                                                                             \
         switch (p.RT) {                                                                  \
-            LMMSE_AFF(1, KK) LMMSE_AFF(2, KK) LMMSE_AFF(4, KK) LMMSE_AFF(8, KK)          \
-            LMMSE_AFF(9, KK) LMMSE_AFF(13, KK) LMMSE_AFF(15, KK) LMMSE_AFF(17, KK)       \
+            LMMSE_AF(1, KK) LMMSE_AF(2, KK) LMMSE_AF(4, KK) LMMSE_AF(8, KK)              \
+            LMMSE_AF(9, KK) LMMSE_AF(13, KK) LMMSE_AF(15, KK) LMMSE_AF(17, KK)           \
             default: return hipErrorInvalidValue;                                        \
         }                                                                                \
         break;
-    switch (p.d.K) {
-        LMMSE_AFK(1) LMMSE_AFK(2) LMMSE_AFK(4) LMMSE_AFK(12) LMMSE_AFK(24)
+    switch (kf) {
+        LMMSE_AFK(0) LMMSE_AFK(1) LMMSE_AFK(2) LMMSE_AFK(4) LMMSE_AFK(12) LMMSE_AFK(24)
         default:
             return hipErrorInvalidValue;
     }
 #undef LMMSE_AFK
-#undef LMMSE_AFF
+#undef LMMSE_AF
     return hipGetLastError();
 }
 

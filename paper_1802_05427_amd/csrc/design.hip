@@ -2,11 +2,18 @@
 //
 // Fixed design: the window correlation R_II is the same Hermitian Toeplitz
 // matrix for every block (the correlation depends only on the subcarrier
-// difference, eq. 16), so one Cholesky factorisation A = R_II + lam I = L L^H
-// serves all blocks.  Solving A X = R_II gives X = A^-1 R_II, and the filter
-// of a block whose outputs sit at rows off..off+B-1 of its window is
-//     W = R_OI A^-1 = (A^-1 R_IO)^H,   W[i][j] = conj(X[j][off + i]).
-// Matrices are column-major (element (i, j) at i + j*n).
+// difference, eq. 16), and so is A = R_II + lam I.  Since R_II A^-1 =
+// (A - lam I) A^-1 = I - lam A^-1, the filter of a block whose outputs sit at
+// rows off..off+B-1 of its window is
+//     W = R_OI A^-1 = (I - lam A^-1)[off : off+B, :].
+// A^-1 of the Hermitian positive definite Toeplitz A is formed in O(n^2):
+// the Levinson-Durbin recursion gives its first column x, and the displacement
+// structure of the inverse of a Toeplitz matrix (Gohberg-Semencul) gives every
+// other entry along its diagonal:
+//     Ainv[i][j] = Ainv[i-1][j-1] + (x_i conj(x_j) - y_{i-1} conj(y_{j-1})) / x_0,
+//     y_k = conj(x_{n-1-k})  (the last column).
+// A^-1 is kept for the backward pass.  Matrices are column-major (element
+// (i, j) at i + j*n).
 #include "internal.h"
 
 namespace lmmse {
@@ -64,133 +71,96 @@ __global__ void rd_kernel(double2* rd, int n, int rsource, double L, double tau,
     rd[n + d] = dr;
 }
 
-// A = R_II + lam I and F = R_II (column-major, n x n) from r_d.
-__global__ void toeplitz_kernel(const double2* __restrict__ rd, double2* __restrict__ A,
-                                double2* __restrict__ F, int n, double lam) {
-    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (long long)n * n) return;
-    const int i = (int)(idx % n), j = (int)(idx / n);
-    const int dd = i - j;
-    const double2 r = dd >= 0 ? rd[dd] : zconj(rd[-dd]);
-    F[idx] = r;
-    A[idx] = i == j ? make_double2(r.x + lam, 0.0) : r;
-}
-
-// In-place lower Cholesky of one n x n Hermitian matrix per workgroup
-// (column-major, right-looking; the pivot column is cached in LDS).
-// On a non-positive or non-finite pivot the status word gets
-// LMMSE_ERR_NOT_PD and info = info_base + blockIdx.x (first failure wins).
-__global__ __launch_bounds__(1024) void chol_kernel(double2* A, long long strideA, int n,
-                                                    int* status, int info_base) {
-    extern __shared__ double2 col[];   // n entries
-    __shared__ double piv_s;
-    __shared__ int bad;
-    A += (long long)blockIdx.x * strideA;
-    const int tid = threadIdx.x, ti = tid & 31, tp = tid >> 5;
-    if (tid == 0) bad = 0;
-    for (int j = 0; j < n; ++j) {
-        __syncthreads();
-        if (tid == 0) {
-            const double dj = A[j + (long long)j * n].x;
-            if (!(dj > 0.0) || !isfinite(dj)) {
-                bad = 1;
-                if (atomicCAS(status, 0, LMMSE_ERR_NOT_PD) == 0) status[1] = info_base + blockIdx.x;
-            }
-            piv_s = sqrt(dj);
-            A[j + (long long)j * n] = make_double2(piv_s, 0.0);
-        }
-        __syncthreads();
-        if (bad) return;
-        const double inv = 1.0 / piv_s;
-        for (int i = j + 1 + tid; i < n; i += blockDim.x) {
-            double2 v = A[i + (long long)j * n];
-            v = make_double2(v.x * inv, v.y * inv);
-            A[i + (long long)j * n] = v;
-            col[i] = v;
-        }
-        __syncthreads();
-        for (int p = j + 1 + tp; p < n; p += 32) {
-            const double2 cp = col[p];
-            double2* Ap = A + (long long)p * n;
-            for (int i = p + ti; i < n; i += 32) {
-                const double2 u = zmulc(col[i], cp);
-                Ap[i] = zsub(Ap[i], u);
-            }
-        }
-    }
-}
-
-// Solve A X = Y in place for the columns of Y (column-major n x nrhs),
-// given the lower Cholesky factor of A.  Each workgroup handles NC columns
-// staged in LDS; 256 threads = NC columns x (256/NC) row lanes.
-__global__ __launch_bounds__(256) void chol_solve_kernel(const double2* __restrict__ Lf, double2* Y,
-                                                         int n, int nrhs, int NC) {
-    extern __shared__ double2 ys[];   // [NC][n]
+// Levinson-Durbin on A[i][j] = a_{i-j}, a_d = r_d + lam delta_d (a_{-d} =
+// conj(a_d)), then the Gohberg-Semencul fill of A^-1.  One wave; LDS holds
+// a_d and two copies of the predictor.  Predictor of order k: A_{k+1} [1; p]
+// = [P_k; 0], p^(k)_i = p^(k-1)_i + kap conj(p^(k-1)_{k-i}), p^(k)_k = kap,
+// kap = -(a_k + sum_{i<k} p_i a_{k-i}) / P_{k-1}, P_k = P_{k-1} (1 - |kap|^2).
+// A non-positive P (A not positive definite) sets LMMSE_ERR_NOT_PD.
+__global__ __launch_bounds__(64) void toeplitz_inverse_kernel(const double2* __restrict__ rd, int n,
+                                                              double lam, double2* __restrict__ ainv,
+                                                              int* status) {
+    extern __shared__ double2 sh[];
+    double2* av = sh;            // a_d
+    double2* p0 = sh + n;        // predictor buffers
+    double2* p1 = sh + 2 * n;
     const int tid = threadIdx.x;
-    const int R = 256 / NC;
-    const int c = tid / R, rl = tid % R;
-    const int col = blockIdx.x * NC + c;
-    const bool live = col < nrhs;
-    double2* yl = ys + (long long)c * n;
-    if (live)
-        for (int i = rl; i < n; i += R) yl[i] = Y[i + (long long)col * n];
-    // forward: L z = y.  Row i is divided by L[i][i] right after its last
-    // update (at step i-1), so step j only reads the finished z_j.
-    __syncthreads();
-    if (live && rl == 0) {
-        const double d = Lf[0].x;
-        yl[0] = make_double2(yl[0].x / d, yl[0].y / d);
+    for (int d = tid; d < n; d += 64) {
+        const double2 r = rd[d];
+        av[d] = d == 0 ? make_double2(r.x + lam, 0.0) : r;
+        p0[d] = make_double2(0.0, 0.0);
+        p1[d] = make_double2(0.0, 0.0);
     }
-    for (int j = 0; j < n; ++j) {
+    __syncthreads();
+    double P = av[0].x;
+    bool ok = P > 0.0 && isfinite(P);
+    double2* cur = p0;
+    double2* nxt = p1;
+    for (int k = 1; k < n && ok; ++k) {
+        double sr = 0.0, si = 0.0;
+        for (int i = 1 + tid; i < k; i += 64) {
+            const double2 u = zmul(cur[i], av[k - i]);
+            sr += u.x;
+            si += u.y;
+        }
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) {
+            sr += __shfl_xor(sr, m);
+            si += __shfl_xor(si, m);
+        }
+        const double2 delta = make_double2(av[k].x + sr, av[k].y + si);
+        const double2 kap = make_double2(-delta.x / P, -delta.y / P);
+        for (int i = 1 + tid; i < k; i += 64) nxt[i] = zadd(cur[i], zmul(kap, zconj(cur[k - i])));
+        if (tid == 0) nxt[k] = kap;
+        P *= 1.0 - (kap.x * kap.x + kap.y * kap.y);
+        ok = P > 0.0 && isfinite(P);
+        double2* sw = cur;
+        cur = nxt;
+        nxt = sw;
         __syncthreads();
-        if (live) {
-            const double2 yj = yl[j];
-            const double2* Lj = Lf + (long long)j * n;
-            for (int i = j + 1 + rl; i < n; i += R) {
-                double2 v = zsub(yl[i], zmul(Lj[i], yj));
-                if (i == j + 1) {
-                    const double d = Lf[i + (long long)i * n].x;
-                    v = make_double2(v.x / d, v.y / d);
-                }
-                yl[i] = v;
-            }
+    }
+    if (!ok) {
+        if (tid == 0 && atomicCAS(status, 0, LMMSE_ERR_NOT_PD) == 0) status[1] = 0;
+        return;
+    }
+    // x = A^-1 e_0 = [1; p] / P, in place
+    const double iP = 1.0 / P;
+    for (int i = tid; i < n; i += 64) {
+        const double2 v = i == 0 ? make_double2(1.0, 0.0) : cur[i];
+        cur[i] = make_double2(v.x * iP, v.y * iP);
+    }
+    __syncthreads();
+    const double2* x = cur;
+    const double ix0 = 1.0 / x[0].x;
+    for (int d = tid; d < n; d += 64) {
+        // diagonal i - j = d: start at (d, 0), walk down
+        double2 v = x[d];
+        ainv[d] = v;
+        ainv[(long long)d * n] = zconj(v);
+        for (int s = 1; d + s < n; ++s) {
+            const int i = d + s, j = s;
+            const double2 t1 = zmulc(x[i], x[j]);
+            // y_{i-1} conj(y_{j-1}) with y_k = conj(x_{n-1-k})
+            const double2 t2 = zmulc(x[n - j], x[n - i]);
+            v = zadd(v, make_double2((t1.x - t2.x) * ix0, (t1.y - t2.y) * ix0));
+            ainv[i + (long long)j * n] = v;
+            ainv[j + (long long)i * n] = zconj(v);
         }
     }
-    // backward: L^H x = z, same scheme from the bottom row up.
-    __syncthreads();
-    if (live && rl == 0) {
-        const double d = Lf[(n - 1) + (long long)(n - 1) * n].x;
-        yl[n - 1] = make_double2(yl[n - 1].x / d, yl[n - 1].y / d);
-    }
-    for (int j = n - 1; j >= 0; --j) {
-        __syncthreads();
-        if (live) {
-            const double2 xj = yl[j];
-            for (int i = rl; i < j; i += R) {
-                double2 v = zsub(yl[i], zmul(zconj(Lf[j + (long long)i * n]), xj));
-                if (i == j - 1) {
-                    const double d = Lf[i + (long long)i * n].x;
-                    v = make_double2(v.x / d, v.y / d);
-                }
-                yl[i] = v;
-            }
-        }
-    }
-    __syncthreads();
-    if (live)
-        for (int i = rl; i < n; i += R) Y[i + (long long)col * n] = yl[i];
 }
 
-// W_c[i][j] = conj(X[j][off_c + i])  (X = A^-1 R_II, column-major n x n).
-__global__ void extract_kernel(const double2* __restrict__ X, const int* __restrict__ class_off,
-                               double2* __restrict__ w, int n_classes, int B, int n) {
+// W_c[i][j] = delta(off_c + i, j) - lam Ainv[off_c + i][j].
+__global__ void extract_kernel(const double2* __restrict__ ainv, const int* __restrict__ class_off,
+                               double2* __restrict__ w, int n_classes, int B, int n, double lam) {
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long per = (long long)B * n;
     if (idx >= per * n_classes) return;
     const int c = (int)(idx / per);
     const long long r = idx % per;
     const int i = (int)(r / n), j = (int)(r % n);
-    w[idx] = zconj(X[j + (long long)(class_off[c] + i) * n]);
+    const int row = class_off[c] + i;
+    const double2 v = ainv[row + (long long)j * n];
+    w[idx] = make_double2((row == j ? 1.0 : 0.0) - lam * v.x, -lam * v.y);
 }
 
 // Real embedding element Wr[r][kr] of filter w (B x Wn complex).
@@ -227,10 +197,11 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
 }
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-// hi = round(x), lo = round((x - hi) * lo_scale) in BF16 (is_fp16 = 0) or FP16.
+// Split parts of the real embedding: hi = round(x), lo = round(x - hi) in
+// BF16; FP16 stores lo = round(2^11 (x - hi)) and hs = 2^11 hi (exact).
 __global__ void pack_split_kernel(const double2* __restrict__ w64, uint16_t* __restrict__ hi,
-                                  uint16_t* __restrict__ lo, int n_classes, int B, int Wn, int G16,
-                                  int Rpad, int is_fp16, double lo_scale) {
+                                  uint16_t* __restrict__ lo, uint16_t* __restrict__ hs,
+                                  int n_classes, int B, int Wn, int G16, int Rpad, int is_fp16) {
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long total = (long long)n_classes * G16 * Rpad * 32;
     if (idx >= total) return;
@@ -244,36 +215,17 @@ __global__ void pack_split_kernel(const double2* __restrict__ w64, uint16_t* __r
     const double x = wreal(w64 + (long long)c * B * Wn, B, Wn, r, 32 * g + 8 * kq + e);
     if (is_fp16) {
         const _Float16 h = (_Float16)x;
-        const _Float16 l = (_Float16)((x - (double)h) * lo_scale);
+        const _Float16 l = (_Float16)((x - (double)h) * 2048.0);
+        const _Float16 s = (_Float16)((double)h * 2048.0);
         hi[idx] = __builtin_bit_cast(uint16_t, h);
         lo[idx] = __builtin_bit_cast(uint16_t, l);
+        hs[idx] = __builtin_bit_cast(uint16_t, s);
     } else {
         const uint16_t h = f32_to_bf16((float)x);
-        const uint16_t l = f32_to_bf16((float)((x - (double)bf16_to_f32(h)) * lo_scale));
+        const uint16_t l = f32_to_bf16((float)(x - (double)bf16_to_f32(h)));
         hi[idx] = h;
         lo[idx] = l;
     }
-}
-
-static int solve_cols_per_wg(int n) {
-    int nc = 16;
-    while (nc > 1 && (long long)nc * n * 16 > 65536) nc >>= 1;
-    return nc;
-}
-
-hipError_t launch_chol(double2* A, long long strideA, int n, int nmat, int* status, int info_base,
-                       hipStream_t st) {
-    hipLaunchKernelGGL(chol_kernel, dim3(nmat), dim3(1024), (size_t)n * sizeof(double2), st, A,
-                       strideA, n, status, info_base);
-    return hipGetLastError();
-}
-
-hipError_t launch_chol_solve(const double2* L, double2* Y, int n, int nrhs, hipStream_t st) {
-    const int nc = solve_cols_per_wg(n);
-    const unsigned grid = (unsigned)((nrhs + nc - 1) / nc);
-    hipLaunchKernelGGL(chol_solve_kernel, dim3(grid), dim3(256), (size_t)nc * n * sizeof(double2),
-                       st, L, Y, n, nrhs, nc);
-    return hipGetLastError();
 }
 
 hipError_t launch_pack_banks(Plan& p, hipStream_t st) {
@@ -286,8 +238,8 @@ hipError_t launch_pack_banks(Plan& p, hipStream_t st) {
     if (p.whi) {
         const long long total = (long long)p.n_classes * p.G16 * p.Rpad * 32;
         hipLaunchKernelGGL(pack_split_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
-                           st, p.w64, p.whi, p.wlo, p.n_classes, B, Wn, p.G16, p.Rpad,
-                           p.d.precision == LMMSE_FP16X3 ? 1 : 0, (double)p.lo_scale);
+                           st, p.w64, p.whi, p.wlo, p.whs, p.n_classes, B, Wn, p.G16, p.Rpad,
+                           p.d.precision == LMMSE_FP16X3 ? 1 : 0);
     }
     return hipGetLastError();
 }
@@ -297,17 +249,12 @@ hipError_t launch_fixed_design(Plan& p, double tau, double sigma2, hipStream_t s
     const double lam = sigma2 / p.d.K;
     hipLaunchKernelGGL(rd_kernel, dim3((n + 127) / 128), dim3(128), 0, st, p.rd, n, p.d.rsource,
                        p.d.L, tau, p.d.taps, p.d.N_fft);
-    const long long nn = (long long)n * n;
-    hipLaunchKernelGGL(toeplitz_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, p.rd,
-                       p.chol, p.fmat, n, lam);
-    hipError_t e = launch_chol(p.chol, 0, n, 1, p.status, 0, st);
-    if (e != hipSuccess) return e;
-    e = launch_chol_solve(p.chol, p.fmat, n, n, st);
-    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(toeplitz_inverse_kernel, dim3(1), dim3(64), (size_t)3 * n * sizeof(double2),
+                       st, p.rd, n, lam, p.ainv, p.status);
     const long long tot = (long long)p.n_classes * p.d.B * n;
     hipLaunchKernelGGL(extract_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
-                       p.fmat, p.d_class_off, p.w64, p.n_classes, p.d.B, n);
-    e = hipGetLastError();
+                       p.ainv, p.d_class_off, p.w64, p.n_classes, p.d.B, n, lam);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_pack_banks(p, st);
 }

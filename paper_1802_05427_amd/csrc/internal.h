@@ -20,7 +20,7 @@ namespace lmmse {
 //    2j, 2j+1 = Re, Im of input j).
 //  * split bank: for each class, groups of 16 complex rows (32 reals), rows
 //    r < Rpad, 4 lanes kq, 8 halves:  hi/lo[(((c*G16 + g)*Rpad + r)*4 + kq)*8 + e]
-//    = Wr[r][32g + 8kq + e].
+//    holds the parts of Wr[r][32g + 8kq + e].
 struct Plan {
     lmmse_plan_desc d{};
     int device = 0;
@@ -35,14 +35,15 @@ struct Plan {
     std::vector<int> h_starts, h_offsets, h_classes, h_class_off;
     int* d_starts = nullptr;     // [nb]
     int* d_classes = nullptr;    // [nb]
+    int* d_offsets = nullptr;    // [nb] output offset of each block in its window
     int* d_class_off = nullptr;  // [n_classes]
     double2* w64 = nullptr;      // [n_classes][B][Wn] FP64 filters
-    double2* fmat = nullptr;     // [Wn][Wn] work: A^-1 R_II  (fixed design)
-    double2* chol = nullptr;     // [Wn][Wn] Cholesky factor of R_II + lam I
+    double2* ainv = nullptr;     // [Wn][Wn] (R_II + lam I)^-1 of the fixed design
     double2* rd = nullptr;       // [2][Wn] r_d and dr_d/dtau, d = 0..Wn-1
     float4* wf32 = nullptr;      // FP32 bank
     uint16_t* whi = nullptr;     // split bank, hi part
-    uint16_t* wlo = nullptr;     // split bank, lo part
+    uint16_t* wlo = nullptr;     // split bank, lo part (FP16: scaled by 2^11)
+    uint16_t* whs = nullptr;     // FP16 only: 2^11 * hi part
     float2* twiddle = nullptr;   // [K] exp(+j 2 pi r / K)
     int* status = nullptr;       // [2] device status word: code, info
     double* dscal = nullptr;     // [4] device scratch for the design backward
@@ -64,8 +65,8 @@ hipError_t launch_apply_split(const Plan& p, int slots, const float2* x, const f
                               bool fused, float2* out, hipStream_t st);
 bool apply_fusable(const Plan& p);
 
-// Fixed design: r_d (and d r_d / d tau) on the device, A = R_II + lam I,
-// Cholesky, F = A^-1 R_II, then class filters W_c = (F^H)[off_c rows].
+// Fixed design: r_d (and d r_d / d tau) on the device, A^-1 of the Toeplitz
+// A = R_II + lam I, then class filters W_c = (I - lam A^-1)[off_c rows].
 hipError_t launch_fixed_design(Plan& p, double tau, double sigma2, hipStream_t st);
 // Convert p.w64 into the FP32 and split banks.
 hipError_t launch_pack_banks(Plan& p, hipStream_t st);

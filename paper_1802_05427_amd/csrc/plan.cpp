@@ -17,7 +17,8 @@ struct lmmse_plan : lmmse::Plan {};
 namespace {
 
 constexpr int kMaxK = 64;
-constexpr int kMaxWindow = 4096;     // FP64 design: pivot column cached in 64 KB of LDS
+constexpr int kMaxWindow = 1344;     // fixed design: 3 Wn complex doubles of LDS (<= 64 KB)
+constexpr int kMaxSampleWindow = 160;  // sample design: window held in registers
 constexpr int kRTs[] = {1, 2, 4, 8, 9, 13, 15, 17};
 
 #define LMMSE_HIP_TRY(expr)                       \
@@ -71,14 +72,15 @@ int validate(const lmmse_plan_desc* d) {
     if (d->Wn > kMaxWindow) return LMMSE_ERR_UNSUPPORTED;
     const long long cols = (long long)d->max_slots * d->M * d->K;
     if (cols * d->N >= (1LL << 40)) return LMMSE_ERR_UNSUPPORTED;
-    if (d->rsource == LMMSE_R_SAMPLE && d->Wn > 256) return LMMSE_ERR_UNSUPPORTED;
+    if (d->rsource == LMMSE_R_SAMPLE && d->Wn > kMaxSampleWindow) return LMMSE_ERR_UNSUPPORTED;
     return LMMSE_OK;
 }
 
-void choose_row_tiles(int B, int& RT, int& rgroups) {
+void choose_row_tiles(int B, int max_rt, int& RT, int& rgroups) {
     const int T = (2 * B + 15) / 16;
     long long best_pad = -1;
     for (int rt : kRTs) {
+        if (rt > max_rt) continue;
         const int g = (T + rt - 1) / rt;
         const long long padded = (long long)g * rt;
         if (best_pad < 0 || padded < best_pad || (padded == best_pad && g < rgroups)) {
@@ -104,8 +106,9 @@ int dev_alloc(T*& p, size_t count) {
 
 void free_plan(lmmse_plan* p) {
     if (!p) return;
-    void* ptrs[] = {p->d_starts, p->d_classes, p->d_class_off, p->w64, p->fmat, p->chol, p->rd,
-                    p->wf32,     p->whi,       p->wlo,         p->twiddle, p->status, p->dscal};
+    void* ptrs[] = {p->d_starts, p->d_classes, p->d_offsets, p->d_class_off, p->w64, p->ainv, p->rd,
+                    p->wf32,     p->whi,       p->wlo,         p->whs,     p->twiddle, p->status,
+                    p->dscal};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     delete p;
@@ -202,7 +205,8 @@ int lmmse_plan_create(const lmmse_plan_desc* desc, lmmse_plan_t* out) {
     p->nb = desc->N / desc->B;
     p->halo = (desc->Wn - desc->B) / 2;
     p->n_classes = (int)p->h_class_off.size();
-    choose_row_tiles(desc->B, p->RT, p->rgroups);
+    // split-precision kernels double-buffer three filter parts in LDS: RT <= 13
+    choose_row_tiles(desc->B, desc->precision == LMMSE_FP32 ? 17 : 13, p->RT, p->rgroups);
     p->Rpad = p->RT * 16 * p->rgroups;
     p->G8 = (desc->Wn + 7) / 8;
     p->G16 = (desc->Wn + 15) / 16;
@@ -218,18 +222,21 @@ int lmmse_plan_create(const lmmse_plan_desc* desc, lmmse_plan_t* out) {
         return code;
     };
     if ((rc = dev_alloc(p->d_starts, p->nb)) || (rc = dev_alloc(p->d_classes, p->nb)) ||
+        (rc = dev_alloc(p->d_offsets, p->nb)) ||
         (rc = dev_alloc(p->d_class_off, p->n_classes)) || (rc = dev_alloc(p->twiddle, K)) ||
         (rc = dev_alloc(p->status, 2)) || (rc = dev_alloc(p->dscal, 4)) ||
         (rc = dev_alloc(p->rd, 2 * (size_t)Wn)))
         return fail(rc);
     if (has_bank) {
         if ((rc = dev_alloc(p->w64, (size_t)p->n_classes * desc->B * Wn)) ||
-            (rc = dev_alloc(p->fmat, (size_t)Wn * Wn)) || (rc = dev_alloc(p->chol, (size_t)Wn * Wn)) ||
+            (rc = dev_alloc(p->ainv, (size_t)Wn * Wn)) ||
             (rc = dev_alloc(p->wf32, fixed_bank_f32_elems(*p))))
             return fail(rc);
         if (desc->precision != LMMSE_FP32 &&
             ((rc = dev_alloc(p->whi, split_bank_elems(*p))) ||
              (rc = dev_alloc(p->wlo, split_bank_elems(*p)))))
+            return fail(rc);
+        if (desc->precision == LMMSE_FP16X3 && (rc = dev_alloc(p->whs, split_bank_elems(*p))))
             return fail(rc);
     }
     std::vector<float2> tw(K);
@@ -240,6 +247,7 @@ int lmmse_plan_create(const lmmse_plan_desc* desc, lmmse_plan_t* out) {
     int zero[2] = {0, 0};
     if (hipMemcpy(p->d_starts, p->h_starts.data(), p->nb * sizeof(int), hipMemcpyHostToDevice) ||
         hipMemcpy(p->d_classes, p->h_classes.data(), p->nb * sizeof(int), hipMemcpyHostToDevice) ||
+        hipMemcpy(p->d_offsets, p->h_offsets.data(), p->nb * sizeof(int), hipMemcpyHostToDevice) ||
         hipMemcpy(p->d_class_off, p->h_class_off.data(), p->n_classes * sizeof(int),
                   hipMemcpyHostToDevice) ||
         hipMemcpy(p->twiddle, tw.data(), K * sizeof(float2), hipMemcpyHostToDevice) ||
@@ -313,8 +321,9 @@ int lmmse_get_filters(lmmse_plan_t plan, void* w_out, void* stream) {
 
 int lmmse_despread(lmmse_plan_t plan, int slots, const void* y, const void* pilots, void* h_ls,
                    void* stream) {
-    if (!plan || !y || !pilots || !h_ls) return LMMSE_ERR_INVALID_ARG;
-    if (slots < 0 || slots > plan->d.max_slots) return LMMSE_ERR_INVALID_ARG;
+    if (!plan || slots < 0 || slots > plan->d.max_slots) return LMMSE_ERR_INVALID_ARG;
+    if (slots == 0) return LMMSE_OK;
+    if (!y || !pilots || !h_ls) return LMMSE_ERR_INVALID_ARG;
     LMMSE_HIP_TRY(launch_despread(*plan, slots, (const float2*)y, (const float2*)pilots,
                                   (float2*)h_ls, (hipStream_t)stream));
     return LMMSE_OK;
@@ -330,18 +339,20 @@ static int apply_dispatch(lmmse_plan_t plan, int slots, const float2* x, const f
 }
 
 int lmmse_apply(lmmse_plan_t plan, int slots, const void* h_ls, void* h_hat, void* stream) {
-    if (!plan || !h_ls || !h_hat) return LMMSE_ERR_INVALID_ARG;
-    if (slots < 0 || slots > plan->d.max_slots) return LMMSE_ERR_INVALID_ARG;
+    if (!plan || slots < 0 || slots > plan->d.max_slots) return LMMSE_ERR_INVALID_ARG;
     if (plan->d.rsource == LMMSE_R_SAMPLE) return LMMSE_ERR_UNSUPPORTED;
     if (!plan->ready) return LMMSE_ERR_NOT_READY;
+    if (slots == 0) return LMMSE_OK;
+    if (!h_ls || !h_hat) return LMMSE_ERR_INVALID_ARG;
     return apply_dispatch(plan, slots, (const float2*)h_ls, nullptr, false, (float2*)h_hat,
                           (hipStream_t)stream);
 }
 
 int lmmse_covariance(lmmse_plan_t plan, int slots, const void* h_ls, void* r_win, void* stream) {
-    if (!plan || !h_ls || !r_win) return LMMSE_ERR_INVALID_ARG;
-    if (slots < 0 || slots > plan->d.max_slots) return LMMSE_ERR_INVALID_ARG;
-    if (plan->d.Wn > 256) return LMMSE_ERR_UNSUPPORTED;
+    if (!plan || slots < 0 || slots > plan->d.max_slots) return LMMSE_ERR_INVALID_ARG;
+    if (plan->d.Wn > kMaxSampleWindow) return LMMSE_ERR_UNSUPPORTED;
+    if (slots == 0) return LMMSE_OK;
+    if (!h_ls || !r_win) return LMMSE_ERR_INVALID_ARG;
     LMMSE_HIP_TRY(launch_covariance(*plan, slots, (const float2*)h_ls, (double2*)r_win,
                                     (hipStream_t)stream));
     return LMMSE_OK;
@@ -349,10 +360,11 @@ int lmmse_covariance(lmmse_plan_t plan, int slots, const void* h_ls, void* r_win
 
 int lmmse_sample_filters(lmmse_plan_t plan, int slots, const void* r_win, double sigma2,
                          void* w_out, void* stream) {
-    if (!plan || !r_win || !w_out) return LMMSE_ERR_INVALID_ARG;
-    if (slots < 0 || slots > plan->d.max_slots) return LMMSE_ERR_INVALID_ARG;
+    if (!plan || slots < 0 || slots > plan->d.max_slots) return LMMSE_ERR_INVALID_ARG;
     if (!(sigma2 >= 0.0) || !std::isfinite(sigma2)) return LMMSE_ERR_INVALID_ARG;
-    if (plan->d.Wn > 256) return LMMSE_ERR_UNSUPPORTED;
+    if (plan->d.Wn > kMaxSampleWindow) return LMMSE_ERR_UNSUPPORTED;
+    if (slots == 0) return LMMSE_OK;
+    if (!r_win || !w_out) return LMMSE_ERR_INVALID_ARG;
     const int nmat = slots * plan->d.K * plan->nb;
     LMMSE_HIP_TRY(launch_batched_filters(*plan, nmat, nullptr, nullptr, (const double2*)r_win,
                                          sigma2 / plan->d.K, (double2*)w_out, (hipStream_t)stream));
@@ -361,9 +373,10 @@ int lmmse_sample_filters(lmmse_plan_t plan, int slots, const void* r_win, double
 
 int lmmse_estimate(lmmse_plan_t plan, int slots, const void* y, const void* pilots, double sigma2,
                    void* h_hat, void* ws, size_t ws_bytes, void* stream) {
-    if (!plan || !y || !pilots || !h_hat) return LMMSE_ERR_INVALID_ARG;
-    if (slots < 0 || slots > plan->d.max_slots) return LMMSE_ERR_INVALID_ARG;
+    if (!plan || slots < 0 || slots > plan->d.max_slots) return LMMSE_ERR_INVALID_ARG;
     if (!(sigma2 > 0.0) || !std::isfinite(sigma2)) return LMMSE_ERR_INVALID_ARG;
+    if (slots == 0) return LMMSE_OK;
+    if (!y || !pilots || !h_hat) return LMMSE_ERR_INVALID_ARG;
     size_t need = 0;
     lmmse_workspace_size(&plan->d, slots, &need);
     const hipStream_t st = (hipStream_t)stream;
@@ -392,8 +405,8 @@ int lmmse_estimate(lmmse_plan_t plan, int slots, const void* y, const void* pilo
 
 int lmmse_backward(lmmse_plan_t plan, int slots, const void* h_ls, const void* g, void* d_hls,
                    double* d_tau, double* d_sigma2, void* ws, size_t ws_bytes, void* stream) {
-    if (!plan || !h_ls || !g || !d_hls) return LMMSE_ERR_INVALID_ARG;
-    if (slots < 0 || slots > plan->d.max_slots) return LMMSE_ERR_INVALID_ARG;
+    if (!plan || slots < 0 || slots > plan->d.max_slots) return LMMSE_ERR_INVALID_ARG;
+    if (slots > 0 && (!h_ls || !g || !d_hls)) return LMMSE_ERR_INVALID_ARG;
     const size_t need = backward_workspace_bytes(plan->d, slots);
     if (need && (!ws || ws_bytes < need)) return LMMSE_ERR_WORKSPACE;
     const hipStream_t st = (hipStream_t)stream;

@@ -70,6 +70,7 @@ def test_validate_accepts_workloads(lib, kw):
     (dict(B=7), _lib.UNSUPPORTED), (dict(Wn=151), _lib.UNSUPPORTED), (dict(Wn=80), _lib.UNSUPPORTED),
     (dict(Wn=1300), _lib.UNSUPPORTED), (dict(K=65), _lib.UNSUPPORTED),
     (dict(rsource="sample", B=300, Wn=300), _lib.UNSUPPORTED),
+    (dict(rsource="sample", B=100, Wn=200), _lib.UNSUPPORTED),
 ])
 def test_validate_rejects(lib, kw, code):
     d = _d(**kw)

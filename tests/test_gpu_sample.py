@@ -1,0 +1,107 @@
+"""GPU parity of the sample-covariance path against the FP64 oracle: the
+window covariances, the batched FP64 block filters, and the whole estimate;
+plus the device-side NOT_PD report."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1802_05427_amd import Plan
+from synth import make_slot_batch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _t(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+CASES = [
+    dict(M=8, K=2, N=72, N_fft=128, taps=8, tau=2.0, B=12, Wn=24, slots=2),      # Wn <= 32
+    dict(M=5, K=3, N=96, N_fft=128, taps=8, tau=2.0, B=16, Wn=48, slots=1),      # ragged M, Wn <= 64
+    dict(M=40, K=2, N=240, N_fft=256, taps=12, tau=3.0, B=60, Wn=120, slots=1),  # Wn <= 128
+    dict(M=130, K=2, N=300, N_fft=512, taps=16, tau=4.0, B=100, Wn=150, slots=1),  # 2 column groups
+    dict(M=128, K=12, N=1200, N_fft=2048, taps=72, tau=4.0, B=100, Wn=150, slots=1),
+    dict(M=128, K=12, N=1200, N_fft=2048, taps=72, tau=16.0, B=100, Wn=100, slots=1),
+]
+
+
+def _plan(c, sigma2):
+    return Plan(M=c["M"], K=c["K"], N=c["N"], N_fft=c["N_fft"], B=c["B"], Wn=c["Wn"],
+                rsource="sample", sigma2=sigma2, max_slots=c["slots"])
+
+
+@pytest.mark.parametrize("c", CASES[:4])
+def test_covariance_and_filters_fp64(dev, c):
+    print(f"sample design {c}", flush=True)
+    sb = make_slot_batch(M=c["M"], K=c["K"], N=c["N"], N_fft=c["N_fft"], taps=c["taps"], tau=c["tau"],
+                         snr_db=10.0, slots=c["slots"], config_id=1)
+    lam = sb.sigma2 / c["K"]
+    hls_ref = O.despread(sb.y, sb.pilots)
+    starts, offs = O.window_starts(c["N"], c["B"], c["Wn"])
+    with _plan(c, sb.sigma2) as plan:
+        hls = plan.despread(_t(sb.y, dev), _t(sb.pilots, dev))
+        r = plan.covariance(hls)
+        w = plan.sample_filters(r, sb.sigma2).cpu().numpy()
+        # filters from the oracle's own covariances: the design step alone
+        S, K, nb, Wn = c["slots"], c["K"], len(starts), c["Wn"]
+        r_or = np.empty((S, K, nb, Wn, Wn), complex)
+        for s in range(S):
+            for k in range(K):
+                for b, st in enumerate(starts):
+                    r_or[s, k, b] = O.sample_covariance(hls_ref[s, :, k, st:st + Wn])
+        w2 = plan.sample_filters(_t(r_or, dev), sb.sigma2).cpu().numpy()
+        st_, info = plan.sync_status()
+        assert st_ == 0
+        r = r.cpu().numpy()
+    # covariance: FP64 sums of exact products of the same FP32 inputs
+    err = np.linalg.norm(r - r_or) / np.linalg.norm(r_or)
+    assert err < 1e-13, err
+    for s in range(c["slots"]):
+        for k in range(c["K"]):
+            for b, (st, off) in enumerate(zip(starts, offs)):
+                R = r_or[s, k, b]
+                ref = O.lmmse._filter(R[off:off + c["B"]], R, lam)
+                e1 = np.linalg.norm(w2[s, k, b] - ref) / np.linalg.norm(ref)
+                e2 = np.linalg.norm(w[s, k, b] - ref) / np.linalg.norm(ref)
+                assert e1 < 1e-9 and e2 < 1e-9, (s, k, b, e1, e2)
+
+
+@pytest.mark.parametrize("c", CASES)
+@pytest.mark.parametrize("snr", [0.0, 20.0])
+def test_sample_estimate_matches_oracle(dev, c, snr):
+    print(f"sample estimate {c} snr={snr}", flush=True)
+    sb = make_slot_batch(M=c["M"], K=c["K"], N=c["N"], N_fft=c["N_fft"], taps=c["taps"], tau=c["tau"],
+                         snr_db=snr, slots=c["slots"], config_id=1)
+    with _plan(c, sb.sigma2) as plan:
+        out = plan.estimate(_t(sb.y, dev), _t(sb.pilots, dev), sb.sigma2).cpu().numpy()
+        st, info = plan.sync_status()
+    assert st == 0
+    ref = O.estimate(sb.y, sb.pilots, sb.sigma2, c["B"], c["Wn"], "sample")
+    disc = O.discrepancy_db(out, ref)
+    gap = abs(O.nmse_db(out, sb.H) - O.nmse_db(ref, sb.H))
+    print(f"  discrepancy {disc:.1f} dB, NMSE gap {gap:.2e} dB", flush=True)
+    assert disc < -100.0
+    assert gap < 1e-4
+
+
+def test_not_positive_definite_is_reported(dev):
+    c = dict(M=4, K=2, N=48, N_fft=64, B=12, Wn=24, slots=1)
+    with Plan(M=4, K=2, N=48, N_fft=64, B=12, Wn=24, rsource="sample", max_slots=1) as plan:
+        r = torch.zeros((1, 2, 4, 24, 24), dtype=torch.complex128, device=dev)
+        r[0, 1, 2] = -torch.eye(24, dtype=torch.complex128, device=dev)   # (k=1, b=2) not PD
+        for kb in [(0, 0), (0, 1), (0, 2), (0, 3), (1, 0), (1, 1), (1, 3)]:
+            r[0, kb[0], kb[1]] = torch.eye(24, dtype=torch.complex128, device=dev)
+        plan.sample_filters(r, 0.0)
+        st, info = plan.sync_status()
+        assert st == 5 and info == 1 * 4 + 2
+        # cleared after reading
+        assert plan.sync_status() == (0, -1)
+    del c

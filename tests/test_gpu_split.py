@@ -1,0 +1,58 @@
+"""GPU parity of the split-precision filtering (BF16 x3, FP16 x3 with FP32
+accumulation) against the FP64 oracle: NMSE gap within 0.05 dB at every SNR
+point, and an error far below the plain 16-bit rounding level."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1802_05427_amd import Plan
+from synth import make_slot_batch
+
+pytestmark = pytest.mark.gpu
+
+SPLIT_GAP_DB = 0.05
+# a single BF16 product would sit near -55 dB; the 3-product split must do far better
+SPLIT_DISC_DB = {"bf16x3": -85.0, "fp16x3": -95.0}
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _t(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16x3"])
+@pytest.mark.parametrize("cfg", [
+    dict(M=8, K=2, N=72, N_fft=128, taps=8, tau=2.0, B=12, Wn=24, slots=2),
+    dict(M=5, K=3, N=96, N_fft=128, taps=8, tau=2.0, B=12, Wn=24, slots=1),
+    dict(M=3, K=12, N=1200, N_fft=2048, taps=72, tau=4.0, B=100, Wn=150, slots=1),
+    dict(M=128, K=12, N=1200, N_fft=2048, taps=72, tau=4.0, B=100, Wn=150, slots=1),
+    dict(M=128, K=12, N=1200, N_fft=2048, taps=72, tau=16.0, B=100, Wn=100, slots=1),
+    dict(M=2, K=24, N=3300, N_fft=4096, taps=144, tau=32.0, B=132, Wn=198, slots=1),
+])
+@pytest.mark.parametrize("snr", [0.0, 10.0, 20.0])
+def test_split_estimate_matches_oracle(dev, prec, cfg, snr):
+    c = cfg
+    print(f"split {prec} {c} snr={snr}", flush=True)
+    sb = make_slot_batch(M=c["M"], K=c["K"], N=c["N"], N_fft=c["N_fft"], taps=c["taps"], tau=c["tau"],
+                         snr_db=snr, slots=c["slots"], config_id=2)
+    with Plan(M=c["M"], K=c["K"], N=c["N"], N_fft=c["N_fft"], B=c["B"], Wn=c["Wn"], rsource="exp",
+              taps=c["taps"], tau_rms=c["tau"], sigma2=sb.sigma2, max_slots=c["slots"],
+              precision=prec) as plan:
+        y, pil = _t(sb.y, dev), _t(sb.pilots, dev)
+        out = plan.estimate(y, pil, sb.sigma2).cpu().numpy()
+        out2 = plan.apply(plan.despread(y, pil)).cpu().numpy()
+    ref = O.estimate(sb.y, sb.pilots, sb.sigma2, c["B"], c["Wn"], "exp", N_fft=c["N_fft"],
+                     tau=c["tau"], taps=c["taps"])
+    for o in (out, out2):
+        disc = O.discrepancy_db(o, ref)
+        gap = abs(O.nmse_db(o, sb.H) - O.nmse_db(ref, sb.H))
+        print(f"  discrepancy {disc:.1f} dB, NMSE gap {gap:.2e} dB", flush=True)
+        assert gap < SPLIT_GAP_DB
+        assert disc < SPLIT_DISC_DB[prec]
