@@ -1,0 +1,46 @@
+"""torch.autograd.Function over the C ABI: the fixed-design block filter as a
+differentiable function of the LS estimates and of the design parameters.
+
+    h_hat = LmmseFn.apply(h_ls, tau_rms, sigma2, plan)
+
+h_ls is a complex64 CUDA tensor [S, M, K, N]; tau_rms and sigma2 are float64
+scalar tensors.  The forward (re)designs the plan's filters for (tau_rms,
+sigma2) and filters h_ls; the backward calls lmmse_backward, which returns
+dL/dh_ls = sum_b W_b^H G_b and the FP64 gradients of the design parameters
+(implicit differentiation of the block solve).  Complex gradients follow
+PyTorch's convention, dL/dRe + j dL/dIm, which is also the library's.
+"""
+from __future__ import annotations
+
+import torch
+
+
+class LmmseFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, h_ls, tau_rms, sigma2, plan):
+        tau = float(tau_rms)
+        sig = float(sigma2)
+        plan.set_design(tau, sig)
+        out = plan.apply(h_ls)
+        ctx.save_for_backward(h_ls)
+        ctx.plan = plan
+        ctx.design = (tau, sig)
+        return out
+
+    @staticmethod
+    def backward(ctx, g):
+        (h_ls,) = ctx.saved_tensors
+        plan = ctx.plan
+        tau, sig = ctx.design
+        # the plan may have been redesigned since this forward
+        plan.set_design(tau, sig)
+        want = bool(ctx.needs_input_grad[1] or ctx.needs_input_grad[2])
+        d_hls, d_tau, d_sig = plan.backward(h_ls, g.contiguous(), want_params=want)
+        gt = torch.tensor(d_tau, dtype=torch.float64) if ctx.needs_input_grad[1] else None
+        gs = torch.tensor(d_sig, dtype=torch.float64) if ctx.needs_input_grad[2] else None
+        return (d_hls if ctx.needs_input_grad[0] else None), gt, gs, None
+
+
+def lmmse_filter(h_ls, tau_rms, sigma2, plan):
+    """Functional form of LmmseFn."""
+    return LmmseFn.apply(h_ls, tau_rms, sigma2, plan)

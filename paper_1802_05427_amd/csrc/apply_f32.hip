@@ -11,14 +11,13 @@
 // (only the contraction order is permuted) and every operand read is a
 // 16-byte LDS read.
 //
-// A workgroup computes one block b, one row group (RT 16-row tiles) and 192
-// columns.  Its waves are specialised: 4 MFMA waves (wave w owns columns
-// [48w, 48w+48), 3 column tiles) and 4 loader waves (6 MFMA waves of 2
-// tiles and 2 loader waves for RT > 13).  The window is streamed
-// in chunks of 16 complex rows through two LDS buffers: while the MFMA waves
-// run RT x 3 x 8 MFMAs on chunk c, the loader waves copy the filter rows of
-// chunk c+1 (shared by all MFMA waves) and produce its LS values in the other
-// buffer; one barrier per chunk hands the buffers over.  LS values come from
+// A workgroup (4 waves) computes one block b, one row group (RT 16-row tiles)
+// and 192 columns; wave w owns columns [48w, 48w+48) (3 column tiles).  The
+// window is streamed in chunks of 16 complex rows: the workgroup copies the
+// chunk's filter rows (shared by all 4 waves) and its LS values into LDS, then
+// every wave runs RT x 3 x 8 MFMAs.  The raw inputs of chunk c+1 are loaded
+// into registers before the MFMAs of chunk c, and two workgroups share a CU,
+// so memory latency overlaps the matrix work.  LS values come from
 // H_LS (unfused) or are made on the fly from the pilot symbols (fused: one
 // thread per (antenna, subcarrier) reads y[s,m,0..K-1,n], undoes the cover
 // code with a K-point DFT and multiplies by conj(x_k[n]) / K).  The block index
@@ -57,38 +56,28 @@ __device__ __forceinline__ float f4c(const float4& v, int i) {
     return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
 }
 
-constexpr int kCols = 192;             // columns per workgroup (= MFMA waves x CT x 16)
+constexpr int kCT = 3;                 // column tiles per wave
+constexpr int kWaves = 4;
+constexpr int kThreads = 64 * kWaves;
+constexpr int kCols = 16 * kCT * kWaves;   // 192 columns per workgroup
 constexpr int kXS = 18;                // LDS column stride in complex (16 rows + pad)
-constexpr int kXBuf = kCols * kXS / 2; // float4 per LS buffer
 
-// Registers one loader thread holds for one chunk (window rows [16cc, 16cc+16)):
-// its share of the chunk's filter rows and of the raw inputs.
-template <int RT, int KF, int NL>
-struct ChunkRegs {
-    static constexpr int TW = (2 * RT * 64 + NL - 1) / NL;
+// Raw LS-path inputs one thread holds for one chunk (window rows [16cc, 16cc+16)).
+template <int KF>
+struct RawRegs {
     static constexpr int NPAIR = KF == 0 ? kCols * 16 : (kCols / KF) * 16;
-    static constexpr int TX = (NPAIR + NL - 1) / NL;
+    static constexpr int TX = (NPAIR + kThreads - 1) / kThreads;
     static constexpr int KV = KF == 0 ? 1 : KF;
-    float4 w[TW];
     float2 v[TX][KV];
 };
 
-// Issue the global loads of chunk cc (no LDS traffic, no waits).
-template <int RT, int KF, int NL>
-__device__ __forceinline__ void load_chunk(const ApplyArgs& a, int lt, int cc, int s0, long long c0,
-                                           const float4* wsrc, ChunkRegs<RT, KF, NL>& R) {
-    using CR = ChunkRegs<RT, KF, NL>;
-#pragma unroll
-    for (int u = 0; u < CR::TW; ++u) {
-        const int i = lt + u * NL;
-        const int gg = i / (RT * 64), rem = i - gg * (RT * 64);
-        const int g = 2 * cc + gg;
-        R.w[u] = (i < 2 * RT * 64 && g < a.G8) ? wsrc[(size_t)g * a.Rpad * 4 + rem]
-                                                 : make_float4(0.f, 0.f, 0.f, 0.f);
-    }
+template <int KF>
+__device__ __forceinline__ void load_raw(const ApplyArgs& a, int tid, int cc, int s0, long long c0,
+                                         RawRegs<KF>& R) {
+    using CR = RawRegs<KF>;
 #pragma unroll
     for (int u = 0; u < CR::TX; ++u) {
-        const int i = lt + u * NL;
+        const int i = tid + u * kThreads;
         const int cq = i >> 4, r = i & 15;
         const int j = cc * 16 + r;
         if constexpr (KF == 0) {
@@ -106,32 +95,25 @@ __device__ __forceinline__ void load_chunk(const ApplyArgs& a, int lt, int cc, i
     }
 }
 
-// Turn the loaded registers of chunk cc into LDS operands: filter rows as
-// they are, LS values straight (unfused) or after despreading (fused).
-template <int RT, int KF, int NL>
-__device__ __forceinline__ void store_chunk(const ApplyArgs& a, int lt, int cc, int s0,
-                                            const ChunkRegs<RT, KF, NL>& R, float4* ws4, float4* xs4) {
-    using CR = ChunkRegs<RT, KF, NL>;
-    float2* xs2 = reinterpret_cast<float2*>(xs4);
-#pragma unroll
-    for (int u = 0; u < CR::TW; ++u) {
-        const int i = lt + u * NL;
-        if (i < 2 * RT * 64) ws4[i] = R.w[u];
-    }
+// LS values of chunk cc into LDS: straight (unfused) or despread (fused).
+template <int KF>
+__device__ __forceinline__ void store_ls(const ApplyArgs& a, int tid, int cc, int s0,
+                                         const RawRegs<KF>& R, float2* xs2) {
+    using CR = RawRegs<KF>;
 #pragma unroll
     for (int u = 0; u < CR::TX; ++u) {
-        const int i = lt + u * NL;
+        const int i = tid + u * kThreads;
         if (i >= CR::NPAIR) continue;
         const int cq = i >> 4, r = i & 15;
         if constexpr (KF == 0) {
             xs2[cq * kXS + r] = R.v[u][0];
         } else {
             const int j = cc * 16 + r;
+            const bool live = j < a.Wn;
+            const int n = live ? s0 + j : 0;
             float2* dst = xs2 + cq * KF * kXS + r;
             float2 z[KF];
             Dft<KF>::run(R.v[u], z, nullptr);
-            const bool live = j < a.Wn;
-            const int n = live ? s0 + j : 0;
 #pragma unroll
             for (int k = 0; k < KF; ++k) {
                 const float2 h = cmulc(z[k], a.pilots[(long long)k * a.N + n]);
@@ -141,17 +123,20 @@ __device__ __forceinline__ void store_chunk(const ApplyArgs& a, int lt, int cc, 
     }
 }
 
-// RT row tiles x CT column tiles per MFMA wave, MW MFMA waves (CT * MW = 12),
-// 8 - MW loader waves.  Loader and MFMA waves run separate loops (the branch
-// is uniform per wave) that pass the same number of barriers, so their
-// registers do not overlap.  A loader thread issues all global loads of its
-// share of a chunk before it stores any of it.
-template <int RT, int CT, int MW, int KF>
-__global__ __launch_bounds__(512) void apply_f32_kernel(ApplyArgs a) {
-    constexpr int NL = 64 * (8 - MW);
-    static_assert(16 * CT * MW == kCols, "workgroup column count");
-    __shared__ float4 xs4[2 * kXBuf];          // LS chunks: [buf][col][16 rows]
-    __shared__ float4 ws4[2 * 2 * RT * 64];    // filter chunks: [buf][g][row][q]
+// RT row tiles x 3 column tiles per wave, 4 waves, 2 workgroups per CU.  Per
+// chunk: filter rows and LS values into LDS, barrier, MFMAs, barrier; the
+// raw inputs of the next chunk are loaded into registers before the MFMAs so
+// that their memory latency is hidden behind them.
+// Two workgroups per CU where the registers allow it (tall row groups and
+// K = 24 run one per CU rather than spill).
+template <int RT, int KF>
+constexpr int min_blocks() { return (RT <= 13 && KF != 24) ? 2 : 1; }
+
+template <int RT, int KF>
+__global__ __launch_bounds__(kThreads, (min_blocks<RT, KF>())) void apply_f32_kernel(ApplyArgs a) {
+    __shared__ float4 xs4[kCols * kXS / 2];   // LS chunk: [col][16 rows]
+    __shared__ float4 ws4[2 * RT * 64];       // filter chunk: [g][row][q]
+    float2* xs2 = reinterpret_cast<float2*>(xs4);
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l16 = lane & 15, q = lane >> 4;
     long long t = xcd_remap(blockIdx.x, a.n_tiles);
@@ -163,50 +148,39 @@ __global__ __launch_bounds__(512) void apply_f32_kernel(ApplyArgs a) {
     const float4* wsrc = a.wbank + ((size_t)cls * a.G8 * a.Rpad + (size_t)rg * RT * 16) * 4;
     const int nchunks = (a.Wn + 15) >> 4;
 
-    if (wave >= MW) {
-        const int lt = tid - 64 * MW;
-        ChunkRegs<RT, KF, NL> cr;
-        load_chunk<RT, KF, NL>(a, lt, 0, s0, c0, wsrc, cr);
-        store_chunk<RT, KF, NL>(a, lt, 0, s0, cr, ws4, xs4);
-        __syncthreads();
-        for (int cc = 0; cc < nchunks; ++cc) {
-            const int nb2 = (cc + 1) & 1;
-            if (cc + 1 < nchunks) {
-                load_chunk<RT, KF, NL>(a, lt, cc + 1, s0, c0, wsrc, cr);
-                store_chunk<RT, KF, NL>(a, lt, cc + 1, s0, cr, ws4 + nb2 * 2 * RT * 64,
-                                        xs4 + nb2 * kXBuf);
-            }
-            __syncthreads();
-        }
-        return;
-    }
-
-    floatx4 acc[RT][CT];
+    floatx4 acc[RT][kCT];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-        for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
-    __syncthreads();
+        for (int ct = 0; ct < kCT; ++ct) acc[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    RawRegs<KF> raw;
+    load_raw<KF>(a, tid, 0, s0, c0, raw);
     for (int cc = 0; cc < nchunks; ++cc) {
-        const int buf = cc & 1;
-        const float4* wb = ws4 + buf * 2 * RT * 64;
-        const float4* xb = xs4 + buf * kXBuf;
+        for (int i = tid; i < 2 * RT * 64; i += kThreads) {
+            const int gg = i / (RT * 64), rem = i - gg * (RT * 64);
+            const int g = 2 * cc + gg;
+            ws4[i] = g < a.G8 ? wsrc[(size_t)g * a.Rpad * 4 + rem] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        store_ls<KF>(a, tid, cc, s0, raw, xs2);
+        if (cc + 1 < nchunks) load_raw<KF>(a, tid, cc + 1, s0, c0, raw);
+        __syncthreads();
 #pragma unroll
         for (int gg = 0; gg < 2; ++gg) {
-            float4 av[RT], xv[CT];
+            float4 xv[kCT];
 #pragma unroll
-            for (int rt = 0; rt < RT; ++rt) av[rt] = wb[gg * RT * 64 + (rt * 16 + l16) * 4 + q];
+            for (int ct = 0; ct < kCT; ++ct)
+                xv[ct] = xs4[((wave * kCT + ct) * 16 + l16) * (kXS / 2) + 4 * gg + q];
 #pragma unroll
-            for (int ct = 0; ct < CT; ++ct)
-                xv[ct] = xb[((wave * CT + ct) * 16 + l16) * (kXS / 2) + 4 * gg + q];
+            for (int rt = 0; rt < RT; ++rt) {
+                const float4 av = ws4[gg * RT * 64 + (rt * 16 + l16) * 4 + q];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+                for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-                    for (int ct = 0; ct < CT; ++ct)
+                    for (int ct = 0; ct < kCT; ++ct)
                         acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                            f4c(av[rt], i), f4c(xv[ct], i), acc[rt][ct], 0, 0, 0);
+                            f4c(av, i), f4c(xv[ct], i), acc[rt][ct], 0, 0, 0);
+            }
         }
         __syncthreads();
     }
@@ -215,8 +189,8 @@ __global__ __launch_bounds__(512) void apply_f32_kernel(ApplyArgs a) {
     // column: complex outputs o, o+1 of the block
     const bool vec = a.vec_store != 0;
 #pragma unroll
-    for (int ct = 0; ct < CT; ++ct) {
-        const long long col = c0 + (wave * CT + ct) * 16 + l16;
+    for (int ct = 0; ct < kCT; ++ct) {
+        const long long col = c0 + (wave * kCT + ct) * 16 + l16;
         if (col >= a.ncols) continue;
         float2* op = a.out + col * a.N + (long long)b * a.B;
 #pragma unroll
@@ -266,13 +240,9 @@ hipError_t launch_apply_f32(const Plan& p, int slots, const float2* x, const flo
     if (a.n_tiles == 0) return hipSuccess;
     const dim3 grid((unsigned)a.n_tiles);
     const int kf = fused ? p.d.K : 0;
-    // tall row groups use 6 MFMA waves of 2 column tiles to stay in registers
-#define LMMSE_AF(R, KK)                                                                       \
-    case R:                                                                                   \
-        if constexpr (R <= 13)                                                                \
-            hipLaunchKernelGGL((apply_f32_kernel<R, 3, 4, KK>), grid, dim3(512), 0, st, a);  \
-        else                                                                                  \
-            hipLaunchKernelGGL((apply_f32_kernel<R, 2, 6, KK>), grid, dim3(512), 0, st, a);  \
+#define LMMSE_AF(R, KK)                                                                  \
+    case R:                                                                              \
+        hipLaunchKernelGGL((apply_f32_kernel<R, KK>), grid, dim3(kThreads), 0, st, a);   \
         break;
 #define LMMSE_AFK(KK)                                                                    \
     case KK:                                                                             \

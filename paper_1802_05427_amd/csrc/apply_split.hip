@@ -10,13 +10,13 @@
 // representable 2^11 hi_W, so the accumulator holds 2^11 W X and one scale by
 // 2^-11 at the store undoes it.  FP16 assumes |W| < 32 and |h_ls| < 65504.
 //
-// The structure follows the FP32 kernel (apply_f32.hip): 4 MFMA waves x 3
-// column tiles = 192 columns per workgroup plus 4 loader waves, RT <= 13
-// 16-row tiles of the real embedding, the window streamed through two LDS
-// buffers in chunks of 16 complex rows (32 reals = the K of one
-// v_mfma_f32_16x16x32_{bf16,f16}).  Lane (i16, kq) of an operand holds reals
-// 8kq..8kq+7 of its row / column (one 16-byte LDS read).  The LS chunk is
-// split once, by the loader, when it is written to LDS.
+// The structure follows the FP32 kernel (apply_f32.hip): 4 waves x 3 column
+// tiles = 192 columns per workgroup, RT <= 13 16-row tiles of the real
+// embedding, the window streamed in chunks of 16 complex rows (32 reals = the
+// K of one v_mfma_f32_16x16x32_{bf16,f16}), the next chunk's raw inputs
+// loaded into registers before the current chunk's MFMAs.  Lane (i16, kq) of
+// an operand holds reals 8kq..8kq+7 of its row / column (one 16-byte LDS
+// read).  The LS chunk is split once, when it is written to LDS.
 #include "dft.h"
 #include "internal.h"
 
@@ -85,39 +85,26 @@ __device__ __forceinline__ floatx4 mma(const uint4& a, const uint4& b, floatx4 c
                                                        __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
 
-constexpr int sCT = 3;                     // column tiles per MFMA wave
-constexpr int sMW = 4;                     // MFMA waves
-constexpr int sNL = 256;                   // loader threads (4 waves)
-constexpr int sCols = 16 * sCT * sMW;      // 192
+constexpr int sCT = 3;                     // column tiles per wave
+constexpr int sThreads = 256;              // 4 waves
+constexpr int sCols = 16 * sCT * 4;        // 192
 constexpr int sXS = 20;                    // LDS column stride in uint32 (16 rows + pad)
-constexpr int sXBuf = sCols * sXS / 4;     // uint4 per LS part buffer
 
-template <int RT, int KF>
-struct SplitRegs {
-    static constexpr int NW = 3 * RT * 64;                 // uint4 of the 3 filter parts
-    static constexpr int TW = (NW + sNL - 1) / sNL;
+template <int KF>
+struct SRaw {
     static constexpr int NPAIR = KF == 0 ? sCols * 16 : (sCols / KF) * 16;
-    static constexpr int TX = (NPAIR + sNL - 1) / sNL;
+    static constexpr int TX = (NPAIR + sThreads - 1) / sThreads;
     static constexpr int KV = KF == 0 ? 1 : KF;
-    uint4 w[TW];
     float2 v[TX][KV];
 };
 
-template <int RT, int KF>
-__device__ __forceinline__ void split_load(const SplitArgs& a, int lt, int cc, int s0, long long c0,
-                                           size_t wbase, SplitRegs<RT, KF>& R) {
-    using CR = SplitRegs<RT, KF>;
-    const size_t wofs = wbase + (size_t)cc * a.Rpad * 4;
-#pragma unroll
-    for (int u = 0; u < CR::TW; ++u) {
-        const int i = lt + u * sNL;
-        const int part = i / (RT * 64), rem = i - part * (RT * 64);
-        const uint4* src = part == 0 ? a.p0 : (part == 1 ? a.p1 : a.p2);
-        R.w[u] = i < CR::NW ? src[wofs + rem] : make_uint4(0u, 0u, 0u, 0u);
-    }
+template <int KF>
+__device__ __forceinline__ void split_load_raw(const SplitArgs& a, int tid, int cc, int s0,
+                                               long long c0, SRaw<KF>& R) {
+    using CR = SRaw<KF>;
 #pragma unroll
     for (int u = 0; u < CR::TX; ++u) {
-        const int i = lt + u * sNL;
+        const int i = tid + u * sThreads;
         const int cq = i >> 4, r = i & 15;
         const int j = cc * 16 + r;
         if constexpr (KF == 0) {
@@ -135,19 +122,14 @@ __device__ __forceinline__ void split_load(const SplitArgs& a, int lt, int cc, i
     }
 }
 
-template <int RT, int KF, bool FP16>
-__device__ __forceinline__ void split_store(const SplitArgs& a, int lt, int cc, int s0,
-                                            const SplitRegs<RT, KF>& R, uint4* w4, uint32_t* xh,
-                                            uint32_t* xl) {
-    using CR = SplitRegs<RT, KF>;
-#pragma unroll
-    for (int u = 0; u < CR::TW; ++u) {
-        const int i = lt + u * sNL;
-        if (i < CR::NW) w4[i] = R.w[u];
-    }
+// LS values of chunk cc, split into hi / lo parts, into LDS.
+template <int KF, bool FP16>
+__device__ __forceinline__ void split_store_ls(const SplitArgs& a, int tid, int cc, int s0,
+                                               const SRaw<KF>& R, uint32_t* xh, uint32_t* xl) {
+    using CR = SRaw<KF>;
 #pragma unroll
     for (int u = 0; u < CR::TX; ++u) {
-        const int i = lt + u * sNL;
+        const int i = tid + u * sThreads;
         if (i >= CR::NPAIR) continue;
         const int cq = i >> 4, r = i & 15;
         if constexpr (KF == 0) {
@@ -175,13 +157,19 @@ __device__ __forceinline__ void split_store(const SplitArgs& a, int lt, int cc, 
     }
 }
 
-// 4 MFMA waves (3 column tiles each) and 4 loader waves; two LDS buffers,
-// one barrier per chunk of 16 window rows (see apply_f32.hip).
+template <int RT, int KF>
+constexpr int split_min_blocks() { return (KF == 24 || (RT >= 13 && KF <= 2)) ? 1 : 2; }
+
+// 4 waves x 3 column tiles, RT <= 13 row tiles; per chunk of 16 window rows:
+// filter parts and split LS values into LDS, barrier, MFMAs, barrier; the
+// raw inputs of the next chunk are loaded into registers before the MFMAs.
 template <int RT, int KF, bool FP16>
-__global__ __launch_bounds__(512) void apply_split_kernel(SplitArgs a) {
-    __shared__ uint4 xh4[2 * sXBuf];
-    __shared__ uint4 xl4[2 * sXBuf];
-    __shared__ uint4 w4[2 * 3 * RT * 64];      // [buf][part][row][kq]
+__global__ __launch_bounds__(sThreads, (split_min_blocks<RT, KF>())) void apply_split_kernel(SplitArgs a) {
+    __shared__ uint4 xh4[sCols * sXS / 4];
+    __shared__ uint4 xl4[sCols * sXS / 4];
+    __shared__ uint4 w4[3 * RT * 64];          // [part][row][kq]
+    uint32_t* xh = reinterpret_cast<uint32_t*>(xh4);
+    uint32_t* xl = reinterpret_cast<uint32_t*>(xl4);
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l16 = lane & 15, kq = lane >> 4;
     long long t = xcd_remap_s(blockIdx.x, a.n_tiles);
@@ -193,46 +181,35 @@ __global__ __launch_bounds__(512) void apply_split_kernel(SplitArgs a) {
     const size_t wbase = ((size_t)cls * a.G16 * a.Rpad + (size_t)rg * RT * 16) * 4;
     const int nchunks = a.G16;
 
-    if (wave >= sMW) {
-        const int lt = tid - 64 * sMW;
-        SplitRegs<RT, KF> cr;
-        split_load<RT, KF>(a, lt, 0, s0, c0, wbase, cr);
-        split_store<RT, KF, FP16>(a, lt, 0, s0, cr, w4, reinterpret_cast<uint32_t*>(xh4),
-                                  reinterpret_cast<uint32_t*>(xl4));
-        __syncthreads();
-        for (int cc = 0; cc < nchunks; ++cc) {
-            const int nb2 = (cc + 1) & 1;
-            if (cc + 1 < nchunks) {
-                split_load<RT, KF>(a, lt, cc + 1, s0, c0, wbase, cr);
-                split_store<RT, KF, FP16>(a, lt, cc + 1, s0, cr, w4 + nb2 * 3 * RT * 64,
-                                          reinterpret_cast<uint32_t*>(xh4 + nb2 * sXBuf),
-                                          reinterpret_cast<uint32_t*>(xl4 + nb2 * sXBuf));
-            }
-            __syncthreads();
-        }
-        return;
-    }
-
     floatx4 acc[RT][sCT];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int ct = 0; ct < sCT; ++ct) acc[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
-    __syncthreads();
+
+    SRaw<KF> raw;
+    split_load_raw<KF>(a, tid, 0, s0, c0, raw);
     for (int cc = 0; cc < nchunks; ++cc) {
-        const int buf = cc & 1;
-        const uint4* wb = w4 + buf * 3 * RT * 64;
+        const size_t wofs = wbase + (size_t)cc * a.Rpad * 4;
+        for (int i = tid; i < RT * 64; i += sThreads) {
+            w4[i] = a.p0[wofs + i];
+            w4[RT * 64 + i] = a.p1[wofs + i];
+            w4[2 * RT * 64 + i] = a.p2[wofs + i];
+        }
+        split_store_ls<KF, FP16>(a, tid, cc, s0, raw, xh, xl);
+        if (cc + 1 < nchunks) split_load_raw<KF>(a, tid, cc + 1, s0, c0, raw);
+        __syncthreads();
         uint4 bh[sCT], bl[sCT];
 #pragma unroll
         for (int ct = 0; ct < sCT; ++ct) {
             const int c = (wave * sCT + ct) * 16 + l16;
-            bh[ct] = xh4[buf * sXBuf + c * (sXS / 4) + kq];
-            bl[ct] = xl4[buf * sXBuf + c * (sXS / 4) + kq];
+            bh[ct] = xh4[c * (sXS / 4) + kq];
+            bl[ct] = xl4[c * (sXS / 4) + kq];
         }
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
             const int wi = (rt * 16 + l16) * 4 + kq;
-            const uint4 a0 = wb[wi], a1 = wb[RT * 64 + wi], a2 = wb[2 * RT * 64 + wi];
+            const uint4 a0 = w4[wi], a1 = w4[RT * 64 + wi], a2 = w4[2 * RT * 64 + wi];
             // three independent column tiles between dependent products
 #pragma unroll
             for (int ct = 0; ct < sCT; ++ct) acc[rt][ct] = mma<FP16>(a0, bh[ct], acc[rt][ct]);
@@ -272,7 +249,7 @@ __global__ __launch_bounds__(512) void apply_split_kernel(SplitArgs a) {
 
 template <bool FP16>
 static hipError_t launch_split_t(const SplitArgs& a, int RT, int kf, hipStream_t st) {
-    const dim3 grid((unsigned)a.n_tiles), block(512);
+    const dim3 grid((unsigned)a.n_tiles), block(sThreads);
 #define LMMSE_AS(R, KK)                                                                  \
     case R:                                                                              \
         hipLaunchKernelGGL((apply_split_kernel<R, KK, FP16>), grid, block, 0, st, a);    \

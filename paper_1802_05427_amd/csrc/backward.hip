@@ -1,0 +1,537 @@
+// Backward pass of the fixed-design estimator (gradients through eq. 12 and
+// the eq. 13 / eq. 17 block filters of Sec. IV-B).
+//
+// Convention: g = dL/dRe(Hhat) + j dL/dIm(Hhat).  For block b with filter W
+// (B x Wn), window X_b (Wn values per column) and outputs G_b:
+//   d X_b  += W^H G_b                          (dx kernels)
+//   dW_c    = sum over blocks b of class c and all columns of G_b X_b^H
+//   Z_c     = dW_c A^-1,   Gamma_II = -W_c^H Z_c,   Gamma_OI = Z_c
+//   dlam    = sum_c Re tr(Gamma_II)
+//   dtau    = sum_c Re [ sum conj(Z_c) dR_OI + sum conj(Gamma_II) dR_II ]
+// with A = R_II + lam I, R entries r_{i-j} and dR = d r / d tau.
+//
+// dX: v_mfma_f32_16x16x4f32 on the real embedding of W^H (2Wn x 2B), one wave
+// per tile (RT row tiles of the Wn window outputs x 3 column tiles), the
+// operand layout of apply_f32.hip.  Windows of neighbouring blocks overlap,
+// so dX is zeroed and the blocks are processed in passes whose windows are
+// disjoint (block b in pass b mod P), each adding its contribution with a
+// read-add-write: deterministic, no atomics.
+//
+// dW: split over column chunks.  A workgroup (4 waves) takes one block and one
+// chunk of columns, stages 32 columns of G_b and X_b at a time in LDS and
+// accumulates G X^H on the FP32 matrix cores (A operand: the real embedding of
+// G^T built from LDS, B operand: X interleaved); its FP32 partial is written
+// out and the partials are summed per class in FP64 in a fixed order.
+#include <algorithm>
+
+#include "internal.h"
+
+namespace lmmse {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float bq(const float4& v, int i) {
+    return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
+}
+__device__ __forceinline__ long long bw_xcd(long long id, long long total) {
+    const long long NX = 8;
+    const long long q = total / NX, r = total % NX;
+    const long long x = id % NX, k = id / NX;
+    return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
+// ---------------------------------------------------------------- layout sizes
+struct BwGeom {
+    int RT, rgroups, Rpad;   // row tiles over the 2Wn real rows of W^H
+    int G8b;                 // groups of 8 complex block outputs (contraction)
+    int P;                   // passes with disjoint windows
+    int nch;                 // column chunks of the dW reduction
+};
+
+constexpr int kBwRTs[] = {1, 2, 4, 5, 8, 10};
+constexpr int kChunkCols = 1536;     // columns per dW workgroup
+
+static BwGeom bw_geom(const lmmse_plan_desc& d, const std::vector<int>& starts, long long ncols) {
+    BwGeom g{};
+    // padded row tiles, with a small charge per row group (each group re-reads G)
+    const int T = (2 * d.Wn + 15) / 16;
+    double best = -1.0;
+    for (int rt : kBwRTs) {
+        const int gg = (T + rt - 1) / rt;
+        const double cost = (double)gg * rt * (1.0 + 0.05 * gg);
+        if (best < 0.0 || cost < best) {
+            best = cost;
+            g.RT = rt;
+            g.rgroups = gg;
+        }
+    }
+    g.Rpad = g.RT * 16 * g.rgroups;
+    g.G8b = (d.B + 7) / 8;
+    const int nb = (int)starts.size();
+    g.P = 1;
+    for (bool clash = true; clash;) {
+        clash = false;
+        for (int b = 0; b + g.P < nb; ++b)
+            if (starts[b + g.P] < starts[b] + d.Wn) clash = true;
+        if (clash) ++g.P;
+    }
+    g.nch = (int)((ncols + kChunkCols - 1) / kChunkCols);
+    return g;
+}
+
+// ---------------------------------------------------------------- W^H bank
+// Real embedding of W^H (2Wn x 2B): Wr'[2i+ri][2o+ro] from conj(W[o][i]),
+// A-ready: bank[((c*G8b + g)*Rpad + r)*4 + q] = Wr'[r][16g + 4q .. +3].
+__global__ void pack_wh_kernel(const double2* __restrict__ w64, float4* __restrict__ bank,
+                               int n_classes, int B, int Wn, int G8b, int Rpad) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long total = (long long)n_classes * G8b * Rpad * 4;
+    if (idx >= total) return;
+    const int q = (int)(idx & 3);
+    long long t = idx >> 2;
+    const int r = (int)(t % Rpad);
+    t /= Rpad;
+    const int g = (int)(t % G8b);
+    const int c = (int)(t / G8b);
+    const int i = r >> 1, ri = r & 1;
+    float v[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int kr = 16 * g + 4 * q + e;
+        const int o = kr >> 1, ro = kr & 1;
+        float x = 0.f;
+        if (i < Wn && o < B) {
+            const double2 w = w64[((long long)c * B + o) * Wn + i];   // W^H[i][o] = conj(w)
+            if (ri == 0) x = (float)(ro == 0 ? w.x : w.y);
+            else x = (float)(ro == 0 ? -w.y : w.x);
+        }
+        v[e] = x;
+    }
+    bank[idx] = make_float4(v[0], v[1], v[2], v[3]);
+}
+
+__global__ void fill_zero_kernel(float2* p, long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = make_float2(0.f, 0.f);
+}
+
+// ---------------------------------------------------------------- dX
+struct DxArgs {
+    const float4* bank;
+    const int* starts;
+    const int* classes;
+    const float2* g;
+    float2* dx;
+    long long ncols, n_tiles;
+    int N, B, Wn, G8b, Rpad, rgroups, pass, P, nbp;   // nbp: blocks in this pass
+};
+
+template <int RT>
+__global__ __launch_bounds__(64) void dx_kernel(DxArgs a) {
+    constexpr int CT = 3;
+    const int lane = threadIdx.x, l16 = lane & 15, q = lane >> 4;
+    long long t = bw_xcd(blockIdx.x, a.n_tiles);
+    const int rg = (int)(t % a.rgroups);
+    t /= a.rgroups;
+    const int b = a.pass + a.P * (int)(t % a.nbp);
+    const long long c0 = (t / a.nbp) * (16 * CT);
+    const int s0 = a.starts[b], cls = a.classes[b];
+    floatx4 acc[RT][CT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const float4* wp = a.bank + ((size_t)cls * a.G8b * a.Rpad + (size_t)rg * RT * 16 + l16) * 4 + q;
+    const float2* gp[CT];
+    bool cv[CT];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+        const long long col = c0 + ct * 16 + l16;
+        cv[ct] = col < a.ncols;
+        gp[ct] = a.g + (cv[ct] ? col : 0) * a.N + (long long)b * a.B;
+    }
+    for (int gi = 0; gi < a.G8b; ++gi) {
+        float4 av[RT], xv[CT];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) av[rt] = wp[((size_t)gi * a.Rpad + rt * 16) * 4];
+        const int j = 8 * gi + 2 * q;
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+            float2 u0 = make_float2(0.f, 0.f), u1 = make_float2(0.f, 0.f);
+            if (cv[ct] && j < a.B) u0 = gp[ct][j];
+            if (cv[ct] && j + 1 < a.B) u1 = gp[ct][j + 1];
+            xv[ct] = make_float4(u0.x, u0.y, u1.x, u1.y);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int ct = 0; ct < CT; ++ct)
+                    acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(bq(av[rt], i), bq(xv[ct], i),
+                                                                       acc[rt][ct], 0, 0, 0);
+    }
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+        if (!cv[ct]) continue;
+        const long long col = c0 + ct * 16 + l16;
+        float2* op = a.dx + col * a.N + s0;
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+            const int o = (((rg * RT + rt) * 16) + 4 * q) >> 1;   // window row
+            const floatx4 v = acc[rt][ct];
+            if (o < a.Wn) {
+                float2 cur = op[o];
+                op[o] = make_float2(cur.x + v[0], cur.y + v[1]);
+            }
+            if (o + 1 < a.Wn) {
+                float2 cur = op[o + 1];
+                op[o + 1] = make_float2(cur.x + v[2], cur.y + v[3]);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- dW partials
+struct DwArgs {
+    const int* starts;
+    const float2* g;
+    const float2* x;
+    float2* part;        // [nb][nch][B][Wn]
+    long long ncols;
+    int N, B, Wn, nb, nch;
+};
+
+constexpr int kDwCols = 32;   // columns staged per step (4 groups of 8)
+
+template <int RT>
+__global__ __launch_bounds__(256) void dw_kernel(DwArgs a) {
+    constexpr int CTW = 3;                       // column tiles (of Wn) per wave
+    __shared__ float2 gs[kDwCols][RT * 8 + 1];   // G_b chunk: [col][output o]
+    __shared__ float2 xs[kDwCols][CTW * 4 * 16 + 1];   // X_b chunk: [col][window j]
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l16 = lane & 15, q = lane >> 4;
+    const int b = (int)(blockIdx.x % a.nb);
+    const int ch = (int)(blockIdx.x / a.nb);
+    const int s0 = a.starts[b];
+    const long long col_lo = (long long)ch * kChunkCols;
+    const long long col_hi = min(col_lo + kChunkCols, a.ncols);
+    floatx4 acc[RT][CTW];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < CTW; ++ct) acc[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const int jw = CTW * 4 * 16;   // window columns covered by the workgroup (>= Wn)
+    for (long long cb = col_lo; cb < col_hi; cb += kDwCols) {
+        for (int e = tid; e < kDwCols * RT * 8; e += 256) {
+            const int c = e / (RT * 8), o = e % (RT * 8);
+            const long long col = cb + c;
+            gs[c][o] = (col < col_hi && o < a.B) ? a.g[col * a.N + (long long)b * a.B + o]
+                                                 : make_float2(0.f, 0.f);
+        }
+        for (int e = tid; e < kDwCols * jw; e += 256) {
+            const int c = e / jw, j = e % jw;
+            const long long col = cb + c;
+            xs[c][j] = (col < col_hi && j < a.Wn) ? a.x[col * a.N + s0 + j] : make_float2(0.f, 0.f);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int gg = 0; gg < kDwCols / 8; ++gg) {
+            const int c = 8 * gg + 2 * q;   // this lane's two columns
+            float4 av[RT], xv[CTW];
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) {
+                const int r = rt * 16 + l16;
+                const int o = r >> 1;
+                const float2 g0 = gs[c][o], g1 = gs[c + 1][o];
+                // row 2o: (gr, gi) per column; row 2o+1: (gi, -gr)
+                av[rt] = (r & 1) == 0 ? make_float4(g0.x, g0.y, g1.x, g1.y)
+                                      : make_float4(g0.y, -g0.x, g1.y, -g1.x);
+            }
+#pragma unroll
+            for (int ct = 0; ct < CTW; ++ct) {
+                const int j = (wave * CTW + ct) * 16 + l16;
+                const float2 x0 = xs[c][j], x1 = xs[c + 1][j];
+                xv[ct] = make_float4(x0.x, x0.y, x1.x, x1.y);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                    for (int ct = 0; ct < CTW; ++ct)
+                        acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(bq(av[rt], i), bq(xv[ct], i),
+                                                                           acc[rt][ct], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    float2* pp = a.part + ((long long)b * a.nch + ch) * a.B * (long long)a.Wn;
+#pragma unroll
+    for (int ct = 0; ct < CTW; ++ct) {
+        const int j = (wave * CTW + ct) * 16 + l16;
+        if (j >= a.Wn) continue;
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+            const int o = (rt * 16 + 4 * q) >> 1;
+            const floatx4 v = acc[rt][ct];
+            if (o < a.B) pp[(long long)o * a.Wn + j] = make_float2(v[0], v[1]);
+            if (o + 1 < a.B) pp[(long long)(o + 1) * a.Wn + j] = make_float2(v[2], v[3]);
+        }
+    }
+}
+
+// dW_c[o][j] = sum over blocks of class c, then chunks, of the partials (FP64, fixed order)
+__global__ void dw_reduce_kernel(const float2* __restrict__ part, const int* __restrict__ classes,
+                                 double2* __restrict__ dwc, int n_classes, int nb, int nch, int B,
+                                 int Wn) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long per = (long long)B * Wn;
+    if (idx >= per * n_classes) return;
+    const int c = (int)(idx / per);
+    const long long e = idx % per;
+    double sx = 0.0, sy = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        if (classes[b] != c) continue;
+        const float2* p = part + (long long)b * nch * per + e;
+        for (int ch = 0; ch < nch; ++ch) {
+            const float2 v = p[(long long)ch * per];
+            sx += v.x;
+            sy += v.y;
+        }
+    }
+    dwc[idx] = make_double2(sx, sy);
+}
+
+// Z_c = dW_c A^-1  (A^-1 column-major, Hermitian)
+__global__ void z_kernel(const double2* __restrict__ dwc, const double2* __restrict__ ainv,
+                         double2* __restrict__ z, int n_classes, int B, int Wn) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long per = (long long)B * Wn;
+    if (idx >= per * n_classes) return;
+    const long long row = idx / Wn;     // (c, o)
+    const int j = (int)(idx % Wn);
+    const double2* d = dwc + row * Wn;
+    const double2* col = ainv + (long long)j * Wn;
+    double sx = 0.0, sy = 0.0;
+    for (int m = 0; m < Wn; ++m) {
+        const double2 u = d[m], v = col[m];
+        sx += u.x * v.x - u.y * v.y;
+        sy += u.x * v.y + u.y * v.x;
+    }
+    z[idx] = make_double2(sx, sy);
+}
+
+// Gamma_II[c][i][j] = -sum_o conj(W_c[o][i]) Z_c[o][j]
+__global__ void gamma_kernel(const double2* __restrict__ w64, const double2* __restrict__ z,
+                             double2* __restrict__ gam, int n_classes, int B, int Wn) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long per = (long long)Wn * Wn;
+    if (idx >= per * n_classes) return;
+    const int c = (int)(idx / per);
+    const int i = (int)((idx % per) / Wn), j = (int)(idx % Wn);
+    const double2* W = w64 + (long long)c * B * Wn;
+    const double2* Z = z + (long long)c * B * Wn;
+    double gx = 0.0, gy = 0.0;
+    for (int o = 0; o < B; ++o) {
+        const double2 w = W[(long long)o * Wn + i], zz = Z[(long long)o * Wn + j];
+        gx -= w.x * zz.x + w.y * zz.y;
+        gy -= w.x * zz.y - w.y * zz.x;
+    }
+    gam[idx] = make_double2(gx, gy);
+}
+
+// Per class: t1 = Re sum conj(Z) dR_OI, t2 = Re sum conj(Gamma_II) dR_II,
+// t3 = Re tr(Gamma_II).  One workgroup per class, fixed-order tree reduction;
+// results out[c*3 + 0..2].
+__global__ __launch_bounds__(256) void param_grad_kernel(const double2* __restrict__ z,
+                                                         const double2* __restrict__ gam,
+                                                         const double2* __restrict__ rd,
+                                                         const int* __restrict__ class_off,
+                                                         double* __restrict__ out, int B, int Wn) {
+    __shared__ double red[3][256];
+    const int c = blockIdx.x, tid = threadIdx.x;
+    const double2* Z = z + (long long)c * B * Wn;
+    const double2* G = gam + (long long)c * Wn * Wn;
+    const double2* dr = rd + Wn;
+    const int off = class_off[c];
+    double t1 = 0.0, t2 = 0.0, t3 = 0.0;
+    for (long long e = tid; e < (long long)B * Wn; e += 256) {
+        const int o = (int)(e / Wn), j = (int)(e % Wn);
+        const int d = off + o - j;
+        const double2 g = d >= 0 ? dr[d] : make_double2(dr[-d].x, -dr[-d].y);
+        t1 += Z[e].x * g.x + Z[e].y * g.y;
+    }
+    for (long long e = tid; e < (long long)Wn * Wn; e += 256) {
+        const int i = (int)(e / Wn), j = (int)(e % Wn);
+        const int d = i - j;
+        const double2 g = d >= 0 ? dr[d] : make_double2(dr[-d].x, -dr[-d].y);
+        t2 += G[e].x * g.x + G[e].y * g.y;
+        if (i == j) t3 += G[e].x;
+    }
+    red[0][tid] = t1;
+    red[1][tid] = t2;
+    red[2][tid] = t3;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s)
+            for (int k = 0; k < 3; ++k) red[k][tid] += red[k][tid + s];
+        __syncthreads();
+    }
+    if (tid == 0)
+        for (int k = 0; k < 3; ++k) out[c * 3 + k] = red[k][0];
+}
+
+// dscal[0] = dtau, dscal[1] = dlam, summed over classes in order
+__global__ void param_sum_kernel(const double* __restrict__ per, double* __restrict__ dscal,
+                                 int n_classes) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double dt = 0.0, dl = 0.0;
+    for (int c = 0; c < n_classes; ++c) {
+        dt += per[c * 3 + 0] + per[c * 3 + 1];
+        dl += per[c * 3 + 2];
+    }
+    dscal[0] = dt;
+    dscal[1] = dl;
+}
+
+// ---------------------------------------------------------------- host side
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static int count_classes(const lmmse_plan_desc& d) {
+    const int nb = d.N / d.B, halo = (d.Wn - d.B) / 2;
+    std::vector<int> offs;
+    for (int b = 0; b < nb; ++b) {
+        const int s = std::min(std::max(b * d.B - halo, 0), d.N - d.Wn);
+        const int o = b * d.B - s;
+        if (std::find(offs.begin(), offs.end(), o) == offs.end()) offs.push_back(o);
+    }
+    return (int)offs.size();
+}
+
+// Workspace: W^H bank | dW partials | dW_c, Z_c | Gamma_II | per-class scalars
+struct BwLayout {
+    size_t bank, part, dwc, zc, gam, per, total;
+};
+
+static BwLayout bw_layout(const lmmse_plan_desc& d, int n_classes, const BwGeom& g) {
+    BwLayout L{};
+    const size_t bank = (size_t)n_classes * g.G8b * g.Rpad * 4 * sizeof(float4);   // 4 lanes q per row
+    const size_t part = (size_t)(d.N / d.B) * g.nch * d.B * d.Wn * sizeof(float2);
+    const size_t bw = (size_t)n_classes * d.B * d.Wn * sizeof(double2);
+    const size_t gam = (size_t)n_classes * d.Wn * d.Wn * sizeof(double2);
+    L.bank = 0;
+    L.part = L.bank + align256(bank);
+    L.dwc = L.part + align256(part);
+    L.zc = L.dwc + align256(bw);
+    L.gam = L.zc + align256(bw);
+    L.per = L.gam + align256(gam);
+    L.total = L.per + align256((size_t)n_classes * 3 * sizeof(double));
+    return L;
+}
+
+size_t backward_workspace_bytes(const lmmse_plan_desc& d, int slots) {
+    if (d.rsource == LMMSE_R_SAMPLE) return 0;
+    const long long ncols = (long long)slots * d.M * d.K;
+    std::vector<int> starts;
+    const int nb = d.N / d.B, halo = (d.Wn - d.B) / 2;
+    for (int b = 0; b < nb; ++b) starts.push_back(std::min(std::max(b * d.B - halo, 0), d.N - d.Wn));
+    const BwGeom g = bw_geom(d, starts, ncols);
+    return bw_layout(d, count_classes(d), g).total;
+}
+
+hipError_t launch_backward_fixed(Plan& p, int slots, const float2* hls, const float2* g,
+                                 float2* dhls, bool want_params, void* ws, hipStream_t st) {
+    const long long ncols = (long long)slots * p.d.M * p.d.K;
+    if (ncols == 0) return hipSuccess;
+    const int B = p.d.B, Wn = p.d.Wn, N = p.d.N;
+    const BwGeom geo = bw_geom(p.d, p.h_starts, ncols);
+    const BwLayout L = bw_layout(p.d, p.n_classes, geo);
+    char* w = (char*)ws;
+    float4* bank = (float4*)(w + L.bank);
+    float2* part = (float2*)(w + L.part);
+    double2* dwc = (double2*)(w + L.dwc);
+    double2* zc = (double2*)(w + L.zc);
+    double2* gam = (double2*)(w + L.gam);
+    double* per = (double*)(w + L.per);
+
+    // W^H bank
+    {
+        const long long total = (long long)p.n_classes * geo.G8b * geo.Rpad * 4;
+        hipLaunchKernelGGL(pack_wh_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                           p.w64, bank, p.n_classes, B, Wn, geo.G8b, geo.Rpad);
+    }
+    // dX = 0, then one pass per window colour
+    {
+        const long long n = ncols * N;
+        hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, dhls, n);
+    }
+    for (int pass = 0; pass < geo.P; ++pass) {
+        DxArgs a;
+        a.bank = bank;
+        a.starts = p.d_starts;
+        a.classes = p.d_classes;
+        a.g = g;
+        a.dx = dhls;
+        a.ncols = ncols;
+        a.N = N;
+        a.B = B;
+        a.Wn = Wn;
+        a.G8b = geo.G8b;
+        a.Rpad = geo.Rpad;
+        a.rgroups = geo.rgroups;
+        a.pass = pass;
+        a.P = geo.P;
+        a.nbp = (p.nb - pass + geo.P - 1) / geo.P;
+        if (a.nbp <= 0) continue;
+        const long long ctiles = (ncols + 47) / 48;
+        a.n_tiles = ctiles * a.nbp * geo.rgroups;
+        const dim3 grid((unsigned)a.n_tiles), block(64);
+        switch (geo.RT) {
+#define LMMSE_DX(R) \
+    case R: hipLaunchKernelGGL((dx_kernel<R>), grid, block, 0, st, a); break;
+            LMMSE_DX(1) LMMSE_DX(2) LMMSE_DX(4) LMMSE_DX(5) LMMSE_DX(8) LMMSE_DX(10)
+#undef LMMSE_DX
+            default:
+                return hipErrorInvalidValue;
+        }
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !want_params) return e;
+
+    // dW partials -> per-class dW (FP64) -> Z -> scalars
+    if (B > 16 * 13 / 2 || Wn > 192) return hipErrorNotSupported;
+    DwArgs dw;
+    dw.starts = p.d_starts;
+    dw.g = g;
+    dw.x = hls;
+    dw.part = part;
+    dw.ncols = ncols;
+    dw.N = N;
+    dw.B = B;
+    dw.Wn = Wn;
+    dw.nb = p.nb;
+    dw.nch = geo.nch;
+    const int rtw = (2 * B + 15) / 16;
+    const dim3 gridw((unsigned)((long long)p.nb * geo.nch)), blockw(256);
+    if (rtw <= 2)
+        hipLaunchKernelGGL((dw_kernel<2>), gridw, blockw, 0, st, dw);
+    else if (rtw <= 4)
+        hipLaunchKernelGGL((dw_kernel<4>), gridw, blockw, 0, st, dw);
+    else if (rtw <= 8)
+        hipLaunchKernelGGL((dw_kernel<8>), gridw, blockw, 0, st, dw);
+    else
+        hipLaunchKernelGGL((dw_kernel<13>), gridw, blockw, 0, st, dw);
+    const long long tot = (long long)p.n_classes * B * Wn;
+    hipLaunchKernelGGL(dw_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, part,
+                       p.d_classes, dwc, p.n_classes, p.nb, geo.nch, B, Wn);
+    hipLaunchKernelGGL(z_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, dwc, p.ainv,
+                       zc, p.n_classes, B, Wn);
+    const long long totg = (long long)p.n_classes * Wn * Wn;
+    hipLaunchKernelGGL(gamma_kernel, dim3((unsigned)((totg + 255) / 256)), dim3(256), 0, st, p.w64, zc,
+                       gam, p.n_classes, B, Wn);
+    hipLaunchKernelGGL(param_grad_kernel, dim3(p.n_classes), dim3(256), 0, st, zc, gam, p.rd,
+                       p.d_class_off, per, B, Wn);
+    hipLaunchKernelGGL(param_sum_kernel, dim3(1), dim3(64), 0, st, per, p.dscal, p.n_classes);
+    return hipGetLastError();
+}
+
+}  // namespace lmmse

@@ -4,11 +4,6 @@
 
 namespace lmmse {
 
-size_t backward_workspace_bytes(const lmmse_plan_desc&, int) { return 0; }
-hipError_t launch_backward_fixed(Plan&, int, const float2*, const float2*, float2*, bool, void*,
-                                 hipStream_t) {
-    return hipErrorNotSupported;
-}
 hipError_t launch_backward_sample(Plan&, int, const float2*, const float2*, float2*, double, bool,
                                   void*, hipStream_t) {
     return hipErrorNotSupported;

@@ -44,10 +44,11 @@ def test_covariance_and_filters_fp64(dev, c):
     sb = make_slot_batch(M=c["M"], K=c["K"], N=c["N"], N_fft=c["N_fft"], taps=c["taps"], tau=c["tau"],
                          snr_db=10.0, slots=c["slots"], config_id=1)
     lam = sb.sigma2 / c["K"]
-    hls_ref = O.despread(sb.y, sb.pilots)
     starts, offs = O.window_starts(c["N"], c["B"], c["Wn"])
     with _plan(c, sb.sigma2) as plan:
         hls = plan.despread(_t(sb.y, dev), _t(sb.pilots, dev))
+        # the covariance is checked on the GPU's own LS values (complex64)
+        hls_ref = hls.cpu().numpy().astype(np.complex128)
         r = plan.covariance(hls)
         w = plan.sample_filters(r, sb.sigma2).cpu().numpy()
         # filters from the oracle's own covariances: the design step alone
