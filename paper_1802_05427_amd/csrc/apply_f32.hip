@@ -135,7 +135,7 @@ constexpr int min_blocks() { return (RT <= 13 && KF != 24) ? 2 : 1; }
 template <int RT, int KF>
 __global__ __launch_bounds__(kThreads, (min_blocks<RT, KF>())) void apply_f32_kernel(ApplyArgs a) {
     __shared__ float4 xs4[kCols * kXS / 2];   // LS chunk: [col][16 rows]
-    __shared__ float4 ws4[2 * RT * 64];       // filter chunk: [g][row][q]
+    __shared__ float4 ws4[2 * RT * 64];       // filter chunk: [g][q][row]
     float2* xs2 = reinterpret_cast<float2*>(xs4);
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l16 = lane & 15, q = lane >> 4;
@@ -157,10 +157,14 @@ __global__ __launch_bounds__(kThreads, (min_blocks<RT, KF>())) void apply_f32_ke
     RawRegs<KF> raw;
     load_raw<KF>(a, tid, 0, s0, c0, raw);
     for (int cc = 0; cc < nchunks; ++cc) {
+        // LDS copy is q-major ([g][q][row]) so that the 16 rows a lane group
+        // reads are consecutive 16-byte words (no bank conflicts)
         for (int i = tid; i < 2 * RT * 64; i += kThreads) {
             const int gg = i / (RT * 64), rem = i - gg * (RT * 64);
             const int g = 2 * cc + gg;
-            ws4[i] = g < a.G8 ? wsrc[(size_t)g * a.Rpad * 4 + rem] : make_float4(0.f, 0.f, 0.f, 0.f);
+            const int row = rem >> 2, qq = rem & 3;
+            ws4[gg * RT * 64 + qq * RT * 16 + row] =
+                g < a.G8 ? wsrc[(size_t)g * a.Rpad * 4 + rem] : make_float4(0.f, 0.f, 0.f, 0.f);
         }
         store_ls<KF>(a, tid, cc, s0, raw, xs2);
         if (cc + 1 < nchunks) load_raw<KF>(a, tid, cc + 1, s0, c0, raw);
@@ -173,7 +177,7 @@ __global__ __launch_bounds__(kThreads, (min_blocks<RT, KF>())) void apply_f32_ke
                 xv[ct] = xs4[((wave * kCT + ct) * 16 + l16) * (kXS / 2) + 4 * gg + q];
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt) {
-                const float4 av = ws4[gg * RT * 64 + (rt * 16 + l16) * 4 + q];
+                const float4 av = ws4[gg * RT * 64 + q * RT * 16 + rt * 16 + l16];
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
 #pragma unroll

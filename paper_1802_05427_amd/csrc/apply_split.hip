@@ -167,7 +167,7 @@ template <int RT, int KF, bool FP16>
 __global__ __launch_bounds__(sThreads, (split_min_blocks<RT, KF>())) void apply_split_kernel(SplitArgs a) {
     __shared__ uint4 xh4[sCols * sXS / 4];
     __shared__ uint4 xl4[sCols * sXS / 4];
-    __shared__ uint4 w4[3 * RT * 64];          // [part][row][kq]
+    __shared__ uint4 w4[3 * RT * 64];          // [part][kq][row]
     uint32_t* xh = reinterpret_cast<uint32_t*>(xh4);
     uint32_t* xl = reinterpret_cast<uint32_t*>(xl4);
 
@@ -191,10 +191,12 @@ __global__ __launch_bounds__(sThreads, (split_min_blocks<RT, KF>())) void apply_
     split_load_raw<KF>(a, tid, 0, s0, c0, raw);
     for (int cc = 0; cc < nchunks; ++cc) {
         const size_t wofs = wbase + (size_t)cc * a.Rpad * 4;
+        // q-major LDS copy ([part][kq][row]): conflict-free 16-byte reads
         for (int i = tid; i < RT * 64; i += sThreads) {
-            w4[i] = a.p0[wofs + i];
-            w4[RT * 64 + i] = a.p1[wofs + i];
-            w4[2 * RT * 64 + i] = a.p2[wofs + i];
+            const int li = (i & 3) * RT * 16 + (i >> 2);
+            w4[li] = a.p0[wofs + i];
+            w4[RT * 64 + li] = a.p1[wofs + i];
+            w4[2 * RT * 64 + li] = a.p2[wofs + i];
         }
         split_store_ls<KF, FP16>(a, tid, cc, s0, raw, xh, xl);
         if (cc + 1 < nchunks) split_load_raw<KF>(a, tid, cc + 1, s0, c0, raw);
@@ -208,7 +210,7 @@ __global__ __launch_bounds__(sThreads, (split_min_blocks<RT, KF>())) void apply_
         }
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
-            const int wi = (rt * 16 + l16) * 4 + kq;
+            const int wi = kq * RT * 16 + rt * 16 + l16;
             const uint4 a0 = w4[wi], a1 = w4[RT * 64 + wi], a2 = w4[2 * RT * 64 + wi];
             // three independent column tiles between dependent products
 #pragma unroll
