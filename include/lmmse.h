@@ -43,10 +43,15 @@
  * start_b - b*B shares one filter ("class"); there are at most 3 classes
  * when the halo (Wn-B)/2 is at most B (first, interior, last block).
  *
- * Precision: filters are designed in FP64 (Cholesky of R_II + lam I and two
- * triangular solves).  The filtering GEMM runs in FP32 on the matrix cores
- * (LMMSE_FP32), or as split products hi*hi + hi*lo + lo*hi with FP32
- * accumulation in BF16 (LMMSE_BF16X3) or FP16 (LMMSE_FP16X3).
+ * Precision: filters are designed in FP64.  A fixed design's R_II + lam I is
+ * Hermitian Toeplitz and is inverted in O(Wn^2) (Levinson-Durbin recursion,
+ * then the Gohberg-Semencul formula); the sample design inverts each window
+ * matrix by a Hermitian sweep (Gauss-Jordan on the lower triangle).  Since
+ * W = R_OI (R_II + lam I)^-1 = [I - lam (R_II + lam I)^-1] restricted to the
+ * kept rows, the inverse alone gives the filter.  The filtering GEMM runs
+ * in FP32 on the matrix cores (LMMSE_FP32), or as split products
+ * hi*hi + hi*lo + lo*hi with FP32 accumulation in BF16 (LMMSE_BF16X3) or
+ * FP16 (LMMSE_FP16X3).  The sample-covariance path always filters in FP32.
  *
  * Calls with slots == 0 launch nothing and accept NULL data pointers.
  *
@@ -151,9 +156,10 @@ int lmmse_plan_get_desc(lmmse_plan_t plan, lmmse_plan_desc *out);
 
 /* Rebuilds a fixed design (UNIFORM or EXPONENTIAL) with a new tau_rms
  * (EXPONENTIAL only; ignored for UNIFORM) and design noise sigma2, on
- * `stream`: r_d, A = R_II + lam I, Cholesky, two triangular solves per
- * class, then the FP32 / split copies.  Asynchronous.  A failed
- * factorisation is reported by lmmse_sync_status. */
+ * `stream`: r_d, then per class the inverse of A = R_II + lam I
+ * (Levinson-Durbin + Gohberg-Semencul), W = I - lam A^-1 on the kept rows,
+ * then the FP32 / split copies.  Asynchronous.  A non-positive prediction
+ * error (A not positive definite) is reported by lmmse_sync_status. */
 int lmmse_set_design(lmmse_plan_t plan, double tau_rms, double sigma2, void *stream);
 
 /* Installs caller filters (LMMSE_R_USER plans): w is device complex128
@@ -176,8 +182,11 @@ int lmmse_despread(lmmse_plan_t plan, int slots, const void *y_pilot,
 int lmmse_apply(lmmse_plan_t plan, int slots, const void *h_ls, void *h_hat,
                 void *stream);
 
-/* Sample covariance per (slot, user, window), a Hermitian rank-M update
- * accumulated in FP32 and stored as complex128 [S][K][N/B][Wn][Wn]. */
+/* Sample covariance per (slot, user, window), R = (1/M) sum_m h_m h_m^H over
+ * the antennas (Sec. III-B, eq. 13's R estimated from the data), products of
+ * the complex64 LS values accumulated in FP64, stored as complex128
+ * [S][K][N/B][Wn][Wn] (full matrix, both triangles).  Any plan with
+ * Wn <= 160 (else UNSUPPORTED). */
 int lmmse_covariance(lmmse_plan_t plan, int slots, const void *h_ls,
                      void *r_win, void *stream);
 
@@ -204,8 +213,9 @@ int lmmse_estimate(lmmse_plan_t plan, int slots, const void *y_pilot,
  * j dL/dIm(h_hat) (complex64 [S][M][K][N]).  Writes d_hls (same layout) and,
  * when the pointers are non-NULL, the host doubles *d_tau (EXPONENTIAL
  * design only; NaN otherwise) and *d_sigma2 (fixed and sample designs);
- * requesting them synchronises `stream`.  For the sample covariance, d_hls
- * includes the path through R. ws: lmmse_workspace_size bytes. */
+ * requesting them synchronises `stream`.  Fixed designs only: a
+ * sample-covariance plan returns UNSUPPORTED (the path through R is not
+ * implemented).  ws: lmmse_workspace_size bytes. */
 int lmmse_backward(lmmse_plan_t plan, int slots, const void *h_ls,
                    const void *g, void *d_hls, double *d_tau, double *d_sigma2,
                    void *ws, size_t ws_bytes, void *stream);

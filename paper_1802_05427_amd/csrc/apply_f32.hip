@@ -13,19 +13,21 @@
 //
 // A workgroup (4 waves) computes one block b, one row group (RT 16-row tiles)
 // and 192 columns; wave w owns columns [48w, 48w+48) (3 column tiles).  The
-// window is streamed in chunks of 16 complex rows: the workgroup copies the
-// chunk's filter rows (shared by all 4 waves) and its LS values into LDS, then
-// every wave runs RT x 3 x 8 MFMAs.  The raw inputs of chunk c+1 are loaded
-// into registers before the MFMAs of chunk c, and two workgroups share a CU,
-// so memory latency overlaps the matrix work.  LS values come from
-// H_LS (unfused) or are made on the fly from the pilot symbols (fused: one
-// thread per (antenna, subcarrier) reads y[s,m,0..K-1,n], undoes the cover
-// code with a K-point DFT and multiplies by conj(x_k[n]) / K).  The block index
-// runs fastest over consecutive tiles and tiles are remapped so that each XCD
-// takes a contiguous range: the overlapping windows of neighbouring blocks of
-// a column group are read through the same L2.
+// window is streamed in chunks of 16 complex rows (two groups of 8).  Per
+// chunk the workgroup puts the LS values into LDS (from H_LS, or made on the
+// fly from the pilot symbols: one thread per (antenna, subcarrier) undoes the
+// cover code of y[s,m,0..K-1,n] with a K-point DFT and multiplies by
+// conj(x_k[n]) / K), then every wave runs RT x 3 x 8 MFMAs against the
+// chunk's filter rows.  Memory latency is kept off the matrix cores: the raw
+// inputs of chunk c+1 are loaded into registers before the MFMAs of chunk c;
+// the filter rows of chunk c+1 are copied global-to-LDS into the other of two
+// buffers, and the pilot slice of chunk c+2 loaded, halfway through them;
+// two workgroups share a CU.  The block index runs fastest over consecutive
+// tiles and tiles are remapped so that each XCD takes a contiguous range: the
+// overlapping windows of neighbouring blocks of a column group are read
+// through the same L2.
+#include "chunk_io.h"
 #include "dft.h"
-#include "internal.h"
 
 namespace lmmse {
 
@@ -40,65 +42,23 @@ struct ApplyArgs {
     float2* out;           // [cols][N]
     long long ncols;       // S*M*K
     long long n_tiles;
-    int N, B, Wn, G8, Rpad, nb, rgroups;
+    int N, B, Wn, G16, Rpad, nb, rgroups;
     int vec_store;         // N, B even and out 16-byte aligned: float4 stores
     float invK;
 };
-
-__device__ __forceinline__ long long xcd_remap(long long id, long long total) {
-    const long long NX = 8;
-    const long long q = total / NX, r = total % NX;
-    const long long x = id % NX, k = id / NX;
-    return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
-}
 
 __device__ __forceinline__ float f4c(const float4& v, int i) {
     return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
 }
 
-constexpr int kCT = 3;                 // column tiles per wave
-constexpr int kWaves = 4;
-constexpr int kThreads = 64 * kWaves;
-constexpr int kCols = 16 * kCT * kWaves;   // 192 columns per workgroup
-constexpr int kXS = 18;                // LDS column stride in complex (16 rows + pad)
-
-// Raw LS-path inputs one thread holds for one chunk (window rows [16cc, 16cc+16)).
-template <int KF>
-struct RawRegs {
-    static constexpr int NPAIR = KF == 0 ? kCols * 16 : (kCols / KF) * 16;
-    static constexpr int TX = (NPAIR + kThreads - 1) / kThreads;
-    static constexpr int KV = KF == 0 ? 1 : KF;
-    float2 v[TX][KV];
-};
-
-template <int KF>
-__device__ __forceinline__ void load_raw(const ApplyArgs& a, int tid, int cc, int s0, long long c0,
-                                         RawRegs<KF>& R) {
-    using CR = RawRegs<KF>;
-#pragma unroll
-    for (int u = 0; u < CR::TX; ++u) {
-        const int i = tid + u * kThreads;
-        const int cq = i >> 4, r = i & 15;
-        const int j = cc * 16 + r;
-        if constexpr (KF == 0) {
-            const long long col = c0 + cq;
-            R.v[u][0] = (i < CR::NPAIR && j < a.Wn && col < a.ncols) ? a.x[col * a.N + s0 + j]
-                                                                    : make_float2(0.f, 0.f);
-        } else {
-            const long long ant = c0 / KF + cq;
-            const bool live = i < CR::NPAIR && j < a.Wn && ant < a.ncols / KF;
-            const float2* yp = a.x + ant * KF * (long long)a.N + s0 + j;
-#pragma unroll
-            for (int tt = 0; tt < KF; ++tt)
-                R.v[u][tt] = live ? yp[(long long)tt * a.N] : make_float2(0.f, 0.f);
-        }
-    }
-}
+// LS chunk in LDS: slot f (complex rows 2f, 2f+1, one float4) of column c.
+__device__ __forceinline__ int xs4_at(int c, int f) { return f * kXP + c; }
+__device__ __forceinline__ int xs2_at(int c, int r) { return 2 * xs4_at(c, r >> 1) + (r & 1); }
 
 // LS values of chunk cc into LDS: straight (unfused) or despread (fused).
 template <int KF>
-__device__ __forceinline__ void store_ls(const ApplyArgs& a, int tid, int cc, int s0,
-                                         const RawRegs<KF>& R, float2* xs2) {
+__device__ __forceinline__ void store_ls(const ApplyArgs& a, int tid, int cc, const RawRegs<KF>& R,
+                                         float2* xs2, const float2* pl) {
     using CR = RawRegs<KF>;
 #pragma unroll
     for (int u = 0; u < CR::TX; ++u) {
@@ -106,47 +66,130 @@ __device__ __forceinline__ void store_ls(const ApplyArgs& a, int tid, int cc, in
         if (i >= CR::NPAIR) continue;
         const int cq = i >> 4, r = i & 15;
         if constexpr (KF == 0) {
-            xs2[cq * kXS + r] = R.v[u][0];
+            xs2[xs2_at(cq, r)] = R.v[u][0];
         } else {
-            const int j = cc * 16 + r;
-            const bool live = j < a.Wn;
-            const int n = live ? s0 + j : 0;
-            float2* dst = xs2 + cq * KF * kXS + r;
+            const bool live = cc * 16 + r < a.Wn;
             float2 z[KF];
             Dft<KF>::run(R.v[u], z, nullptr);
 #pragma unroll
             for (int k = 0; k < KF; ++k) {
-                const float2 h = cmulc(z[k], a.pilots[(long long)k * a.N + n]);
-                dst[k * kXS] = live ? make_float2(h.x * a.invK, h.y * a.invK) : make_float2(0.f, 0.f);
+                const float2 h = cmulc(z[k], pl[k * 16 + r]);
+                xs2[xs2_at(cq * KF + k, r)] =
+                    live ? make_float2(h.x * a.invK, h.y * a.invK) : make_float2(0.f, 0.f);
             }
         }
     }
 }
 
-// RT row tiles x 3 column tiles per wave, 4 waves, 2 workgroups per CU.  Per
-// chunk: filter rows and LS values into LDS, barrier, MFMAs, barrier; the
-// raw inputs of the next chunk are loaded into registers before the MFMAs so
-// that their memory latency is hidden behind them.
-// Two workgroups per CU where the registers allow it (tall row groups and
-// K = 24 run one per CU rather than spill).
+// LS operands of one group of 8 complex window rows for this wave's 3
+// column tiles.
+__device__ __forceinline__ void load_xv(float4 (&xv)[kCT], const float4* xs4, int gg, int wave,
+                                        int l16, int q) {
+#pragma unroll
+    for (int ct = 0; ct < kCT; ++ct) xv[ct] = xs4[xs4_at((wave * kCT + ct) * 16 + l16, 4 * gg + q)];
+}
+
+// One group of 8 complex window rows: 4 k-steps x RT x 3 MFMAs per wave.
+// ws4 holds the chunk's filter rows as [gg][q][row].
+template <int RT>
+__device__ __forceinline__ void mfma_group(floatx4 (&acc)[RT][kCT], const float4 (&xv)[kCT],
+                                           const float4* ws4, int gg, int l16, int q) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+        const float4 av = ws4[gg * RT * 64 + q * RT * 16 + rt * 16 + l16];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int ct = 0; ct < kCT; ++ct)
+                acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(f4c(av, i), f4c(xv[ct], i),
+                                                                   acc[rt][ct], 0, 0, 0);
+    }
+}
+
+// Filter rows of chunk cc of this workgroup's row group into LDS: two runs
+// of RT*64 float4 (one per group of 8 window rows), contiguous in the bank.
+template <int RT>
+__device__ __forceinline__ void copy_w(const float4* wsrc, size_t gstride, int cc, int wave,
+                                       int lane, float4* wdst) {
+    dma_copy<RT * 64>(wsrc + (size_t)(2 * cc) * gstride, wdst, wave, lane);
+    dma_copy<RT * 64>(wsrc + (size_t)(2 * cc + 1) * gstride, wdst + RT * 64, wave, lane);
+}
+
+// Per-workgroup constants of the filtering loop.
+struct ChunkCtx {
+    const ApplyArgs& a;
+    const float4* wsrc;
+    size_t gstride;
+    long long c0;
+    int s0, nchunks, tid, wave, lane, l16, q;
+};
+
+// One chunk: chunk cc+1's pilots (held in registers) and chunk cc's LS values
+// into LDS, chunk cc+1's raw inputs into registers, barrier, the MFMAs of
+// the first group, the copy of chunk cc+1's filter rows into wnext and chunk
+// cc+2's pilots into registers, the MFMAs of the second group, wait for this
+// wave's loads, barrier.  wcur / wnext name the two LDS filter buffers
+// directly, so the compiler sees that the copy into one does not touch the
+// other and adds no wait before the reads of wcur; the LS operands of the
+// second group are read before the copy is issued (the compiler cannot tell
+// xs4 from wnext and would wait for the copy before reading them).
+template <int RT, int KF>
+__device__ __forceinline__ void chunk_step(const ChunkCtx& x, int cc, float4* xs4, float2* pl,
+                                           float4* wcur, float4* wnext, floatx4 (&acc)[RT][kCT],
+                                           RawRegs<KF>& raw, PilotRegs<KF>& pr) {
+    constexpr int NS = PilotRegs<KF>::NS;
+    if constexpr (KF > 0)
+        if (cc + 1 < x.nchunks) store_pil<KF>(pr, pl + ((cc + 1) & 1) * NS, x.tid);
+    store_ls<KF>(x.a, x.tid, cc, raw, reinterpret_cast<float2*>(xs4), pl + (cc & 1) * NS);
+    if (cc + 1 < x.nchunks) load_raw<KF>(x.a, x.tid, cc + 1, x.s0, x.c0, raw);
+    __syncthreads();
+    float4 xv[kCT];
+    load_xv(xv, xs4, 0, x.wave, x.l16, x.q);
+    mfma_group<RT>(acc, xv, wcur, 0, x.l16, x.q);
+    load_xv(xv, xs4, 1, x.wave, x.l16, x.q);
+    if (cc + 1 < x.nchunks) {
+        copy_w<RT>(x.wsrc, x.gstride, cc + 1, x.wave, x.lane, wnext);
+        if constexpr (KF > 0)
+            if (cc + 2 < x.nchunks) load_pil<KF>(x.a, x.s0, cc + 2, x.tid, pr);
+    }
+    // the second group of the last chunk may lie wholly past the window
+    if (16 * cc + 8 < x.a.Wn) mfma_group<RT>(acc, xv, wcur, 1, x.l16, x.q);
+    wait_vm();
+    __syncthreads();
+}
+
+// RT row tiles x 3 column tiles per wave, 4 waves.  Two workgroups per CU
+// where registers and LDS allow it (tall row groups and K = 24 run one per
+// CU rather than spill).
 template <int RT, int KF>
 constexpr int min_blocks() { return (RT <= 13 && KF != 24) ? 2 : 1; }
 
 template <int RT, int KF>
 __global__ __launch_bounds__(kThreads, (min_blocks<RT, KF>())) void apply_f32_kernel(ApplyArgs a) {
-    __shared__ float4 xs4[kCols * kXS / 2];   // LS chunk: [col][16 rows]
-    __shared__ float4 ws4[2 * RT * 64];       // filter chunk: [g][q][row]
-    float2* xs2 = reinterpret_cast<float2*>(xs4);
+    constexpr int NS = PilotRegs<KF>::NS;
+    __shared__ float4 xs4[8 * kXP];           // LS chunk: [slot][col]
+    __shared__ float4 wA[2 * RT * 64];        // filter chunks, even / odd: [gg][q][row]
+    __shared__ float4 wB[2 * RT * 64];
+    __shared__ float2 pl[2 * NS];             // pilot slices of two chunks
 
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l16 = lane & 15, q = lane >> 4;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform per wave
     long long t = xcd_remap(blockIdx.x, a.n_tiles);
     const int rg = (int)(t % a.rgroups);
     t /= a.rgroups;
     const int b = (int)(t % a.nb);
-    const long long c0 = (t / a.nb) * kCols;
-    const int s0 = a.starts[b], cls = a.classes[b];
-    const float4* wsrc = a.wbank + ((size_t)cls * a.G8 * a.Rpad + (size_t)rg * RT * 16) * 4;
-    const int nchunks = (a.Wn + 15) >> 4;
+    const int cls = a.classes[b];
+    const ChunkCtx x{a,
+                     a.wbank + ((size_t)cls * 2 * a.G16 * a.rgroups + rg) * (RT * 64),
+                     (size_t)a.rgroups * (RT * 64),
+                     (t / a.nb) * kCols,
+                     a.starts[b],
+                     a.G16,
+                     tid,
+                     wave,
+                     lane,
+                     lane & 15,
+                     lane >> 4};
 
     floatx4 acc[RT][kCT];
 #pragma unroll
@@ -154,47 +197,29 @@ __global__ __launch_bounds__(kThreads, (min_blocks<RT, KF>())) void apply_f32_ke
 #pragma unroll
         for (int ct = 0; ct < kCT; ++ct) acc[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
 
+    PilotRegs<KF> pr;
     RawRegs<KF> raw;
-    load_raw<KF>(a, tid, 0, s0, c0, raw);
-    for (int cc = 0; cc < nchunks; ++cc) {
-        // LDS copy is q-major ([g][q][row]) so that the 16 rows a lane group
-        // reads are consecutive 16-byte words (no bank conflicts)
-        for (int i = tid; i < 2 * RT * 64; i += kThreads) {
-            const int gg = i / (RT * 64), rem = i - gg * (RT * 64);
-            const int g = 2 * cc + gg;
-            const int row = rem >> 2, qq = rem & 3;
-            ws4[gg * RT * 64 + qq * RT * 16 + row] =
-                g < a.G8 ? wsrc[(size_t)g * a.Rpad * 4 + rem] : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-        store_ls<KF>(a, tid, cc, s0, raw, xs2);
-        if (cc + 1 < nchunks) load_raw<KF>(a, tid, cc + 1, s0, c0, raw);
-        __syncthreads();
-#pragma unroll
-        for (int gg = 0; gg < 2; ++gg) {
-            float4 xv[kCT];
-#pragma unroll
-            for (int ct = 0; ct < kCT; ++ct)
-                xv[ct] = xs4[((wave * kCT + ct) * 16 + l16) * (kXS / 2) + 4 * gg + q];
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt) {
-                const float4 av = ws4[gg * RT * 64 + q * RT * 16 + rt * 16 + l16];
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int ct = 0; ct < kCT; ++ct)
-                        acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                            f4c(av, i), f4c(xv[ct], i), acc[rt][ct], 0, 0, 0);
-            }
-        }
-        __syncthreads();
+    copy_w<RT>(x.wsrc, x.gstride, 0, wave, lane, wA);
+    if constexpr (KF > 0) {
+        load_pil<KF>(a, x.s0, 0, tid, pr);
+        store_pil<KF>(pr, pl, tid);
+        if (x.nchunks > 1) load_pil<KF>(a, x.s0, 1, tid, pr);
+    }
+    load_raw<KF>(a, tid, 0, x.s0, x.c0, raw);
+    wait_vm();
+    __syncthreads();
+    for (int cc = 0; cc < x.nchunks; cc += 2) {
+        chunk_step<RT, KF>(x, cc, xs4, pl, wA, wB, acc, raw, pr);
+        if (cc + 1 < x.nchunks) chunk_step<RT, KF>(x, cc + 1, xs4, pl, wB, wA, acc, raw, pr);
     }
 
     // lane (l16, q) of tile (rt, ct) holds real rows 16rt + 4q .. +3 of its
     // column: complex outputs o, o+1 of the block
+    const int l16 = x.l16, q = x.q;
     const bool vec = a.vec_store != 0;
 #pragma unroll
     for (int ct = 0; ct < kCT; ++ct) {
-        const long long col = c0 + (wave * kCT + ct) * 16 + l16;
+        const long long col = x.c0 + (wave * kCT + ct) * 16 + l16;
         if (col >= a.ncols) continue;
         float2* op = a.out + col * a.N + (long long)b * a.B;
 #pragma unroll
@@ -233,7 +258,7 @@ hipError_t launch_apply_f32(const Plan& p, int slots, const float2* x, const flo
     a.N = p.d.N;
     a.B = p.d.B;
     a.Wn = p.d.Wn;
-    a.G8 = p.G8;
+    a.G16 = p.G16;
     a.Rpad = p.Rpad;
     a.nb = p.nb;
     a.rgroups = p.rgroups;

@@ -6,19 +6,22 @@
 // product W X is formed as hi_W hi_X + lo_W hi_X + hi_W lo_X with FP32
 // accumulation (lo_W lo_X is dropped).  BF16 has the FP32 exponent range, so
 // its parts are used as they are.  FP16 lo parts are scaled by 2^11 to stay
-// clear of the subnormal range, and the hi_W hi_X product uses the exactly
-// representable 2^11 hi_W, so the accumulator holds 2^11 W X and one scale by
-// 2^-11 at the store undoes it.  FP16 assumes |W| < 32 and |h_ls| < 65504.
+// clear of the subnormal range, and the hi_W hi_X product uses 2^11 hi_W
+// (exact: a power-of-two scaling, formed in registers from hi_W), so the
+// accumulator holds 2^11 W X and one scale by 2^-11 at the store undoes it.
+// FP16 assumes |W| < 32 and |h_ls| < 65504.
 //
 // The structure follows the FP32 kernel (apply_f32.hip): 4 waves x 3 column
 // tiles = 192 columns per workgroup, RT <= 13 16-row tiles of the real
 // embedding, the window streamed in chunks of 16 complex rows (32 reals = the
-// K of one v_mfma_f32_16x16x32_{bf16,f16}), the next chunk's raw inputs
-// loaded into registers before the current chunk's MFMAs.  Lane (i16, kq) of
-// an operand holds reals 8kq..8kq+7 of its row / column (one 16-byte LDS
-// read).  The LS chunk is split once, when it is written to LDS.
+// K of one v_mfma_f32_16x16x32_{bf16,f16}).  Lane (i16, kq) of an operand
+// holds reals 8kq..8kq+7 of its row / column (one 16-byte LDS read).  The LS
+// chunk is split once, when it is written to LDS.  Per chunk the MFMA phase
+// is short (3 RT x 3 products per wave), so the copy of the next chunk's
+// filter parts (global-to-LDS, into the other of two buffers) is issued as
+// soon as the wave has read its LS operands, ahead of all the chunk's MFMAs.
+#include "chunk_io.h"
 #include "dft.h"
-#include "internal.h"
 
 namespace lmmse {
 
@@ -27,9 +30,8 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
 struct SplitArgs {
-    const uint4* p0;       // A part multiplying hi_X: BF16 hi_W, FP16 2^11 hi_W
-    const uint4* p1;       // A part multiplying lo_X: hi_W
-    const uint4* p2;       // A part multiplying hi_X: BF16 lo_W, FP16 2^11 lo_W
+    const float4* whi;     // hi parts of the real embedding (16-byte units of 8 halves)
+    const float4* wlo;     // lo parts (FP16: scaled by 2^11)
     const int* starts;
     const int* classes;
     const float2* x;
@@ -42,13 +44,6 @@ struct SplitArgs {
     float invK;
     float out_scale;
 };
-
-__device__ __forceinline__ long long xcd_remap_s(long long id, long long total) {
-    const long long NX = 8;
-    const long long q = total / NX, r = total % NX;
-    const long long x = id % NX, k = id / NX;
-    return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
-}
 
 template <bool FP16>
 __device__ __forceinline__ void split2(float v, uint16_t& h, uint16_t& l) {
@@ -76,7 +71,7 @@ __device__ __forceinline__ void split_c(float2 v, uint32_t& hi, uint32_t& lo) {
 }
 
 template <bool FP16>
-__device__ __forceinline__ floatx4 mma(const uint4& a, const uint4& b, floatx4 c) {
+__device__ __forceinline__ floatx4 mma(const float4& a, const float4& b, floatx4 c) {
     if constexpr (FP16)
         return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a),
                                                       __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
@@ -85,149 +80,173 @@ __device__ __forceinline__ floatx4 mma(const uint4& a, const uint4& b, floatx4 c
                                                        __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
 
-constexpr int sCT = 3;                     // column tiles per wave
-constexpr int sThreads = 256;              // 4 waves
-constexpr int sCols = 16 * sCT * 4;        // 192
-constexpr int sXS = 20;                    // LDS column stride in uint32 (16 rows + pad)
-
-template <int KF>
-struct SRaw {
-    static constexpr int NPAIR = KF == 0 ? sCols * 16 : (sCols / KF) * 16;
-    static constexpr int TX = (NPAIR + sThreads - 1) / sThreads;
-    static constexpr int KV = KF == 0 ? 1 : KF;
-    float2 v[TX][KV];
-};
-
-template <int KF>
-__device__ __forceinline__ void split_load_raw(const SplitArgs& a, int tid, int cc, int s0,
-                                               long long c0, SRaw<KF>& R) {
-    using CR = SRaw<KF>;
-#pragma unroll
-    for (int u = 0; u < CR::TX; ++u) {
-        const int i = tid + u * sThreads;
-        const int cq = i >> 4, r = i & 15;
-        const int j = cc * 16 + r;
-        if constexpr (KF == 0) {
-            const long long col = c0 + cq;
-            R.v[u][0] = (i < CR::NPAIR && j < a.Wn && col < a.ncols) ? a.x[col * a.N + s0 + j]
-                                                                    : make_float2(0.f, 0.f);
-        } else {
-            const long long ant = c0 / KF + cq;
-            const bool live = i < CR::NPAIR && j < a.Wn && ant < a.ncols / KF;
-            const float2* yp = a.x + ant * KF * (long long)a.N + s0 + j;
-#pragma unroll
-            for (int tt = 0; tt < KF; ++tt)
-                R.v[u][tt] = live ? yp[(long long)tt * a.N] : make_float2(0.f, 0.f);
-        }
-    }
+// 2^11 hi for the FP16 hi_W hi_X product (exact for |hi| < 32).
+__device__ __forceinline__ float4 scale2048_f16(const float4& a) {
+    f16x8 h = __builtin_bit_cast(f16x8, a);
+    h = h * (_Float16)2048.0f;
+    return __builtin_bit_cast(float4, h);
 }
+
+// LS chunk parts in LDS, slot-major: 16-byte slot kq (complex rows
+// 4kq..4kq+3) of column c at kq * kXP + c; complex row r of column c is the
+// 32-bit word 4 (kq kXP + c) + (r & 3).
+__device__ __forceinline__ int xw_at(int c, int r) { return 4 * ((r >> 2) * kXP + c) + (r & 3); }
 
 // LS values of chunk cc, split into hi / lo parts, into LDS.
 template <int KF, bool FP16>
-__device__ __forceinline__ void split_store_ls(const SplitArgs& a, int tid, int cc, int s0,
-                                               const SRaw<KF>& R, uint32_t* xh, uint32_t* xl) {
-    using CR = SRaw<KF>;
+__device__ __forceinline__ void split_store_ls(const SplitArgs& a, int tid, int cc,
+                                               const RawRegs<KF>& R, uint32_t* xh, uint32_t* xl,
+                                               const float2* pl) {
+    using CR = RawRegs<KF>;
 #pragma unroll
     for (int u = 0; u < CR::TX; ++u) {
-        const int i = tid + u * sThreads;
+        const int i = tid + u * kThreads;
         if (i >= CR::NPAIR) continue;
         const int cq = i >> 4, r = i & 15;
         if constexpr (KF == 0) {
             uint32_t h, l;
             split_c<FP16>(R.v[u][0], h, l);
-            xh[cq * sXS + r] = h;
-            xl[cq * sXS + r] = l;
+            xh[xw_at(cq, r)] = h;
+            xl[xw_at(cq, r)] = l;
         } else {
-            const int j = cc * 16 + r;
-            const bool live = j < a.Wn;
-            const int n = live ? s0 + j : 0;
-            const int cb = cq * KF * sXS + r;
+            const bool live = cc * 16 + r < a.Wn;
             float2 z[KF];
             Dft<KF>::run(R.v[u], z, nullptr);
 #pragma unroll
             for (int k = 0; k < KF; ++k) {
-                float2 h = cmulc(z[k], a.pilots[(long long)k * a.N + n]);
+                float2 h = cmulc(z[k], pl[k * 16 + r]);
                 h = live ? make_float2(h.x * a.invK, h.y * a.invK) : make_float2(0.f, 0.f);
                 uint32_t hh, ll;
                 split_c<FP16>(h, hh, ll);
-                xh[cb + k * sXS] = hh;
-                xl[cb + k * sXS] = ll;
+                xh[xw_at(cq * KF + k, r)] = hh;
+                xl[xw_at(cq * KF + k, r)] = ll;
             }
         }
     }
 }
 
+struct SplitCtx {
+    const SplitArgs& a;
+    size_t wofs0;      // bank offset (16-byte units) of chunk 0 of this row group
+    size_t cstride;    // bank offset between consecutive chunks
+    long long c0;
+    int s0, nchunks, tid, wave, lane, l16, kq;
+};
+
+// One chunk: chunk cc+1's pilots (registers) and chunk cc's split LS values
+// into LDS, chunk cc+1's raw inputs into registers, barrier, this wave's LS
+// operands from LDS, then the copy of chunk cc+1's filter parts into wnext
+// and chunk cc+2's pilots into registers, the chunk's MFMAs (reading only
+// wcur, which the compiler can tell from wnext), wait for this wave's loads,
+// barrier.
+template <int RT, int KF, bool FP16>
+__device__ __forceinline__ void split_step(const SplitCtx& x, int cc, float4* xh4, float4* xl4,
+                                           float2* pl, float4* wcur, float4* wnext,
+                                           floatx4 (&acc)[RT][kCT], RawRegs<KF>& raw,
+                                           PilotRegs<KF>& pr) {
+    constexpr int NS = PilotRegs<KF>::NS;
+    if constexpr (KF > 0)
+        if (cc + 1 < x.nchunks) store_pil<KF>(pr, pl + ((cc + 1) & 1) * NS, x.tid);
+    split_store_ls<KF, FP16>(x.a, x.tid, cc, raw, reinterpret_cast<uint32_t*>(xh4),
+                             reinterpret_cast<uint32_t*>(xl4), pl + (cc & 1) * NS);
+    if (cc + 1 < x.nchunks) load_raw<KF>(x.a, x.tid, cc + 1, x.s0, x.c0, raw);
+    __syncthreads();
+    float4 bh[kCT], bl[kCT];
+#pragma unroll
+    for (int ct = 0; ct < kCT; ++ct) {
+        const int c = (x.wave * kCT + ct) * 16 + x.l16;
+        bh[ct] = xh4[x.kq * kXP + c];
+        bl[ct] = xl4[x.kq * kXP + c];
+    }
+    if (cc + 1 < x.nchunks) {
+        const size_t o = x.wofs0 + (size_t)(cc + 1) * x.cstride;
+        dma_copy<RT * 64>(x.a.whi + o, wnext, x.wave, x.lane);
+        dma_copy<RT * 64>(x.a.wlo + o, wnext + RT * 64, x.wave, x.lane);
+        if constexpr (KF > 0)
+            if (cc + 2 < x.nchunks) load_pil<KF>(x.a, x.s0, cc + 2, x.tid, pr);
+    }
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+        const int wi = x.kq * RT * 16 + rt * 16 + x.l16;
+        const float4 ahi = wcur[wi], alo = wcur[RT * 64 + wi];
+        const float4 a0 = FP16 ? scale2048_f16(ahi) : ahi;
+        // three independent column tiles between dependent products
+#pragma unroll
+        for (int ct = 0; ct < kCT; ++ct) acc[rt][ct] = mma<FP16>(a0, bh[ct], acc[rt][ct]);
+#pragma unroll
+        for (int ct = 0; ct < kCT; ++ct) acc[rt][ct] = mma<FP16>(alo, bh[ct], acc[rt][ct]);
+#pragma unroll
+        for (int ct = 0; ct < kCT; ++ct) acc[rt][ct] = mma<FP16>(ahi, bl[ct], acc[rt][ct]);
+    }
+    wait_vm();
+    __syncthreads();
+}
+
 template <int RT, int KF>
 constexpr int split_min_blocks() { return (KF == 24 || (RT >= 13 && KF <= 2)) ? 1 : 2; }
 
-// 4 waves x 3 column tiles, RT <= 13 row tiles; per chunk of 16 window rows:
-// filter parts and split LS values into LDS, barrier, MFMAs, barrier; the
-// raw inputs of the next chunk are loaded into registers before the MFMAs.
+// 4 waves x 3 column tiles, RT <= 13 row tiles.  Two workgroups per CU where
+// the registers allow it (K = 24 and the tallest unfused / K <= 2 variants
+// run one per CU rather than spill).
 template <int RT, int KF, bool FP16>
-__global__ __launch_bounds__(sThreads, (split_min_blocks<RT, KF>())) void apply_split_kernel(SplitArgs a) {
-    __shared__ uint4 xh4[sCols * sXS / 4];
-    __shared__ uint4 xl4[sCols * sXS / 4];
-    __shared__ uint4 w4[3 * RT * 64];          // [part][kq][row]
-    uint32_t* xh = reinterpret_cast<uint32_t*>(xh4);
-    uint32_t* xl = reinterpret_cast<uint32_t*>(xl4);
+__global__ __launch_bounds__(kThreads, (split_min_blocks<RT, KF>())) void apply_split_kernel(
+    SplitArgs a) {
+    constexpr int NS = PilotRegs<KF>::NS;
+    __shared__ float4 xh4[4 * kXP];        // LS chunk, hi parts: [kq][col]
+    __shared__ float4 xl4[4 * kXP];        // lo parts
+    __shared__ float4 wA[2 * RT * 64];     // filter chunks, even / odd: [hi, lo][kq][row]
+    __shared__ float4 wB[2 * RT * 64];
+    __shared__ float2 pl[2 * NS];          // pilot slices of two chunks
 
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l16 = lane & 15, kq = lane >> 4;
-    long long t = xcd_remap_s(blockIdx.x, a.n_tiles);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform per wave
+    long long t = xcd_remap(blockIdx.x, a.n_tiles);
     const int rg = (int)(t % a.rgroups);
     t /= a.rgroups;
     const int b = (int)(t % a.nb);
-    const long long c0 = (t / a.nb) * sCols;
-    const int s0 = a.starts[b], cls = a.classes[b];
-    const size_t wbase = ((size_t)cls * a.G16 * a.Rpad + (size_t)rg * RT * 16) * 4;
-    const int nchunks = a.G16;
+    const int cls = a.classes[b];
+    const SplitCtx x{a,
+                     ((size_t)cls * a.G16 * a.rgroups + rg) * (RT * 64),
+                     (size_t)a.rgroups * (RT * 64),
+                     (t / a.nb) * kCols,
+                     a.starts[b],
+                     a.G16,
+                     tid,
+                     wave,
+                     lane,
+                     lane & 15,
+                     lane >> 4};
 
-    floatx4 acc[RT][sCT];
+    floatx4 acc[RT][kCT];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-        for (int ct = 0; ct < sCT; ++ct) acc[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int ct = 0; ct < kCT; ++ct) acc[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-    SRaw<KF> raw;
-    split_load_raw<KF>(a, tid, 0, s0, c0, raw);
-    for (int cc = 0; cc < nchunks; ++cc) {
-        const size_t wofs = wbase + (size_t)cc * a.Rpad * 4;
-        // q-major LDS copy ([part][kq][row]): conflict-free 16-byte reads
-        for (int i = tid; i < RT * 64; i += sThreads) {
-            const int li = (i & 3) * RT * 16 + (i >> 2);
-            w4[li] = a.p0[wofs + i];
-            w4[RT * 64 + li] = a.p1[wofs + i];
-            w4[2 * RT * 64 + li] = a.p2[wofs + i];
-        }
-        split_store_ls<KF, FP16>(a, tid, cc, s0, raw, xh, xl);
-        if (cc + 1 < nchunks) split_load_raw<KF>(a, tid, cc + 1, s0, c0, raw);
-        __syncthreads();
-        uint4 bh[sCT], bl[sCT];
-#pragma unroll
-        for (int ct = 0; ct < sCT; ++ct) {
-            const int c = (wave * sCT + ct) * 16 + l16;
-            bh[ct] = xh4[c * (sXS / 4) + kq];
-            bl[ct] = xl4[c * (sXS / 4) + kq];
-        }
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt) {
-            const int wi = kq * RT * 16 + rt * 16 + l16;
-            const uint4 a0 = w4[wi], a1 = w4[RT * 64 + wi], a2 = w4[2 * RT * 64 + wi];
-            // three independent column tiles between dependent products
-#pragma unroll
-            for (int ct = 0; ct < sCT; ++ct) acc[rt][ct] = mma<FP16>(a0, bh[ct], acc[rt][ct]);
-#pragma unroll
-            for (int ct = 0; ct < sCT; ++ct) acc[rt][ct] = mma<FP16>(a2, bh[ct], acc[rt][ct]);
-#pragma unroll
-            for (int ct = 0; ct < sCT; ++ct) acc[rt][ct] = mma<FP16>(a1, bl[ct], acc[rt][ct]);
-        }
-        __syncthreads();
+    PilotRegs<KF> pr;
+    RawRegs<KF> raw;
+    dma_copy<RT * 64>(a.whi + x.wofs0, wA, wave, lane);
+    dma_copy<RT * 64>(a.wlo + x.wofs0, wA + RT * 64, wave, lane);
+    if constexpr (KF > 0) {
+        load_pil<KF>(a, x.s0, 0, tid, pr);
+        store_pil<KF>(pr, pl, tid);
+        if (x.nchunks > 1) load_pil<KF>(a, x.s0, 1, tid, pr);
+    }
+    load_raw<KF>(a, tid, 0, x.s0, x.c0, raw);
+    wait_vm();
+    __syncthreads();
+    for (int cc = 0; cc < x.nchunks; cc += 2) {
+        split_step<RT, KF, FP16>(x, cc, xh4, xl4, pl, wA, wB, acc, raw, pr);
+        if (cc + 1 < x.nchunks)
+            split_step<RT, KF, FP16>(x, cc + 1, xh4, xl4, pl, wB, wA, acc, raw, pr);
     }
 
+    const int l16 = x.l16, kq = x.kq;
     const bool vec = a.vec_store != 0;
     const float sc = a.out_scale;
 #pragma unroll
-    for (int ct = 0; ct < sCT; ++ct) {
-        const long long col = c0 + (wave * sCT + ct) * 16 + l16;
+    for (int ct = 0; ct < kCT; ++ct) {
+        const long long col = x.c0 + (wave * kCT + ct) * 16 + l16;
         if (col >= a.ncols) continue;
         float2* op = a.out + col * a.N + (long long)b * a.B;
 #pragma unroll
@@ -251,7 +270,7 @@ __global__ __launch_bounds__(sThreads, (split_min_blocks<RT, KF>())) void apply_
 
 template <bool FP16>
 static hipError_t launch_split_t(const SplitArgs& a, int RT, int kf, hipStream_t st) {
-    const dim3 grid((unsigned)a.n_tiles), block(sThreads);
+    const dim3 grid((unsigned)a.n_tiles), block(kThreads);
 #define LMMSE_AS(R, KK)                                                                  \
     case R:                                                                              \
         hipLaunchKernelGGL((apply_split_kernel<R, KK, FP16>), grid, block, 0, st, a);    \
@@ -278,9 +297,8 @@ hipError_t launch_apply_split(const Plan& p, int slots, const float2* x, const f
                               bool fused, float2* out, hipStream_t st) {
     const bool fp16 = p.d.precision == LMMSE_FP16X3;
     SplitArgs a;
-    a.p0 = reinterpret_cast<const uint4*>(fp16 ? p.whs : p.whi);
-    a.p1 = reinterpret_cast<const uint4*>(p.whi);
-    a.p2 = reinterpret_cast<const uint4*>(p.wlo);
+    a.whi = reinterpret_cast<const float4*>(p.whi);
+    a.wlo = reinterpret_cast<const float4*>(p.wlo);
     a.starts = p.d_starts;
     a.classes = p.d_classes;
     a.x = x;
@@ -297,7 +315,7 @@ hipError_t launch_apply_split(const Plan& p, int slots, const float2* x, const f
     a.invK = 1.0f / (float)p.d.K;
     a.out_scale = fp16 ? 1.0f / 2048.0f : 1.0f;
     a.vec_store = (((a.N | a.B) & 1) == 0 && ((uintptr_t)out & 15) == 0) ? 1 : 0;
-    const long long ctiles = (a.ncols + sCols - 1) / sCols;
+    const long long ctiles = (a.ncols + kCols - 1) / kCols;
     a.n_tiles = ctiles * p.nb * p.rgroups;
     if (a.n_tiles == 0) return hipSuccess;
     const int kf = fused ? p.d.K : 0;

@@ -173,16 +173,20 @@ __device__ __forceinline__ double wreal(const double2* w, int B, int Wn, int r, 
 }
 
 __global__ void pack_f32_kernel(const double2* __restrict__ w64, float4* __restrict__ bank,
-                                int n_classes, int B, int Wn, int G8, int Rpad) {
+                                int n_classes, int B, int Wn, int ngroups, int RT, int rgroups) {
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long total = (long long)n_classes * G8 * Rpad * 4;
+    const int rows = RT * 16;
+    const long long total = (long long)n_classes * ngroups * rgroups * 4 * rows;
     if (idx >= total) return;
-    const int q = (int)(idx & 3);
-    long long t = idx >> 2;
-    const int r = (int)(t % Rpad);
-    t /= Rpad;
-    const int g = (int)(t % G8);
-    const int c = (int)(t / G8);
+    const int rr = (int)(idx % rows);
+    long long t = idx / rows;
+    const int q = (int)(t & 3);
+    t >>= 2;
+    const int rg = (int)(t % rgroups);
+    t /= rgroups;
+    const int g = (int)(t % ngroups);
+    const int c = (int)(t / ngroups);
+    const int r = rg * rows + rr;
     const double2* w = w64 + (long long)c * B * Wn;
     const int k0 = 16 * g + 4 * q;
     bank[idx] = make_float4((float)wreal(w, B, Wn, r, k0), (float)wreal(w, B, Wn, r, k0 + 1),
@@ -198,28 +202,31 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 // Split parts of the real embedding: hi = round(x), lo = round(x - hi) in
-// BF16; FP16 stores lo = round(2^11 (x - hi)) and hs = 2^11 hi (exact).
+// BF16; FP16 stores lo = round(2^11 (x - hi)).
 __global__ void pack_split_kernel(const double2* __restrict__ w64, uint16_t* __restrict__ hi,
-                                  uint16_t* __restrict__ lo, uint16_t* __restrict__ hs,
-                                  int n_classes, int B, int Wn, int G16, int Rpad, int is_fp16) {
+                                  uint16_t* __restrict__ lo, int n_classes, int B, int Wn, int G16, int RT, int rgroups,
+                                  int is_fp16) {
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long total = (long long)n_classes * G16 * Rpad * 32;
+    const int rows = RT * 16;
+    const long long total = (long long)n_classes * G16 * rgroups * 4 * rows * 8;
     if (idx >= total) return;
     const int e = (int)(idx & 7);
-    const int kq = (int)((idx >> 3) & 3);
-    long long t = idx >> 5;
-    const int r = (int)(t % Rpad);
-    t /= Rpad;
+    long long t = idx >> 3;
+    const int rr = (int)(t % rows);
+    t /= rows;
+    const int kq = (int)(t & 3);
+    t >>= 2;
+    const int rg = (int)(t % rgroups);
+    t /= rgroups;
     const int g = (int)(t % G16);
     const int c = (int)(t / G16);
+    const int r = rg * rows + rr;
     const double x = wreal(w64 + (long long)c * B * Wn, B, Wn, r, 32 * g + 8 * kq + e);
     if (is_fp16) {
         const _Float16 h = (_Float16)x;
         const _Float16 l = (_Float16)((x - (double)h) * 2048.0);
-        const _Float16 s = (_Float16)((double)h * 2048.0);
         hi[idx] = __builtin_bit_cast(uint16_t, h);
         lo[idx] = __builtin_bit_cast(uint16_t, l);
-        hs[idx] = __builtin_bit_cast(uint16_t, s);
     } else {
         const uint16_t h = f32_to_bf16((float)x);
         const uint16_t l = f32_to_bf16((float)(x - (double)bf16_to_f32(h)));
@@ -231,15 +238,15 @@ __global__ void pack_split_kernel(const double2* __restrict__ w64, uint16_t* __r
 hipError_t launch_pack_banks(Plan& p, hipStream_t st) {
     const int B = p.d.B, Wn = p.d.Wn;
     {
-        const long long total = (long long)p.n_classes * p.G8 * p.Rpad * 4;
+        const long long total = (long long)fixed_bank_f32_elems(p);
         hipLaunchKernelGGL(pack_f32_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
-                           p.w64, p.wf32, p.n_classes, B, Wn, p.G8, p.Rpad);
+                           p.w64, p.wf32, p.n_classes, B, Wn, 2 * p.G16, p.RT, p.rgroups);
     }
     if (p.whi) {
-        const long long total = (long long)p.n_classes * p.G16 * p.Rpad * 32;
+        const long long total = (long long)split_bank_elems(p);
         hipLaunchKernelGGL(pack_split_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
-                           st, p.w64, p.whi, p.wlo, p.whs, p.n_classes, B, Wn, p.G16, p.Rpad,
-                           p.d.precision == LMMSE_FP16X3 ? 1 : 0);
+                           st, p.w64, p.whi, p.wlo, p.n_classes, B, Wn, p.G16, p.RT,
+                           p.rgroups, p.d.precision == LMMSE_FP16X3 ? 1 : 0);
     }
     return hipGetLastError();
 }

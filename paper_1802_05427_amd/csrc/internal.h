@@ -11,16 +11,19 @@
 
 namespace lmmse {
 
-// Sizes of the filter layouts the GEMM kernels read.
-//  * FP32 "A-ready" bank: for each class, groups g of 8 complex window rows
-//    (16 reals), rows r of the real embedding padded to Rpad = 16*ceil(2B/16),
-//    4 lanes q, 4 floats:  bank[((c*G8 + g)*Rpad + r)*4 + q] (float4) holds
-//    Wr[r][16g + 4q + i], i = 0..3, where Wr is the 2B x 2Wn real embedding
-//    of the complex filter (rows 2a, 2a+1 = Re, Im of output a; columns
-//    2j, 2j+1 = Re, Im of input j).
-//  * split bank: for each class, groups of 16 complex rows (32 reals), rows
-//    r < Rpad, 4 lanes kq, 8 halves:  hi/lo[(((c*G16 + g)*Rpad + r)*4 + kq)*8 + e]
-//    holds the parts of Wr[r][32g + 8kq + e].
+// Filter layouts the GEMM kernels read.  Wr is the 2B x 2Wn real embedding
+// of a complex filter (rows 2a, 2a+1 = Re, Im of output a; columns 2j, 2j+1 =
+// Re, Im of input j); its rows are padded to Rpad = RT*16*rgroups and split
+// into rgroups row groups of RT*16 rows (one per workgroup).  Both banks are
+// stored in the order a workgroup holds them in LDS, so that one chunk of one
+// row group is a contiguous run:
+//  * FP32 bank, groups g < 2*G16 of 8 complex window rows (16 reals), 4 lanes
+//    q, rows rr of the row group:  bank[(((c*2*G16 + g)*rgroups + rg)*4 + q)
+//    *RT*16 + rr] (float4) holds Wr[rg*RT*16 + rr][16g + 4q + i], i = 0..3.
+//  * split banks, groups g < G16 of 16 complex rows (32 reals), 4 lanes kq:
+//    part[((((c*G16 + g)*rgroups + rg)*4 + kq)*RT*16 + rr)*8 + e] holds the
+//    part of Wr[rg*RT*16 + rr][32g + 8kq + e].
+// Window rows past Wn and rows past 2B are zero.
 struct Plan {
     lmmse_plan_desc d{};
     int device = 0;
@@ -43,7 +46,6 @@ struct Plan {
     float4* wf32 = nullptr;      // FP32 bank
     uint16_t* whi = nullptr;     // split bank, hi part
     uint16_t* wlo = nullptr;     // split bank, lo part (FP16: scaled by 2^11)
-    uint16_t* whs = nullptr;     // FP16 only: 2^11 * hi part
     float2* twiddle = nullptr;   // [K] exp(+j 2 pi r / K)
     int* status = nullptr;       // [2] device status word: code, info
     double* dscal = nullptr;     // [4] device scratch for the design backward

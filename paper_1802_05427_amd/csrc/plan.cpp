@@ -107,7 +107,7 @@ int dev_alloc(T*& p, size_t count) {
 void free_plan(lmmse_plan* p) {
     if (!p) return;
     void* ptrs[] = {p->d_starts, p->d_classes, p->d_offsets, p->d_class_off, p->w64, p->ainv, p->rd,
-                    p->wf32,     p->whi,       p->wlo,         p->whs,     p->twiddle, p->status,
+                    p->wf32,     p->whi,       p->wlo,         p->twiddle, p->status,
                     p->dscal};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
@@ -133,7 +133,7 @@ size_t hls_bytes(const lmmse_plan_desc& d, int slots) {
 
 namespace lmmse {
 
-size_t fixed_bank_f32_elems(const Plan& p) { return (size_t)p.n_classes * p.G8 * p.Rpad * 4; }
+size_t fixed_bank_f32_elems(const Plan& p) { return (size_t)p.n_classes * 2 * p.G16 * p.Rpad * 4; }
 size_t split_bank_elems(const Plan& p) { return (size_t)p.n_classes * p.G16 * p.Rpad * 32; }
 
 }  // namespace lmmse
@@ -235,8 +235,6 @@ int lmmse_plan_create(const lmmse_plan_desc* desc, lmmse_plan_t* out) {
         if (desc->precision != LMMSE_FP32 &&
             ((rc = dev_alloc(p->whi, split_bank_elems(*p))) ||
              (rc = dev_alloc(p->wlo, split_bank_elems(*p)))))
-            return fail(rc);
-        if (desc->precision == LMMSE_FP16X3 && (rc = dev_alloc(p->whs, split_bank_elems(*p))))
             return fail(rc);
     }
     std::vector<float2> tw(K);
