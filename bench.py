@@ -47,19 +47,26 @@ def parse():
     return ap.parse_args()
 
 
-def src_digest() -> str:
-    """Hash of the sources of the dominant kernel (to match stored counters)."""
+KERNEL_SOURCES = {
+    "fp32": ("apply_f32.hip", "chunk_io.h", "dft.h", "internal.h"),
+    "split": ("apply_split.hip", "chunk_io.h", "dft.h", "internal.h"),
+}
+
+
+def src_digest(family: str) -> str:
+    """Hash of the sources of a filtering kernel (to match stored counters)."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("apply_f32.hip", "dft.h", "internal.h"):
+    for f in KERNEL_SOURCES[family]:
         with open(os.path.join(ROOT, "paper_1802_05427_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def stored_traffic(kernel: str, coeffs: int):
-    """HBM bytes per launch from committed rocprofv3 counters, if they were
-    taken on the current kernel source; else None."""
+def stored_traffic(kernel: str, family: str, coeffs: int):
+    """HBM bytes per launch from committed rocprofv3 counters (FETCH_SIZE and
+    WRITE_SIZE, each scaled by what the counter reads for a plain device copy
+    of known size), if they were taken on the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
@@ -67,7 +74,7 @@ def stored_traffic(kernel: str, coeffs: int):
     except (OSError, ValueError):
         return None
     e = rec.get(kernel)
-    if not e or e.get("src_digest") != src_digest() or e.get("coeffs") != coeffs:
+    if not e or e.get("src_digest") != src_digest(family) or e.get("coeffs") != coeffs:
         return None
     return e.get("hbm_bytes_per_launch")
 
@@ -181,15 +188,19 @@ def main():
     disc = O.discrepancy_db(out_u[:1], ref)
     nmse_gpu = O.nmse_db(out_u, sb.H)
 
+    # roofline of the one kernel a step launches, from the mean event time
     flops_per_coef = 8.0 * Wn   # complex B x Wn filter per block: 8*B*Wn flops per column per block
     kernel_flops = flops_per_coef * coeffs
-    achieved = kernel_flops / (ms_med * 1e-3) / 1e12
+    achieved = kernel_flops / (ms * 1e-3) / 1e12
     peak = {"fp32": PEAK["fp32_mfma_TFs"], "bf16x3": PEAK["bf16_mfma_TFs"] / 3,
             "fp16x3": PEAK["fp16_mfma_TFs"] / 3}[args.precision]
     bytes_per_coef = 16.0
-    gbs = bytes_per_coef * coeffs / (ms_med * 1e-3) / 1e9
-    kname = "apply_f32_kernel<13, 12>" if args.precision == "fp32" else f"apply_split_kernel<13, 12, {args.precision}>"
-    traffic = stored_traffic(kname, coeffs) if (args.rsource == "exp" and B == 100 and Wn == 150) else None
+    gbs = bytes_per_coef * coeffs / (ms * 1e-3) / 1e9
+    family = "fp32" if args.precision == "fp32" else "split"
+    kname = ("apply_f32_kernel<13, 12>" if args.precision == "fp32"
+             else f"apply_split_kernel<13, 12, {args.precision}>")
+    traffic = (stored_traffic(kname, family, coeffs)
+               if (args.rsource == "exp" and B == 100 and Wn == 150) else None)
     if args.precision == "fp32":
         roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": traffic}
@@ -284,6 +295,7 @@ def main():
         "nmse_gap_db": gap,
         "discrepancy_db": round(disc, 1),
         "nmse_db": round(nmse_gpu, 3),
+        "kernel_ms_mean": round(ms, 5),
         "kernel_ms_median": round(ms_med, 5),
         "design_ms": design_ms,
         "roofline": roof,

@@ -116,12 +116,16 @@ __device__ __forceinline__ void copy_w(const float4* wsrc, size_t gstride, int c
 }
 
 // Per-workgroup constants of the filtering loop.
+// Odd blocks stream their window backwards (rev): the halo a block shares
+// with each neighbour is then read by both at about the same time, while it
+// is still in L2.
 struct ChunkCtx {
     const ApplyArgs& a;
     const float4* wsrc;
     size_t gstride;
     long long c0;
-    int s0, nchunks, tid, wave, lane, l16, q;
+    int s0, nchunks, rev, tid, wave, lane, l16, q;
+    __device__ int ch(int step) const { return rev ? nchunks - 1 - step : step; }
 };
 
 // One chunk: chunk cc+1's pilots (held in registers) and chunk cc's LS values
@@ -140,20 +144,20 @@ __device__ __forceinline__ void chunk_step(const ChunkCtx& x, int cc, float4* xs
     constexpr int NS = PilotRegs<KF>::NS;
     if constexpr (KF > 0)
         if (cc + 1 < x.nchunks) store_pil<KF>(pr, pl + ((cc + 1) & 1) * NS, x.tid);
-    store_ls<KF>(x.a, x.tid, cc, raw, reinterpret_cast<float2*>(xs4), pl + (cc & 1) * NS);
-    if (cc + 1 < x.nchunks) load_raw<KF>(x.a, x.tid, cc + 1, x.s0, x.c0, raw);
+    store_ls<KF>(x.a, x.tid, x.ch(cc), raw, reinterpret_cast<float2*>(xs4), pl + (cc & 1) * NS);
+    if (cc + 1 < x.nchunks) load_raw<KF>(x.a, x.tid, x.ch(cc + 1), x.s0, x.c0, raw);
     __syncthreads();
     float4 xv[kCT];
     load_xv(xv, xs4, 0, x.wave, x.l16, x.q);
     mfma_group<RT>(acc, xv, wcur, 0, x.l16, x.q);
     load_xv(xv, xs4, 1, x.wave, x.l16, x.q);
     if (cc + 1 < x.nchunks) {
-        copy_w<RT>(x.wsrc, x.gstride, cc + 1, x.wave, x.lane, wnext);
+        copy_w<RT>(x.wsrc, x.gstride, x.ch(cc + 1), x.wave, x.lane, wnext);
         if constexpr (KF > 0)
-            if (cc + 2 < x.nchunks) load_pil<KF>(x.a, x.s0, cc + 2, x.tid, pr);
+            if (cc + 2 < x.nchunks) load_pil<KF>(x.a, x.s0, x.ch(cc + 2), x.tid, pr);
     }
     // the second group of the last chunk may lie wholly past the window
-    if (16 * cc + 8 < x.a.Wn) mfma_group<RT>(acc, xv, wcur, 1, x.l16, x.q);
+    if (16 * x.ch(cc) + 8 < x.a.Wn) mfma_group<RT>(acc, xv, wcur, 1, x.l16, x.q);
     wait_vm();
     __syncthreads();
 }
@@ -185,6 +189,7 @@ __global__ __launch_bounds__(kThreads, (min_blocks<RT, KF>())) void apply_f32_ke
                      (t / a.nb) * kCols,
                      a.starts[b],
                      a.G16,
+                     b & 1,
                      tid,
                      wave,
                      lane,
@@ -199,13 +204,13 @@ __global__ __launch_bounds__(kThreads, (min_blocks<RT, KF>())) void apply_f32_ke
 
     PilotRegs<KF> pr;
     RawRegs<KF> raw;
-    copy_w<RT>(x.wsrc, x.gstride, 0, wave, lane, wA);
+    copy_w<RT>(x.wsrc, x.gstride, x.ch(0), wave, lane, wA);
     if constexpr (KF > 0) {
-        load_pil<KF>(a, x.s0, 0, tid, pr);
+        load_pil<KF>(a, x.s0, x.ch(0), tid, pr);
         store_pil<KF>(pr, pl, tid);
-        if (x.nchunks > 1) load_pil<KF>(a, x.s0, 1, tid, pr);
+        if (x.nchunks > 1) load_pil<KF>(a, x.s0, x.ch(1), tid, pr);
     }
-    load_raw<KF>(a, tid, 0, x.s0, x.c0, raw);
+    load_raw<KF>(a, tid, x.ch(0), x.s0, x.c0, raw);
     wait_vm();
     __syncthreads();
     for (int cc = 0; cc < x.nchunks; cc += 2) {

@@ -125,12 +125,15 @@ __device__ __forceinline__ void split_store_ls(const SplitArgs& a, int tid, int 
     }
 }
 
+// Odd blocks stream their window backwards (rev), so that neighbouring
+// blocks read the halo they share at about the same time, while it is in L2.
 struct SplitCtx {
     const SplitArgs& a;
     size_t wofs0;      // bank offset (16-byte units) of chunk 0 of this row group
     size_t cstride;    // bank offset between consecutive chunks
     long long c0;
-    int s0, nchunks, tid, wave, lane, l16, kq;
+    int s0, nchunks, rev, tid, wave, lane, l16, kq;
+    __device__ int ch(int step) const { return rev ? nchunks - 1 - step : step; }
 };
 
 // One chunk: chunk cc+1's pilots (registers) and chunk cc's split LS values
@@ -147,9 +150,9 @@ __device__ __forceinline__ void split_step(const SplitCtx& x, int cc, float4* xh
     constexpr int NS = PilotRegs<KF>::NS;
     if constexpr (KF > 0)
         if (cc + 1 < x.nchunks) store_pil<KF>(pr, pl + ((cc + 1) & 1) * NS, x.tid);
-    split_store_ls<KF, FP16>(x.a, x.tid, cc, raw, reinterpret_cast<uint32_t*>(xh4),
+    split_store_ls<KF, FP16>(x.a, x.tid, x.ch(cc), raw, reinterpret_cast<uint32_t*>(xh4),
                              reinterpret_cast<uint32_t*>(xl4), pl + (cc & 1) * NS);
-    if (cc + 1 < x.nchunks) load_raw<KF>(x.a, x.tid, cc + 1, x.s0, x.c0, raw);
+    if (cc + 1 < x.nchunks) load_raw<KF>(x.a, x.tid, x.ch(cc + 1), x.s0, x.c0, raw);
     __syncthreads();
     float4 bh[kCT], bl[kCT];
 #pragma unroll
@@ -159,11 +162,11 @@ __device__ __forceinline__ void split_step(const SplitCtx& x, int cc, float4* xh
         bl[ct] = xl4[x.kq * kXP + c];
     }
     if (cc + 1 < x.nchunks) {
-        const size_t o = x.wofs0 + (size_t)(cc + 1) * x.cstride;
+        const size_t o = x.wofs0 + (size_t)x.ch(cc + 1) * x.cstride;
         dma_copy<RT * 64>(x.a.whi + o, wnext, x.wave, x.lane);
         dma_copy<RT * 64>(x.a.wlo + o, wnext + RT * 64, x.wave, x.lane);
         if constexpr (KF > 0)
-            if (cc + 2 < x.nchunks) load_pil<KF>(x.a, x.s0, cc + 2, x.tid, pr);
+            if (cc + 2 < x.nchunks) load_pil<KF>(x.a, x.s0, x.ch(cc + 2), x.tid, pr);
     }
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
@@ -211,6 +214,7 @@ __global__ __launch_bounds__(kThreads, (split_min_blocks<RT, KF>())) void apply_
                      (t / a.nb) * kCols,
                      a.starts[b],
                      a.G16,
+                     b & 1,
                      tid,
                      wave,
                      lane,
@@ -225,14 +229,15 @@ __global__ __launch_bounds__(kThreads, (split_min_blocks<RT, KF>())) void apply_
 
     PilotRegs<KF> pr;
     RawRegs<KF> raw;
-    dma_copy<RT * 64>(a.whi + x.wofs0, wA, wave, lane);
-    dma_copy<RT * 64>(a.wlo + x.wofs0, wA + RT * 64, wave, lane);
+    const size_t o0 = x.wofs0 + (size_t)x.ch(0) * x.cstride;
+    dma_copy<RT * 64>(a.whi + o0, wA, wave, lane);
+    dma_copy<RT * 64>(a.wlo + o0, wA + RT * 64, wave, lane);
     if constexpr (KF > 0) {
-        load_pil<KF>(a, x.s0, 0, tid, pr);
+        load_pil<KF>(a, x.s0, x.ch(0), tid, pr);
         store_pil<KF>(pr, pl, tid);
-        if (x.nchunks > 1) load_pil<KF>(a, x.s0, 1, tid, pr);
+        if (x.nchunks > 1) load_pil<KF>(a, x.s0, x.ch(1), tid, pr);
     }
-    load_raw<KF>(a, tid, 0, x.s0, x.c0, raw);
+    load_raw<KF>(a, tid, x.ch(0), x.s0, x.c0, raw);
     wait_vm();
     __syncthreads();
     for (int cc = 0; cc < x.nchunks; cc += 2) {
