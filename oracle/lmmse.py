@@ -99,7 +99,11 @@ def toeplitz_from_r(r_of_d, rows, cols) -> np.ndarray:
     rows = np.asarray(rows)
     cols = np.asarray(cols)
     d = rows[:, None] - cols[None, :]
-    return np.asarray(r_of_d(d), dtype=C128)
+    # r is evaluated once per distinct difference (the same values as
+    # evaluating it entry by entry)
+    d0 = int(d.min()) if d.size else 0
+    vals = np.asarray(r_of_d(np.arange(d0, int(d.max()) + 1 if d.size else 0)), dtype=C128)
+    return vals[d - d0]
 
 
 def sample_covariance(x: np.ndarray) -> np.ndarray:
