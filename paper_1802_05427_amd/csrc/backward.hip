@@ -17,11 +17,15 @@
 // disjoint (block b in pass b mod P), each adding its contribution with a
 // read-add-write: deterministic, no atomics.
 //
-// dW: split over column chunks.  A workgroup (4 waves) takes one block and one
-// chunk of columns, stages 32 columns of G_b and X_b at a time in LDS and
-// accumulates G X^H on the FP32 matrix cores (A operand: the real embedding of
-// G^T built from LDS, B operand: X interleaved); its FP32 partial is written
-// out and the partials are summed per class in FP64 in a fixed order.
+// dW: split over column chunks.  A workgroup takes one block, one row group of
+// its 2B real output rows and one chunk of columns; wave w owns window columns
+// [16w, 16w+16) of dW_b and all row tiles of the group.  16 LS columns at a
+// time, G_b and X_b are staged in LDS transposed (column index fastest), so
+// that each MFMA operand is one 16-byte read: A is the real embedding of G
+// built in registers, B is X interleaved, contracted over (column, re/im).
+// The next 16 columns are loaded into registers before the MFMAs of the
+// current ones.  Each workgroup writes its FP32 partial; the partials are
+// summed per class in FP64 in a fixed order.
 #include <algorithm>
 
 #include "internal.h"
@@ -45,11 +49,16 @@ struct BwGeom {
     int RT, rgroups, Rpad;   // row tiles over the 2Wn real rows of W^H
     int G8b;                 // groups of 8 complex block outputs (contraction)
     int P;                   // passes with disjoint windows
+    int dwRT, dwRG;          // dW: row tiles per workgroup, row groups
     int nch;                 // column chunks of the dW reduction
+    long long cpw;           // columns per chunk (multiple of 16)
 };
 
 constexpr int kBwRTs[] = {1, 2, 4, 5, 8, 10};
-constexpr int kChunkCols = 1536;     // columns per dW workgroup
+constexpr int kDwMaxRT = 7;           // dW row tiles per workgroup (2B real rows in row groups):
+                                      // <= 96 registers, 5 waves per SIMD
+constexpr int kDwMaxWaves = 16;       // one wave per 16 window columns: Wn <= 256
+constexpr int kDwSlots = 512;         // workgroups resident at once (2 per CU)
 
 static BwGeom bw_geom(const lmmse_plan_desc& d, const std::vector<int>& starts, long long ncols) {
     BwGeom g{};
@@ -75,7 +84,15 @@ static BwGeom bw_geom(const lmmse_plan_desc& d, const std::vector<int>& starts, 
             if (starts[b + g.P] < starts[b] + d.Wn) clash = true;
         if (clash) ++g.P;
     }
-    g.nch = (int)((ncols + kChunkCols - 1) / kChunkCols);
+    const int tw = (2 * d.B + 15) / 16;
+    g.dwRG = (tw + kDwMaxRT - 1) / kDwMaxRT;
+    g.dwRT = (tw + g.dwRG - 1) / g.dwRG;
+    // one resident wave of workgroups; at least 16 columns per chunk
+    const long long steps = (ncols + 15) / 16;
+    const long long want = std::max(1, kDwSlots / (nb * g.dwRG));
+    g.nch = (int)std::max(1LL, std::min(want, steps));
+    g.cpw = 16 * ((steps + g.nch - 1) / g.nch);
+    g.nch = (int)((ncols + g.cpw - 1) / g.cpw);
     return g;
 }
 
@@ -198,84 +215,109 @@ struct DwArgs {
     const float2* g;
     const float2* x;
     float2* part;        // [nb][nch][B][Wn]
-    long long ncols;
-    int N, B, Wn, nb, nch;
+    long long ncols, cpw;
+    int N, B, Wn, nb, nch, rgroups;
 };
 
-constexpr int kDwCols = 32;   // columns staged per step (4 groups of 8)
+constexpr int kDwS = 18;   // LDS row stride (float2) of the transposed tiles: 16 columns + pad
 
 template <int RT>
-__global__ __launch_bounds__(256) void dw_kernel(DwArgs a) {
-    constexpr int CTW = 3;                       // column tiles (of Wn) per wave
-    __shared__ float2 gs[kDwCols][RT * 8 + 1];   // G_b chunk: [col][output o]
-    __shared__ float2 xs[kDwCols][CTW * 4 * 16 + 1];   // X_b chunk: [col][window j]
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l16 = lane & 15, q = lane >> 4;
-    const int b = (int)(blockIdx.x % a.nb);
-    const int ch = (int)(blockIdx.x / a.nb);
+__global__ __launch_bounds__(64 * kDwMaxWaves) __attribute__((amdgpu_waves_per_eu(5)))
+void dw_kernel(DwArgs a) {
+    constexpr int NO = RT * 8;                     // complex output rows of the group
+    __shared__ float2 gT[NO * kDwS];               // G: [o][col]
+    __shared__ float2 xT[16 * kDwMaxWaves * kDwS]; // X: [j][col]
+    const int nthr = blockDim.x;
+    const int tid = threadIdx.x, lane = tid & 63, l16 = lane & 15, q = lane >> 4;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    long long t = blockIdx.x;
+    const int rg = (int)(t % a.rgroups);
+    t /= a.rgroups;
+    const int b = (int)(t % a.nb);
+    const int ch = (int)(t / a.nb);
     const int s0 = a.starts[b];
-    const long long col_lo = (long long)ch * kChunkCols;
-    const long long col_hi = min(col_lo + kChunkCols, a.ncols);
-    floatx4 acc[RT][CTW];
+    const int o0 = rg * NO;                        // first output row of the group
+    const long long col_lo = (long long)ch * a.cpw;
+    const long long col_hi = min(col_lo + a.cpw, a.ncols);
+    const int nsteps = (int)((col_hi - col_lo + 15) / 16);
+    // Staging: the 16 x NO tile of G and the 16 x Wn tile of X are cut into
+    // runs of 16 consecutive rows of one column (128 contiguous bytes); lane
+    // group gi = tid / 16 of the workgroup takes runs gi, gi + nthr/16, ...,
+    // lane r = tid % 16 row r of each.  The workgroup has 4W lane groups
+    // (W = ceil(Wn/16) waves) and X has 16W runs; G has 16 ceil(RT/2) runs
+    // with RT <= ceil(2B/16) <= ceil(Wn/8) <= 2W (B <= Wn), so at most 16W
+    // too: 4 runs of each per lane group.
+    constexpr int kPG = 4, kPX = 4;
+    const int gi = tid >> 4, r16 = tid & 15, ngrp = nthr >> 4;
+    const int gruns = 16 * ((NO + 15) / 16), xruns = 16 * ((a.Wn + 15) / 16);
+    float2 rgv[kPG], rxv[kPX];
+    auto load = [&](int st) {
+        const long long cb = col_lo + 16LL * st;
+        const float2* gb = a.g + cb * a.N + (long long)b * a.B + o0;   // uniform
+        const float2* xb = a.x + cb * a.N + s0;
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
+        for (int u = 0; u < kPG; ++u) {
+            const int pr = gi + u * ngrp, c = pr & 15, o = (pr >> 4) * 16 + r16;
+            rgv[u] = (pr < gruns && o < NO && o0 + o < a.B && cb + c < col_hi)
+                         ? gb[(unsigned)(c * a.N + o)] : make_float2(0.f, 0.f);
+        }
 #pragma unroll
-        for (int ct = 0; ct < CTW; ++ct) acc[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
-    const int jw = CTW * 4 * 16;   // window columns covered by the workgroup (>= Wn)
-    for (long long cb = col_lo; cb < col_hi; cb += kDwCols) {
-        for (int e = tid; e < kDwCols * RT * 8; e += 256) {
-            const int c = e / (RT * 8), o = e % (RT * 8);
-            const long long col = cb + c;
-            gs[c][o] = (col < col_hi && o < a.B) ? a.g[col * a.N + (long long)b * a.B + o]
-                                                 : make_float2(0.f, 0.f);
+        for (int u = 0; u < kPX; ++u) {
+            const int pr = gi + u * ngrp, c = pr & 15, j = (pr >> 4) * 16 + r16;
+            rxv[u] = (pr < xruns && j < a.Wn && cb + c < col_hi)
+                         ? xb[(unsigned)(c * a.N + j)] : make_float2(0.f, 0.f);
         }
-        for (int e = tid; e < kDwCols * jw; e += 256) {
-            const int c = e / jw, j = e % jw;
-            const long long col = cb + c;
-            xs[c][j] = (col < col_hi && j < a.Wn) ? a.x[col * a.N + s0 + j] : make_float2(0.f, 0.f);
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int u = 0; u < kPG; ++u) {
+            const int pr = gi + u * ngrp, c = pr & 15, o = (pr >> 4) * 16 + r16;
+            if (pr < gruns && o < NO) gT[o * kDwS + c] = rgv[u];
         }
+#pragma unroll
+        for (int u = 0; u < kPX; ++u) {
+            const int pr = gi + u * ngrp, c = pr & 15, j = (pr >> 4) * 16 + r16;
+            if (pr < xruns) xT[j * kDwS + c] = rxv[u];
+        }
+    };
+
+    floatx4 acc[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) acc[rt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    // window columns past Wn stay zero in xT: clear them once
+    for (int e = tid; e < 16 * kDwMaxWaves * kDwS; e += nthr) xT[e] = make_float2(0.f, 0.f);
+    __syncthreads();
+    const int jcol = wave * 16 + l16;   // this lane's window column (B operand)
+    load(0);
+    for (int st = 0; st < nsteps; ++st) {
+        store();
         __syncthreads();
+        if (st + 1 < nsteps) load(st + 1);
 #pragma unroll
-        for (int gg = 0; gg < kDwCols / 8; ++gg) {
-            const int c = 8 * gg + 2 * q;   // this lane's two columns
-            float4 av[RT], xv[CTW];
+        for (int kg = 0; kg < 2; ++kg) {   // 8 columns = 16 reals = 4 k-steps each
+            const int c = 8 * kg + 2 * q;  // this lane's two columns
+            const float4 xv = *reinterpret_cast<const float4*>(&xT[jcol * kDwS + c]);
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt) {
                 const int r = rt * 16 + l16;
-                const int o = r >> 1;
-                const float2 g0 = gs[c][o], g1 = gs[c + 1][o];
-                // row 2o: (gr, gi) per column; row 2o+1: (gi, -gr)
-                av[rt] = (r & 1) == 0 ? make_float4(g0.x, g0.y, g1.x, g1.y)
-                                      : make_float4(g0.y, -g0.x, g1.y, -g1.x);
+                const float4 gv = *reinterpret_cast<const float4*>(&gT[(r >> 1) * kDwS + c]);
+                // real row 2o: (gr, gi) per column; row 2o+1: (gi, -gr)
+                const float4 av = (r & 1) == 0 ? gv : make_float4(gv.y, -gv.x, gv.w, -gv.z);
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    acc[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(bq(av, i), bq(xv, i), acc[rt], 0, 0, 0);
             }
-#pragma unroll
-            for (int ct = 0; ct < CTW; ++ct) {
-                const int j = (wave * CTW + ct) * 16 + l16;
-                const float2 x0 = xs[c][j], x1 = xs[c + 1][j];
-                xv[ct] = make_float4(x0.x, x0.y, x1.x, x1.y);
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-                    for (int ct = 0; ct < CTW; ++ct)
-                        acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(bq(av[rt], i), bq(xv[ct], i),
-                                                                           acc[rt][ct], 0, 0, 0);
         }
         __syncthreads();
     }
+    if (jcol >= a.Wn) return;
     float2* pp = a.part + ((long long)b * a.nch + ch) * a.B * (long long)a.Wn;
 #pragma unroll
-    for (int ct = 0; ct < CTW; ++ct) {
-        const int j = (wave * CTW + ct) * 16 + l16;
-        if (j >= a.Wn) continue;
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt) {
-            const int o = (rt * 16 + 4 * q) >> 1;
-            const floatx4 v = acc[rt][ct];
-            if (o < a.B) pp[(long long)o * a.Wn + j] = make_float2(v[0], v[1]);
-            if (o + 1 < a.B) pp[(long long)(o + 1) * a.Wn + j] = make_float2(v[2], v[3]);
-        }
+    for (int rt = 0; rt < RT; ++rt) {
+        const int o = o0 + ((rt * 16 + 4 * q) >> 1);
+        const floatx4 v = acc[rt];
+        if (o < a.B) pp[(long long)o * a.Wn + jcol] = make_float2(v[0], v[1]);
+        if (o + 1 < a.B) pp[(long long)(o + 1) * a.Wn + jcol] = make_float2(v[2], v[3]);
     }
 }
 
@@ -498,28 +540,30 @@ hipError_t launch_backward_fixed(Plan& p, int slots, const float2* hls, const fl
     if (e != hipSuccess || !want_params) return e;
 
     // dW partials -> per-class dW (FP64) -> Z -> scalars
-    if (B > 16 * 13 / 2 || Wn > 192) return hipErrorNotSupported;
+    if (Wn > 16 * kDwMaxWaves) return hipErrorNotSupported;
     DwArgs dw;
     dw.starts = p.d_starts;
     dw.g = g;
     dw.x = hls;
     dw.part = part;
     dw.ncols = ncols;
+    dw.cpw = geo.cpw;
     dw.N = N;
     dw.B = B;
     dw.Wn = Wn;
     dw.nb = p.nb;
     dw.nch = geo.nch;
-    const int rtw = (2 * B + 15) / 16;
-    const dim3 gridw((unsigned)((long long)p.nb * geo.nch)), blockw(256);
-    if (rtw <= 2)
-        hipLaunchKernelGGL((dw_kernel<2>), gridw, blockw, 0, st, dw);
-    else if (rtw <= 4)
-        hipLaunchKernelGGL((dw_kernel<4>), gridw, blockw, 0, st, dw);
-    else if (rtw <= 8)
-        hipLaunchKernelGGL((dw_kernel<8>), gridw, blockw, 0, st, dw);
-    else
-        hipLaunchKernelGGL((dw_kernel<13>), gridw, blockw, 0, st, dw);
+    dw.rgroups = geo.dwRG;
+    const dim3 gridw((unsigned)((long long)p.nb * geo.nch * geo.dwRG));
+    const dim3 blockw(64 * ((Wn + 15) / 16));
+    switch (geo.dwRT) {
+#define LMMSE_DW(R) \
+    case R: hipLaunchKernelGGL((dw_kernel<R>), gridw, blockw, 0, st, dw); break;
+        LMMSE_DW(1) LMMSE_DW(2) LMMSE_DW(3) LMMSE_DW(4) LMMSE_DW(5) LMMSE_DW(6) LMMSE_DW(7)
+#undef LMMSE_DW
+        default:
+            return hipErrorInvalidValue;
+    }
     const long long tot = (long long)p.n_classes * B * Wn;
     hipLaunchKernelGGL(dw_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, part,
                        p.d_classes, dwc, p.n_classes, p.nb, geo.nch, B, Wn);
