@@ -33,17 +33,24 @@ namespace lmmse {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
+// Block b of the launch reads x[col][starts[b] + j], j < Wn (the
+// contraction), and writes out[col][ostarts[b] + o], o < B; the forward pass
+// has starts = window starts, ostarts = b*B, and the backward dX pass the
+// transposed roles with the W^H bank.  The launch covers blocks pass,
+// pass + P, ... (nbp of them).
 struct ApplyArgs {
     const float4* wbank;
     const int* starts;
+    const int* ostarts;
     const int* classes;
     const float2* x;       // H_LS [cols][N] (unfused) or y [S*M][K][N] (fused)
     const float2* pilots;  // [K][N] (fused only)
     float2* out;           // [cols][N]
     long long ncols;       // S*M*K
     long long n_tiles;
-    int N, B, Wn, G16, Rpad, nb, rgroups;
-    int vec_store;         // N, B even and out 16-byte aligned: float4 stores
+    int N, B, Wn, G16, Rpad, nbp, pass, P, rgroups;
+    int vec_store;         // out offsets even and out 16-byte aligned: float4 stores
+    int accumulate;        // out += (read-add-write) instead of out =
     float invK;
 };
 
@@ -181,12 +188,12 @@ __global__ __launch_bounds__(kThreads, (min_blocks<RT, KF>())) void apply_f32_ke
     long long t = xcd_remap(blockIdx.x, a.n_tiles);
     const int rg = (int)(t % a.rgroups);
     t /= a.rgroups;
-    const int b = (int)(t % a.nb);
+    const int b = a.pass + a.P * (int)(t % a.nbp);
     const int cls = a.classes[b];
     const ChunkCtx x{a,
                      a.wbank + ((size_t)cls * 2 * a.G16 * a.rgroups + rg) * (RT * 64),
                      (size_t)a.rgroups * (RT * 64),
-                     (t / a.nb) * kCols,
+                     (t / a.nbp) * kCols,
                      a.starts[b],
                      a.G16,
                      b & 1,
@@ -226,12 +233,21 @@ __global__ __launch_bounds__(kThreads, (min_blocks<RT, KF>())) void apply_f32_ke
     for (int ct = 0; ct < kCT; ++ct) {
         const long long col = x.c0 + (wave * kCT + ct) * 16 + l16;
         if (col >= a.ncols) continue;
-        float2* op = a.out + col * a.N + (long long)b * a.B;
+        float2* op = a.out + col * a.N + a.ostarts[b];
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
             const int o = (((rg * RT + rt) * 16) + 4 * q) >> 1;
             const floatx4 v = acc[rt][ct];
-            if (o + 1 < a.B) {
+            if (a.accumulate) {
+                if (o < a.B) {
+                    const float2 c0v = op[o];
+                    op[o] = make_float2(c0v.x + v[0], c0v.y + v[1]);
+                }
+                if (o + 1 < a.B) {
+                    const float2 c1v = op[o + 1];
+                    op[o + 1] = make_float2(c1v.x + v[2], c1v.y + v[3]);
+                }
+            } else if (o + 1 < a.B) {
                 if (vec) {
                     *reinterpret_cast<float4*>(op + o) = make_float4(v[0], v[1], v[2], v[3]);
                 } else {
@@ -250,11 +266,43 @@ bool apply_fusable(const Plan& p) {
     return K == 1 || K == 2 || K == 4 || K == 12 || K == 24;
 }
 
+static hipError_t launch_args(const ApplyArgs& a, int RT, int kf, hipStream_t st) {
+    const dim3 grid((unsigned)a.n_tiles);
+#define LMMSE_AF(R, KK)                                                                  \
+    case R:                                                                              \
+        hipLaunchKernelGGL((apply_f32_kernel<R, KK>), grid, dim3(kThreads), 0, st, a);   \
+        break;
+#define LMMSE_AFK(KK)                                                                    \
+    case KK:                                                                             \
+        switch (RT) {                                                                    \
+            LMMSE_AF(1, KK) LMMSE_AF(2, KK) LMMSE_AF(4, KK) LMMSE_AF(8, KK)              \
+            LMMSE_AF(9, KK) LMMSE_AF(13, KK) LMMSE_AF(15, KK) LMMSE_AF(17, KK)           \
+            default: return hipErrorInvalidValue;                                        \
+        }                                                                                \
+        break;
+    switch (kf) {
+        case 0:
+            switch (RT) {
+                LMMSE_AF(1, 0) LMMSE_AF(2, 0) LMMSE_AF(4, 0) LMMSE_AF(8, 0) LMMSE_AF(9, 0)
+                LMMSE_AF(10, 0) LMMSE_AF(13, 0) LMMSE_AF(15, 0) LMMSE_AF(17, 0)
+                default: return hipErrorInvalidValue;
+            }
+            break;
+        LMMSE_AFK(1) LMMSE_AFK(2) LMMSE_AFK(4) LMMSE_AFK(12) LMMSE_AFK(24)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef LMMSE_AFK
+#undef LMMSE_AF
+    return hipGetLastError();
+}
+
 hipError_t launch_apply_f32(const Plan& p, int slots, const float2* x, const float2* pilots,
                             bool fused, float2* out, hipStream_t st) {
     ApplyArgs a;
     a.wbank = p.wf32;
     a.starts = p.d_starts;
+    a.ostarts = p.d_bstarts;
     a.classes = p.d_classes;
     a.x = x;
     a.pilots = pilots;
@@ -265,35 +313,62 @@ hipError_t launch_apply_f32(const Plan& p, int slots, const float2* x, const flo
     a.Wn = p.d.Wn;
     a.G16 = p.G16;
     a.Rpad = p.Rpad;
-    a.nb = p.nb;
+    a.nbp = p.nb;
+    a.pass = 0;
+    a.P = 1;
     a.rgroups = p.rgroups;
+    a.accumulate = 0;
     a.invK = 1.0f / (float)p.d.K;
     a.vec_store = (((a.N | a.B) & 1) == 0 && ((uintptr_t)out & 15) == 0) ? 1 : 0;
     const long long ctiles = (a.ncols + kCols - 1) / kCols;
     a.n_tiles = ctiles * p.nb * p.rgroups;
     if (a.n_tiles == 0) return hipSuccess;
-    const dim3 grid((unsigned)a.n_tiles);
-    const int kf = fused ? p.d.K : 0;
-#define LMMSE_AF(R, KK)                                                                  \
-    case R:                                                                              \
-        hipLaunchKernelGGL((apply_f32_kernel<R, KK>), grid, dim3(kThreads), 0, st, a);   \
-        break;
-#define LMMSE_AFK(KK)                                                                    \
-    case KK:                                                                             \
-        switch (p.RT) {                                                                  \
-            LMMSE_AF(1, KK) LMMSE_AF(2, KK) LMMSE_AF(4, KK) LMMSE_AF(8, KK)              \
-            LMMSE_AF(9, KK) LMMSE_AF(13, KK) LMMSE_AF(15, KK) LMMSE_AF(17, KK)           \
-            default: return hipErrorInvalidValue;                                        \
-        }                                                                                \
-        break;
-    switch (kf) {
-        LMMSE_AFK(0) LMMSE_AFK(1) LMMSE_AFK(2) LMMSE_AFK(4) LMMSE_AFK(12) LMMSE_AFK(24)
-        default:
-            return hipErrorInvalidValue;
+    return launch_args(a, p.RT, fused ? p.d.K : 0, st);
+}
+
+void transposed_row_tiles(int out_len, int& RT, int& rgroups) {
+    static const int cand[] = {1, 2, 4, 8, 9, 10, 13, 15, 17};
+    const int T = (2 * out_len + 15) / 16;
+    long long best = -1;
+    for (int rt : cand) {
+        const int g = (T + rt - 1) / rt;
+        const long long padded = (long long)g * rt;
+        if (best < 0 || padded < best || (padded == best && g < rgroups)) {
+            best = padded;
+            RT = rt;
+            rgroups = g;
+        }
     }
-#undef LMMSE_AFK
-#undef LMMSE_AF
-    return hipGetLastError();
+}
+
+hipError_t launch_apply_f32_transposed(const Plan& p, int slots, const float4* bank, int RT,
+                                       int rgroups, int pass, int P, const float2* g, float2* dx,
+                                       hipStream_t st) {
+    ApplyArgs a;
+    a.wbank = bank;
+    a.starts = p.d_bstarts;
+    a.ostarts = p.d_starts;
+    a.classes = p.d_classes;
+    a.x = g;
+    a.pilots = nullptr;
+    a.out = dx;
+    a.ncols = (long long)slots * p.d.M * p.d.K;
+    a.N = p.d.N;
+    a.B = p.d.Wn;
+    a.Wn = p.d.B;
+    a.G16 = (p.d.B + 15) / 16;
+    a.Rpad = RT * 16 * rgroups;
+    a.nbp = (p.nb - pass + P - 1) / P;
+    a.pass = pass;
+    a.P = P;
+    a.rgroups = rgroups;
+    a.accumulate = 1;
+    a.invK = 1.0f;
+    a.vec_store = 0;
+    const long long ctiles = (a.ncols + kCols - 1) / kCols;
+    a.n_tiles = ctiles * a.nbp * rgroups;
+    if (a.n_tiles <= 0 || a.nbp <= 0) return hipSuccess;
+    return launch_args(a, RT, 0, st);
 }
 
 }  // namespace lmmse

@@ -10,12 +10,12 @@
 //   dtau    = sum_c Re [ sum conj(Z_c) dR_OI + sum conj(Gamma_II) dR_II ]
 // with A = R_II + lam I, R entries r_{i-j} and dR = d r / d tau.
 //
-// dX: v_mfma_f32_16x16x4f32 on the real embedding of W^H (2Wn x 2B), one wave
-// per tile (RT row tiles of the Wn window outputs x 3 column tiles), the
-// operand layout of apply_f32.hip.  Windows of neighbouring blocks overlap,
-// so dX is zeroed and the blocks are processed in passes whose windows are
-// disjoint (block b in pass b mod P), each adding its contribution with a
-// read-add-write: deterministic, no atomics.
+// dX: the FP32 filtering kernel of the forward pass with transposed roles
+// (apply_f32.hip): contraction over the B outputs of each block, Wn output
+// rows, the real embedding of W^H as its bank.  Windows of neighbouring
+// blocks overlap, so dX is zeroed and the blocks are processed in passes whose
+// windows are disjoint (block b in pass b mod P), each adding its
+// contribution with a read-add-write: deterministic, no atomics.
 //
 // dW: split over column chunks.  A workgroup takes one block, one row group of
 // its 2B real output rows and one chunk of columns; wave w owns window columns
@@ -37,24 +37,17 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ float bq(const float4& v, int i) {
     return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
 }
-__device__ __forceinline__ long long bw_xcd(long long id, long long total) {
-    const long long NX = 8;
-    const long long q = total / NX, r = total % NX;
-    const long long x = id % NX, k = id / NX;
-    return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
-}
 
 // ---------------------------------------------------------------- layout sizes
 struct BwGeom {
-    int RT, rgroups, Rpad;   // row tiles over the 2Wn real rows of W^H
-    int G8b;                 // groups of 8 complex block outputs (contraction)
+    int RT, rgroups, Rpad;   // dX: row tiles over the 2Wn real rows of W^H
+    int G16b;                // dX: chunks of 16 block outputs (contraction)
     int P;                   // passes with disjoint windows
     int dwRT, dwRG;          // dW: row tiles per workgroup, row groups
     int nch;                 // column chunks of the dW reduction
     long long cpw;           // columns per chunk (multiple of 16)
 };
 
-constexpr int kBwRTs[] = {1, 2, 4, 5, 8, 10};
 constexpr int kDwMaxRT = 7;           // dW row tiles per workgroup (2B real rows in row groups):
                                       // <= 96 registers, 5 waves per SIMD
 constexpr int kDwMaxWaves = 16;       // one wave per 16 window columns: Wn <= 256
@@ -62,20 +55,9 @@ constexpr int kDwSlots = 512;         // workgroups resident at once (2 per CU)
 
 static BwGeom bw_geom(const lmmse_plan_desc& d, const std::vector<int>& starts, long long ncols) {
     BwGeom g{};
-    // padded row tiles, with a small charge per row group (each group re-reads G)
-    const int T = (2 * d.Wn + 15) / 16;
-    double best = -1.0;
-    for (int rt : kBwRTs) {
-        const int gg = (T + rt - 1) / rt;
-        const double cost = (double)gg * rt * (1.0 + 0.05 * gg);
-        if (best < 0.0 || cost < best) {
-            best = cost;
-            g.RT = rt;
-            g.rgroups = gg;
-        }
-    }
+    transposed_row_tiles(d.Wn, g.RT, g.rgroups);
     g.Rpad = g.RT * 16 * g.rgroups;
-    g.G8b = (d.B + 7) / 8;
+    g.G16b = (d.B + 15) / 16;
     const int nb = (int)starts.size();
     g.P = 1;
     for (bool clash = true; clash;) {
@@ -97,19 +79,25 @@ static BwGeom bw_geom(const lmmse_plan_desc& d, const std::vector<int>& starts, 
 }
 
 // ---------------------------------------------------------------- W^H bank
-// Real embedding of W^H (2Wn x 2B): Wr'[2i+ri][2o+ro] from conj(W[o][i]),
-// A-ready: bank[((c*G8b + g)*Rpad + r)*4 + q] = Wr'[r][16g + 4q .. +3].
+// Real embedding of W^H (2Wn x 2B): Wr'[2i+ri][2o+ro] from conj(W[o][i]), in
+// the FP32 bank order of the filtering kernel: groups g < 2 ceil(B/16) of 8
+// block outputs, row groups of RT*16 rows, lanes q:
+// bank[(((c*ngroups + g)*rgroups + rg)*4 + q)*RT*16 + rr] = Wr'[rg*RT*16 + rr][16g + 4q .. +3].
 __global__ void pack_wh_kernel(const double2* __restrict__ w64, float4* __restrict__ bank,
-                               int n_classes, int B, int Wn, int G8b, int Rpad) {
+                               int n_classes, int B, int Wn, int ngroups, int RT, int rgroups) {
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long total = (long long)n_classes * G8b * Rpad * 4;
+    const int rows = RT * 16;
+    const long long total = (long long)n_classes * ngroups * rgroups * 4 * rows;
     if (idx >= total) return;
-    const int q = (int)(idx & 3);
-    long long t = idx >> 2;
-    const int r = (int)(t % Rpad);
-    t /= Rpad;
-    const int g = (int)(t % G8b);
-    const int c = (int)(t / G8b);
+    const int rr = (int)(idx % rows);
+    long long t = idx / rows;
+    const int q = (int)(t & 3);
+    t >>= 2;
+    const int rg = (int)(t % rgroups);
+    t /= rgroups;
+    const int g = (int)(t % ngroups);
+    const int c = (int)(t / ngroups);
+    const int r = rg * rows + rr;
     const int i = r >> 1, ri = r & 1;
     float v[4];
 #pragma unroll
@@ -130,83 +118,6 @@ __global__ void pack_wh_kernel(const double2* __restrict__ w64, float4* __restri
 __global__ void fill_zero_kernel(float2* p, long long n) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = make_float2(0.f, 0.f);
-}
-
-// ---------------------------------------------------------------- dX
-struct DxArgs {
-    const float4* bank;
-    const int* starts;
-    const int* classes;
-    const float2* g;
-    float2* dx;
-    long long ncols, n_tiles;
-    int N, B, Wn, G8b, Rpad, rgroups, pass, P, nbp;   // nbp: blocks in this pass
-};
-
-template <int RT>
-__global__ __launch_bounds__(64) void dx_kernel(DxArgs a) {
-    constexpr int CT = 3;
-    const int lane = threadIdx.x, l16 = lane & 15, q = lane >> 4;
-    long long t = bw_xcd(blockIdx.x, a.n_tiles);
-    const int rg = (int)(t % a.rgroups);
-    t /= a.rgroups;
-    const int b = a.pass + a.P * (int)(t % a.nbp);
-    const long long c0 = (t / a.nbp) * (16 * CT);
-    const int s0 = a.starts[b], cls = a.classes[b];
-    floatx4 acc[RT][CT];
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-        for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
-    const float4* wp = a.bank + ((size_t)cls * a.G8b * a.Rpad + (size_t)rg * RT * 16 + l16) * 4 + q;
-    const float2* gp[CT];
-    bool cv[CT];
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct) {
-        const long long col = c0 + ct * 16 + l16;
-        cv[ct] = col < a.ncols;
-        gp[ct] = a.g + (cv[ct] ? col : 0) * a.N + (long long)b * a.B;
-    }
-    for (int gi = 0; gi < a.G8b; ++gi) {
-        float4 av[RT], xv[CT];
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt) av[rt] = wp[((size_t)gi * a.Rpad + rt * 16) * 4];
-        const int j = 8 * gi + 2 * q;
-#pragma unroll
-        for (int ct = 0; ct < CT; ++ct) {
-            float2 u0 = make_float2(0.f, 0.f), u1 = make_float2(0.f, 0.f);
-            if (cv[ct] && j < a.B) u0 = gp[ct][j];
-            if (cv[ct] && j + 1 < a.B) u1 = gp[ct][j + 1];
-            xv[ct] = make_float4(u0.x, u0.y, u1.x, u1.y);
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-                for (int ct = 0; ct < CT; ++ct)
-                    acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(bq(av[rt], i), bq(xv[ct], i),
-                                                                       acc[rt][ct], 0, 0, 0);
-    }
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct) {
-        if (!cv[ct]) continue;
-        const long long col = c0 + ct * 16 + l16;
-        float2* op = a.dx + col * a.N + s0;
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt) {
-            const int o = (((rg * RT + rt) * 16) + 4 * q) >> 1;   // window row
-            const floatx4 v = acc[rt][ct];
-            if (o < a.Wn) {
-                float2 cur = op[o];
-                op[o] = make_float2(cur.x + v[0], cur.y + v[1]);
-            }
-            if (o + 1 < a.Wn) {
-                float2 cur = op[o + 1];
-                op[o + 1] = make_float2(cur.x + v[2], cur.y + v[3]);
-            }
-        }
-    }
 }
 
 // ---------------------------------------------------------------- dW partials
@@ -456,7 +367,7 @@ struct BwLayout {
 
 static BwLayout bw_layout(const lmmse_plan_desc& d, int n_classes, const BwGeom& g) {
     BwLayout L{};
-    const size_t bank = (size_t)n_classes * g.G8b * g.Rpad * 4 * sizeof(float4);   // 4 lanes q per row
+    const size_t bank = (size_t)n_classes * 2 * g.G16b * g.Rpad * 4 * sizeof(float4);   // 4 lanes q per row
     const size_t part = (size_t)(d.N / d.B) * g.nch * d.B * d.Wn * sizeof(float2);
     const size_t bw = (size_t)n_classes * d.B * d.Wn * sizeof(double2);
     const size_t gam = (size_t)n_classes * d.Wn * d.Wn * sizeof(double2);
@@ -497,9 +408,9 @@ hipError_t launch_backward_fixed(Plan& p, int slots, const float2* hls, const fl
 
     // W^H bank
     {
-        const long long total = (long long)p.n_classes * geo.G8b * geo.Rpad * 4;
+        const long long total = (long long)p.n_classes * 2 * geo.G16b * geo.Rpad * 4;
         hipLaunchKernelGGL(pack_wh_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
-                           p.w64, bank, p.n_classes, B, Wn, geo.G8b, geo.Rpad);
+                           p.w64, bank, p.n_classes, B, Wn, 2 * geo.G16b, geo.RT, geo.rgroups);
     }
     // dX = 0, then one pass per window colour
     {
@@ -507,34 +418,9 @@ hipError_t launch_backward_fixed(Plan& p, int slots, const float2* hls, const fl
         hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, dhls, n);
     }
     for (int pass = 0; pass < geo.P; ++pass) {
-        DxArgs a;
-        a.bank = bank;
-        a.starts = p.d_starts;
-        a.classes = p.d_classes;
-        a.g = g;
-        a.dx = dhls;
-        a.ncols = ncols;
-        a.N = N;
-        a.B = B;
-        a.Wn = Wn;
-        a.G8b = geo.G8b;
-        a.Rpad = geo.Rpad;
-        a.rgroups = geo.rgroups;
-        a.pass = pass;
-        a.P = geo.P;
-        a.nbp = (p.nb - pass + geo.P - 1) / geo.P;
-        if (a.nbp <= 0) continue;
-        const long long ctiles = (ncols + 47) / 48;
-        a.n_tiles = ctiles * a.nbp * geo.rgroups;
-        const dim3 grid((unsigned)a.n_tiles), block(64);
-        switch (geo.RT) {
-#define LMMSE_DX(R) \
-    case R: hipLaunchKernelGGL((dx_kernel<R>), grid, block, 0, st, a); break;
-            LMMSE_DX(1) LMMSE_DX(2) LMMSE_DX(4) LMMSE_DX(5) LMMSE_DX(8) LMMSE_DX(10)
-#undef LMMSE_DX
-            default:
-                return hipErrorInvalidValue;
-        }
+        const hipError_t e = launch_apply_f32_transposed(p, slots, bank, geo.RT, geo.rgroups, pass,
+                                                         geo.P, g, dhls, st);
+        if (e != hipSuccess) return e;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !want_params) return e;

@@ -39,6 +39,7 @@ struct Plan {
     int* d_starts = nullptr;     // [nb]
     int* d_classes = nullptr;    // [nb]
     int* d_offsets = nullptr;    // [nb] output offset of each block in its window
+    int* d_bstarts = nullptr;    // [nb] first output subcarrier of each block, b*B
     int* d_class_off = nullptr;  // [n_classes]
     double2* w64 = nullptr;      // [n_classes][B][Wn] FP64 filters
     double2* ainv = nullptr;     // [Wn][Wn] (R_II + lam I)^-1 of the fixed design
@@ -66,6 +67,14 @@ hipError_t launch_apply_f32(const Plan& p, int slots, const float2* x, const flo
 hipError_t launch_apply_split(const Plan& p, int slots, const float2* x, const float2* pilots,
                               bool fused, float2* out, hipStream_t st);
 bool apply_fusable(const Plan& p);
+// The FP32 filtering kernel with transposed roles (backward dX): for blocks
+// pass, pass + P, ..., dx[col][start_b + i] += sum_o Wr^H[i][o] g[col][bB + o],
+// i < Wn, with `bank` the real embedding of W^H (2Wn x 2B) laid out as the
+// FP32 bank (RT-row tiles, rgroups row groups, ceil(B/16) chunks).
+void transposed_row_tiles(int out_len, int& RT, int& rgroups);
+hipError_t launch_apply_f32_transposed(const Plan& p, int slots, const float4* bank, int RT,
+                                       int rgroups, int pass, int P, const float2* g, float2* dx,
+                                       hipStream_t st);
 
 // Fixed design: r_d (and d r_d / d tau) on the device, A^-1 of the Toeplitz
 // A = R_II + lam I, then class filters W_c = (I - lam A^-1)[off_c rows].

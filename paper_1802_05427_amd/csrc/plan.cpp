@@ -106,7 +106,7 @@ int dev_alloc(T*& p, size_t count) {
 
 void free_plan(lmmse_plan* p) {
     if (!p) return;
-    void* ptrs[] = {p->d_starts, p->d_classes, p->d_offsets, p->d_class_off, p->w64, p->ainv, p->rd,
+    void* ptrs[] = {p->d_starts, p->d_classes, p->d_offsets, p->d_bstarts, p->d_class_off, p->w64, p->ainv, p->rd,
                     p->wf32,     p->whi,       p->wlo,         p->twiddle, p->status,
                     p->dscal};
     for (void* q : ptrs)
@@ -222,7 +222,7 @@ int lmmse_plan_create(const lmmse_plan_desc* desc, lmmse_plan_t* out) {
         return code;
     };
     if ((rc = dev_alloc(p->d_starts, p->nb)) || (rc = dev_alloc(p->d_classes, p->nb)) ||
-        (rc = dev_alloc(p->d_offsets, p->nb)) ||
+        (rc = dev_alloc(p->d_offsets, p->nb)) || (rc = dev_alloc(p->d_bstarts, p->nb)) ||
         (rc = dev_alloc(p->d_class_off, p->n_classes)) || (rc = dev_alloc(p->twiddle, K)) ||
         (rc = dev_alloc(p->status, 2)) || (rc = dev_alloc(p->dscal, 4)) ||
         (rc = dev_alloc(p->rd, 2 * (size_t)Wn)))
@@ -243,7 +243,10 @@ int lmmse_plan_create(const lmmse_plan_desc* desc, lmmse_plan_t* out) {
         tw[r] = make_float2((float)std::cos(a), (float)std::sin(a));
     }
     int zero[2] = {0, 0};
+    std::vector<int> bstarts(p->nb);
+    for (int b = 0; b < p->nb; ++b) bstarts[b] = b * desc->B;
     if (hipMemcpy(p->d_starts, p->h_starts.data(), p->nb * sizeof(int), hipMemcpyHostToDevice) ||
+        hipMemcpy(p->d_bstarts, bstarts.data(), p->nb * sizeof(int), hipMemcpyHostToDevice) ||
         hipMemcpy(p->d_classes, p->h_classes.data(), p->nb * sizeof(int), hipMemcpyHostToDevice) ||
         hipMemcpy(p->d_offsets, p->h_offsets.data(), p->nb * sizeof(int), hipMemcpyHostToDevice) ||
         hipMemcpy(p->d_class_off, p->h_class_off.data(), p->n_classes * sizeof(int),
