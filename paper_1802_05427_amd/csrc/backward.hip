@@ -71,6 +71,11 @@ static BwGeom bw_geom(const lmmse_plan_desc& d, const std::vector<int>& starts, 
     g.dwRT = (tw + g.dwRG - 1) / g.dwRG;
     // one resident wave of workgroups; at least 16 columns per chunk
     const long long steps = (ncols + 15) / 16;
+    if (steps == 0) {   // empty batch: no chunks
+        g.nch = 0;
+        g.cpw = 16;
+        return g;
+    }
     const long long want = std::max(1, kDwSlots / (nb * g.dwRG));
     g.nch = (int)std::max(1LL, std::min(want, steps));
     g.cpw = 16 * ((steps + g.nch - 1) / g.nch);

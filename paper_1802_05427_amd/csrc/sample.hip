@@ -4,20 +4,22 @@
 // and the block filter is W = R_OI (R + lam I)^-1 = (I - lam A^-1)[off_b rows]
 // with A = R + lam I (eq. 13 on the block, Sec. IV-B).
 //
-// sample_design_kernel: one workgroup of 512 threads per (s, k, b).  The sweep
-// below keeps A Hermitian, so only the 32 x 32 blocks (P, Q) with P >= Q are
-// stored: thread t owns, in every such block, the elements
-// (32P + t%32, 32Q + t/32) and (32P + t%32, 32Q + 16 + t/32), in registers
-// (n <= 32 NBK).  R is accumulated in FP64 from the FP32 LS values (the
-// products are exact), staged through LDS 16 antennas at a time.  A is then
-// inverted in place by the Hermitian sweep: for pivot k with d = A[k][k] and
-// c = A[:, k],
-//     A[i][j] -= c_i conj(c_j) / d  (i, j != k),  A[i][k] = c_i / d,
-//     A[k][j] = conj(c_j) / d,      A[k][k] = -1 / d,
-// which leaves -A^-1 after all n pivots (Gauss-Jordan elimination without
-// pivoting, safe for a positive definite A).  The next pivot column is
-// published by the owners of its lower-triangle entries through a
-// double-buffered LDS vector, one barrier per pivot.
+// sample_design_kernel: one workgroup of 1024 threads per (s, k, b).  The
+// matrix is cut into 32 x 32 blocks; only blocks (P, Q) with P >= Q are kept,
+// the diagonal ones in full, and thread (tr, tc) = (t % 32, t / 32) holds
+// entry (32P + tr, 32Q + tc) of every kept block in registers (n <= 32 NBK).
+// R is accumulated in FP64 from the FP32 LS values (the products are exact),
+// staged through LDS 16 antennas at a time.  A = R + lam I is then inverted
+// in place by the Hermitian sweep, written as one rank-1 update per pivot k:
+// with d = A[k][k], c = A[:, k] and w = c - e_k,
+//     A <- A - w w^H / d,   then A[k][k] -= 2,
+// which gives A[i][j] - c_i conj(c_j)/d off the pivot row and column,
+// c_i / d and conj(c_j) / d on them and -1/d at (k, k); after all n pivots
+// A holds -A^-1 (Gauss-Jordan elimination without pivoting, safe for a
+// positive definite A).  The pivot loop is unrolled over the column blocks,
+// so the owners of the next pivot column know at compile time which of their
+// registers hold it; they publish it through a double-buffered LDS vector,
+// one barrier per pivot.
 //
 // apply_sample_kernel: Hhat[s, m, k, O_b] = W_(s,k,b) h_ls[s, m, k, I_b] for the
 // M antennas, on v_mfma_f32_16x16x4f32 with the operand layout of the fixed
@@ -48,12 +50,37 @@ struct SampleArgs {
     int want_w;
 };
 
+// Entry index of kept block (P, Q), P >= Q.
+__host__ __device__ constexpr int blk(int P, int Q) { return P * (P + 1) / 2 + Q; }
+
+// Publish column kn = 32 QN + tn of the current A into cn: rows i >= 32 QN
+// from column block QN (owners tc == tn), rows i < 32 QN from row block QN
+// (owners tr == tn, conjugated: A[i][kn] = conj(A[kn][i])).
+template <int NBK, int QN>
+__device__ __forceinline__ void publish_col(const double2 (&A)[NBK * (NBK + 1) / 2], int tn, int tr,
+                                            int tc, int n, double2* cn) {
+    if (tc == tn) {
+#pragma unroll
+        for (int P = QN; P < NBK; ++P) {
+            const int i = 32 * P + tr;
+            if (i < n) cn[i] = A[blk(P, QN)];
+        }
+    }
+    if (tr == tn) {
+#pragma unroll
+        for (int Q = 0; Q < QN; ++Q) {
+            const double2 v = A[blk(QN, Q)];
+            cn[32 * Q + tc] = make_double2(v.x, -v.y);
+        }
+    }
+}
+
 template <int NBK>
-__global__ __launch_bounds__(512) void sample_design_kernel(SampleArgs a) {
+__global__ __launch_bounds__(1024) void sample_design_kernel(SampleArgs a) {
     constexpr int AM = 16;                     // antennas per LDS chunk
     constexpr int NMAX = 32 * NBK;
-    constexpr int NS = NBK * (NBK + 1);        // owned slots: 2 per lower block
-    __shared__ float2 xs[AM][NMAX + 1];
+    constexpr int NE = NBK * (NBK + 1) / 2;    // kept blocks = entries per thread
+    __shared__ float2 xs[AM][NMAX];
     __shared__ double2 cb[2][NMAX];
 
     const int tid = threadIdx.x, tr = tid & 31, tc = tid >> 5;
@@ -65,168 +92,151 @@ __global__ __launch_bounds__(512) void sample_design_kernel(SampleArgs a) {
     const long long s = sk / a.K;
     const int st = a.starts[b];
 
-    // slot -> (row block P, column block Q, half h), enumerated P, Q <= P, h
-    double2 A[NS];
+    double2 A[NE];
 #pragma unroll
-    for (int e = 0; e < NS; ++e) A[e] = make_double2(0.0, 0.0);
+    for (int e = 0; e < NE; ++e) A[e] = make_double2(0.0, 0.0);
 
     if (a.r_in) {
         const double2* R = a.r_in + mat * n * n;
-        int e = 0;
 #pragma unroll
         for (int P = 0; P < NBK; ++P)
 #pragma unroll
-            for (int Q = 0; Q <= P; ++Q)
-#pragma unroll
-                for (int h = 0; h < 2; ++h, ++e) {
-                    const int i = 32 * P + tr, j = 32 * Q + 16 * h + tc;
-                    if (i < n && j < n) A[e] = R[(long long)i * n + j];
-                }
+            for (int Q = 0; Q <= P; ++Q) {
+                const int i = 32 * P + tr, j = 32 * Q + tc;
+                if (i < n && j < n) A[blk(P, Q)] = R[(long long)i * n + j];
+            }
     } else {
         const double invM = 1.0 / a.M;
+        const float2* xrow = a.hls + ((s * a.M) * a.K + k) * (long long)a.N + st;   // antenna 0
+        const long long mstride = (long long)a.K * a.N;
         for (int m0 = 0; m0 < a.M; m0 += AM) {
-            for (int e = tid; e < AM * n; e += 512) {
-                const int mm = e / n, j = e % n;
+            for (int e = tid; e < AM * NMAX; e += 1024) {
+                const int mm = e / NMAX, j = e - mm * NMAX;
                 const int m = m0 + mm;
-                xs[mm][j] = m < a.M ? a.hls[(((s * a.M + m) * a.K) + k) * (long long)a.N + st + j]
-                                    : make_float2(0.f, 0.f);
+                xs[mm][j] = (m < a.M && j < n) ? xrow[m * mstride + j] : make_float2(0.f, 0.f);
             }
             __syncthreads();
-#pragma unroll 1
+#pragma unroll 2
             for (int mm = 0; mm < AM; ++mm) {
-                double2 xj[2 * NBK];
-#pragma unroll
-                for (int q = 0; q < 2 * NBK; ++q) {
-                    const int j = 16 * q + tc;
-                    const float2 v = j < n ? xs[mm][j] : make_float2(0.f, 0.f);
-                    xj[q] = make_double2(v.x, v.y);
-                }
-                int e = 0;
+                double2 xr[NBK], xc[NBK];
 #pragma unroll
                 for (int P = 0; P < NBK; ++P) {
-                    const int i = 32 * P + tr;
-                    const float2 v = i < n ? xs[mm][i] : make_float2(0.f, 0.f);
-                    const double2 xi = make_double2(v.x, v.y);
-#pragma unroll
-                    for (int Q = 0; Q <= P; ++Q)
-#pragma unroll
-                        for (int h = 0; h < 2; ++h, ++e) {
-                            const double2 u = dz_mulc(xi, xj[2 * Q + h]);
-                            A[e].x += u.x;
-                            A[e].y += u.y;
-                        }
+                    const float2 u = xs[mm][32 * P + tr], v = xs[mm][32 * P + tc];
+                    xr[P] = make_double2(u.x, u.y);
+                    xc[P] = make_double2(v.x, v.y);
                 }
+#pragma unroll
+                for (int P = 0; P < NBK; ++P)
+#pragma unroll
+                    for (int Q = 0; Q <= P; ++Q) {
+                        // A[i][j] += x_i conj(x_j)
+                        double2& t = A[blk(P, Q)];
+                        t.x = fma(xr[P].x, xc[Q].x, fma(xr[P].y, xc[Q].y, t.x));
+                        t.y = fma(xr[P].y, xc[Q].x, fma(-xr[P].x, xc[Q].y, t.y));
+                    }
             }
             __syncthreads();
         }
 #pragma unroll
-        for (int e = 0; e < NS; ++e) {
+        for (int e = 0; e < NE; ++e) {
             A[e].x *= invM;
             A[e].y *= invM;
         }
         if (a.r_out) {
             double2* R = a.r_out + mat * n * n;
-            int e = 0;
 #pragma unroll
             for (int P = 0; P < NBK; ++P)
 #pragma unroll
-                for (int Q = 0; Q <= P; ++Q)
-#pragma unroll
-                    for (int h = 0; h < 2; ++h, ++e) {
-                        const int i = 32 * P + tr, j = 32 * Q + 16 * h + tc;
-                        if (i < n && j <= i) {
-                            R[(long long)i * n + j] = A[e];
-                            R[(long long)j * n + i] = make_double2(A[e].x, -A[e].y);
-                        }
-                    }
+                for (int Q = 0; Q <= P; ++Q) {
+                    const int i = 32 * P + tr, j = 32 * Q + tc;
+                    if (i >= n || j >= n) continue;
+                    const double2 v = A[blk(P, Q)];
+                    R[(long long)i * n + j] = v;
+                    if (P > Q) R[(long long)j * n + i] = make_double2(v.x, -v.y);
+                }
         }
     }
     if (!a.want_w) return;
 
-    // A = R + lam I; publish pivot column 0 (entries A[i][0], all in the lower triangle)
-    for (int e = tid; e < 2 * NMAX; e += 512) cb[e / NMAX][e % NMAX] = make_double2(0.0, 0.0);
+    // A = R + lam I; publish pivot column 0
+#pragma unroll
+    for (int P = 0; P < NBK; ++P)
+        if (tr == tc && 32 * P + tr < n) A[blk(P, P)].x += a.lam;
+    for (int e = tid; e < 2 * NMAX; e += 1024) cb[e / NMAX][e % NMAX] = make_double2(0.0, 0.0);
     __syncthreads();
-    {
-        int e = 0;
-#pragma unroll
-        for (int P = 0; P < NBK; ++P)
-#pragma unroll
-            for (int Q = 0; Q <= P; ++Q)
-#pragma unroll
-                for (int h = 0; h < 2; ++h, ++e) {
-                    const int i = 32 * P + tr, j = 32 * Q + 16 * h + tc;
-                    if (i == j && i < n) A[e].x += a.lam;
-                    if (j == 0 && i < n) cb[0][i] = A[e];
-                }
-    }
+    publish_col<NBK, 0>(A, 0, tr, tc, n, cb[0]);
     __syncthreads();
+
     bool ok = true;
-#pragma unroll 1
-    for (int kp = 0; kp < n; ++kp) {
-        const double2* cc = cb[kp & 1];
-        double2* cn = cb[(kp + 1) & 1];
-        const double d = cc[kp].x;
-        if (!(d > 0.0) || !isfinite(d)) {
-            if (tid == 0 && atomicCAS(a.status, 0, LMMSE_ERR_NOT_PD) == 0) a.status[1] = (int)mat;
-            ok = false;
-            break;   // every thread reads the same d: uniform exit
-        }
-        const double invd = 1.0 / d;
-        double2 cj[2 * NBK];
-#pragma unroll
-        for (int q = 0; q < 2 * NBK; ++q) cj[q] = cc[16 * q + tc];
-        int e = 0;
-#pragma unroll
-        for (int P = 0; P < NBK; ++P) {
-            const int i = 32 * P + tr;
-            const double2 ci = cc[i];
-            const double2 cis = make_double2(ci.x * invd, ci.y * invd);
-#pragma unroll
-            for (int Q = 0; Q <= P; ++Q)
-#pragma unroll
-                for (int h = 0; h < 2; ++h, ++e) {
-                    const int j = 32 * Q + 16 * h + tc;
-                    const double2 cjv = cj[2 * Q + h];
-                    const double2 u = dz_mulc(cis, cjv);
-                    double2 v = make_double2(A[e].x - u.x, A[e].y - u.y);
-                    if (j == kp) v = cis;
-                    if (i == kp) v = make_double2(cjv.x * invd, -cjv.y * invd);
-                    if (i == kp && j == kp) v = make_double2(-invd, 0.0);
-                    A[e] = v;
-                    if (i < n && j <= i) {
-                        if (j == kp + 1) cn[i] = v;                               // A[i][k+1], i >= k+1
-                        else if (i == kp + 1) cn[j] = make_double2(v.x, -v.y);    // A[j][k+1] = conj(A[k+1][j])
-                    }
-                }
-        }
-        __syncthreads();
+    // Pivots kp = 32 QP + t; the block index QP is unrolled
+#define LMMSE_SWEEP_GROUP(QP)                                                              \
+    if (ok && 32 * (QP) < n) {                                                             \
+        const int tmax = min(32, n - 32 * (QP));                                           \
+        for (int t = 0; t < tmax; ++t) {                                                   \
+            const int kp = 32 * (QP) + t;                                                  \
+            const double2* cc = cb[kp & 1];                                                \
+            double2* cn = cb[(kp + 1) & 1];                                                \
+            const double d = cc[kp].x;                                                     \
+            if (!(d > 0.0) || !isfinite(d)) {                                              \
+                if (tid == 0 && atomicCAS(a.status, 0, LMMSE_ERR_NOT_PD) == 0)             \
+                    a.status[1] = (int)mat;                                                \
+                ok = false; /* every thread reads the same d: uniform exit */              \
+                break;                                                                     \
+            }                                                                              \
+            const double invd = 1.0 / d;                                                   \
+            double2 wr[NBK], wc[NBK];                                                      \
+            _Pragma("unroll") for (int P = 0; P < NBK; ++P) {                              \
+                double2 u = cc[32 * P + tr], v = cc[32 * P + tc];                          \
+                if (32 * P + tr == kp) u.x -= 1.0;                                         \
+                if (32 * P + tc == kp) v.x -= 1.0;                                         \
+                wr[P] = make_double2(u.x * invd, u.y * invd);                              \
+                wc[P] = v;                                                                 \
+            }                                                                              \
+            _Pragma("unroll") for (int P = 0; P < NBK; ++P)                                \
+                _Pragma("unroll") for (int Q = 0; Q <= P; ++Q) {                           \
+                    double2& x = A[blk(P, Q)];                                             \
+                    x.x = fma(-wr[P].x, wc[Q].x, fma(-wr[P].y, wc[Q].y, x.x));             \
+                    x.y = fma(-wr[P].y, wc[Q].x, fma(wr[P].x, wc[Q].y, x.y));              \
+                }                                                                          \
+            if (tr == t && tc == t) A[blk(QP, QP)].x -= 2.0;                               \
+            if (kp + 1 < n) {                                                              \
+                if (t + 1 < 32) publish_col<NBK, (QP)>(A, t + 1, tr, tc, n, cn);           \
+                else if ((QP) + 1 < NBK)                                                   \
+                    publish_col<NBK, ((QP) + 1 < NBK ? (QP) + 1 : (QP))>(A, 0, tr, tc, n, cn); \
+            }                                                                              \
+            __syncthreads();                                                               \
+        }                                                                                  \
     }
+    LMMSE_SWEEP_GROUP(0)
+    if constexpr (NBK > 1) { LMMSE_SWEEP_GROUP(1) }
+    if constexpr (NBK > 2) { LMMSE_SWEEP_GROUP(2) }
+    if constexpr (NBK > 3) { LMMSE_SWEEP_GROUP(3) }
+    if constexpr (NBK > 4) { LMMSE_SWEEP_GROUP(4) }
+#undef LMMSE_SWEEP_GROUP
     if (!ok) return;
+
     // A now holds -A^-1: W[o][j] = delta(off + o, j) + lam (-A^-1)[off + o][j]
     const int off = a.offsets[b];
-    int e = 0;
 #pragma unroll
     for (int P = 0; P < NBK; ++P)
 #pragma unroll
-        for (int Q = 0; Q <= P; ++Q)
+        for (int Q = 0; Q <= P; ++Q) {
+            const int i = 32 * P + tr, j = 32 * Q + tc;
+            if (i >= n || j >= n) continue;
+            const double2 v = A[blk(P, Q)];
+            // entry (i, j) and, off the diagonal blocks, its mirror (j, i)
 #pragma unroll
-            for (int h = 0; h < 2; ++h, ++e) {
-                const int i = 32 * P + tr, j = 32 * Q + 16 * h + tc;
-                if (i >= n || j > i) continue;
-                const double2 v = A[e];
-                // entry (i, j) and, by symmetry, (j, i)
-                for (int side = 0; side < 2; ++side) {
-                    const int row = side == 0 ? i : j, col = side == 0 ? j : i;
-                    if (side == 1 && i == j) break;
-                    const int o = row - off;
-                    if (o < 0 || o >= a.B) continue;
-                    const double vy = side == 0 ? v.y : -v.y;
-                    const double2 w = make_double2((row == col ? 1.0 : 0.0) + a.lam * v.x, a.lam * vy);
-                    const long long wi = (mat * a.B + o) * n + col;
-                    if (a.w64) a.w64[wi] = w;
-                    if (a.w32) a.w32[wi] = make_float2((float)w.x, (float)w.y);
-                }
+            for (int side = 0; side < (P > Q ? 2 : 1); ++side) {
+                const int row = side == 0 ? i : j, col = side == 0 ? j : i;
+                const int o = row - off;
+                if (o < 0 || o >= a.B) continue;
+                const double vy = side == 0 ? v.y : -v.y;
+                const double2 w = make_double2((row == col ? 1.0 : 0.0) + a.lam * v.x, a.lam * vy);
+                const long long wi = (mat * a.B + o) * n + col;
+                if (a.w64) a.w64[wi] = w;
+                if (a.w32) a.w32[wi] = make_float2((float)w.x, (float)w.y);
             }
+        }
 }
 
 // ---------------------------------------------------------------- apply
@@ -361,11 +371,13 @@ __global__ __launch_bounds__(64 * (pMW + pLW)) void apply_sample_kernel(SampleAp
 // ---------------------------------------------------------------- launchers
 static hipError_t launch_sample_design(const Plan& p, long long nmat, SampleArgs sa, hipStream_t st) {
     if (nmat == 0) return hipSuccess;
-    const dim3 grid((unsigned)nmat), block(512);
+    const dim3 grid((unsigned)nmat), block(1024);
     if (p.d.Wn <= 32)
         hipLaunchKernelGGL((sample_design_kernel<1>), grid, block, 0, st, sa);
     else if (p.d.Wn <= 64)
         hipLaunchKernelGGL((sample_design_kernel<2>), grid, block, 0, st, sa);
+    else if (p.d.Wn <= 96)
+        hipLaunchKernelGGL((sample_design_kernel<3>), grid, block, 0, st, sa);
     else if (p.d.Wn <= 128)
         hipLaunchKernelGGL((sample_design_kernel<4>), grid, block, 0, st, sa);
     else if (p.d.Wn <= 160)

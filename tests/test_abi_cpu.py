@@ -129,6 +129,18 @@ def test_workspace_sizes():
         workspace_size(_d(), 65)
 
 
+@pytest.mark.parametrize("rsource", ["exp", "uniform", "sample", "user"])
+@pytest.mark.parametrize("kw", [dict(), dict(K=3), dict(B=132, Wn=198, N=3300, N_fft=4096, K=24, M=2)])
+def test_workspace_size_of_an_empty_batch(rsource, kw):
+    """Zero slots (and every smaller batch) must size without faulting."""
+    if rsource == "sample" and kw.get("Wn", 150) > 160:
+        pytest.skip("sample covariance needs Wn <= 160")
+    d = _d(rsource=rsource, **kw)
+    assert workspace_size(d, 0) >= 0
+    for s in (1, 2, 3):
+        assert workspace_size(d, s) >= 0
+
+
 def test_plan_create_without_device_fails_cleanly(lib):
     import torch
     if torch.cuda.is_available():
