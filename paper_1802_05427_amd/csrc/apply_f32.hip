@@ -326,15 +326,17 @@ hipError_t launch_apply_f32(const Plan& p, int slots, const float2* x, const flo
     return launch_args(a, p.RT, fused ? p.d.K : 0, st);
 }
 
+// Row tiles of the transposed product: padded tiles, charged 5% per row group
+// (each group re-reads its input window and redoes the staging).
 void transposed_row_tiles(int out_len, int& RT, int& rgroups) {
     static const int cand[] = {1, 2, 4, 8, 9, 10, 13, 15, 17};
     const int T = (2 * out_len + 15) / 16;
-    long long best = -1;
+    double best = -1.0;
     for (int rt : cand) {
         const int g = (T + rt - 1) / rt;
-        const long long padded = (long long)g * rt;
-        if (best < 0 || padded < best || (padded == best && g < rgroups)) {
-            best = padded;
+        const double cost = (double)g * rt * (1.0 + 0.05 * g);
+        if (best < 0.0 || cost < best) {
+            best = cost;
             RT = rt;
             rgroups = g;
         }

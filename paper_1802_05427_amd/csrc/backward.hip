@@ -250,6 +250,7 @@ __global__ void dw_reduce_kernel(const float2* __restrict__ part, const int* __r
     for (int b = 0; b < nb; ++b) {
         if (classes[b] != c) continue;
         const float2* p = part + (long long)b * nch * per + e;
+#pragma unroll 8
         for (int ch = 0; ch < nch; ++ch) {
             const float2 v = p[(long long)ch * per];
             sx += v.x;
@@ -259,7 +260,9 @@ __global__ void dw_reduce_kernel(const float2* __restrict__ part, const int* __r
     dwc[idx] = make_double2(sx, sy);
 }
 
-// Z_c = dW_c A^-1  (A^-1 column-major, Hermitian)
+// Z_c = dW_c A^-1.  A^-1 is stored column-major and is Hermitian, so
+// A^-1[m][j] = conj(ainv[j + m Wn]): consecutive j (threads) read
+// consecutive entries, and the dW_c row is shared by the workgroup's threads.
 __global__ void z_kernel(const double2* __restrict__ dwc, const double2* __restrict__ ainv,
                          double2* __restrict__ z, int n_classes, int B, int Wn) {
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -268,12 +271,12 @@ __global__ void z_kernel(const double2* __restrict__ dwc, const double2* __restr
     const long long row = idx / Wn;     // (c, o)
     const int j = (int)(idx % Wn);
     const double2* d = dwc + row * Wn;
-    const double2* col = ainv + (long long)j * Wn;
     double sx = 0.0, sy = 0.0;
+#pragma unroll 4
     for (int m = 0; m < Wn; ++m) {
-        const double2 u = d[m], v = col[m];
-        sx += u.x * v.x - u.y * v.y;
-        sy += u.x * v.y + u.y * v.x;
+        const double2 u = d[m], v = ainv[j + (long long)m * Wn];   // v = conj(A^-1[m][j])
+        sx += u.x * v.x + u.y * v.y;
+        sy += u.y * v.x - u.x * v.y;
     }
     z[idx] = make_double2(sx, sy);
 }
@@ -289,6 +292,7 @@ __global__ void gamma_kernel(const double2* __restrict__ w64, const double2* __r
     const double2* W = w64 + (long long)c * B * Wn;
     const double2* Z = z + (long long)c * B * Wn;
     double gx = 0.0, gy = 0.0;
+#pragma unroll 4
     for (int o = 0; o < B; ++o) {
         const double2 w = W[(long long)o * Wn + i], zz = Z[(long long)o * Wn + j];
         gx -= w.x * zz.x + w.y * zz.y;
@@ -298,27 +302,30 @@ __global__ void gamma_kernel(const double2* __restrict__ w64, const double2* __r
 }
 
 // Per class: t1 = Re sum conj(Z) dR_OI, t2 = Re sum conj(Gamma_II) dR_II,
-// t3 = Re tr(Gamma_II).  One workgroup per class, fixed-order tree reduction;
-// results out[c*3 + 0..2].
+// t3 = Re tr(Gamma_II).  kPgSlices workgroups per class each reduce a fixed
+// slice with a fixed-order tree; out[(c*kPgSlices + slice)*3 + 0..2].
+constexpr int kPgSlices = 32;
+
 __global__ __launch_bounds__(256) void param_grad_kernel(const double2* __restrict__ z,
                                                          const double2* __restrict__ gam,
                                                          const double2* __restrict__ rd,
                                                          const int* __restrict__ class_off,
                                                          double* __restrict__ out, int B, int Wn) {
     __shared__ double red[3][256];
-    const int c = blockIdx.x, tid = threadIdx.x;
+    const int c = blockIdx.x / kPgSlices, sl = blockIdx.x % kPgSlices, tid = threadIdx.x;
     const double2* Z = z + (long long)c * B * Wn;
     const double2* G = gam + (long long)c * Wn * Wn;
     const double2* dr = rd + Wn;
     const int off = class_off[c];
     double t1 = 0.0, t2 = 0.0, t3 = 0.0;
-    for (long long e = tid; e < (long long)B * Wn; e += 256) {
+    const int stride = 256 * kPgSlices;
+    for (long long e = sl * 256 + tid; e < (long long)B * Wn; e += stride) {
         const int o = (int)(e / Wn), j = (int)(e % Wn);
         const int d = off + o - j;
         const double2 g = d >= 0 ? dr[d] : make_double2(dr[-d].x, -dr[-d].y);
         t1 += Z[e].x * g.x + Z[e].y * g.y;
     }
-    for (long long e = tid; e < (long long)Wn * Wn; e += 256) {
+    for (long long e = sl * 256 + tid; e < (long long)Wn * Wn; e += stride) {
         const int i = (int)(e / Wn), j = (int)(e % Wn);
         const int d = i - j;
         const double2 g = d >= 0 ? dr[d] : make_double2(dr[-d].x, -dr[-d].y);
@@ -335,18 +342,20 @@ __global__ __launch_bounds__(256) void param_grad_kernel(const double2* __restri
         __syncthreads();
     }
     if (tid == 0)
-        for (int k = 0; k < 3; ++k) out[c * 3 + k] = red[k][0];
+        for (int k = 0; k < 3; ++k) out[((long long)c * kPgSlices + sl) * 3 + k] = red[k][0];
 }
 
-// dscal[0] = dtau, dscal[1] = dlam, summed over classes in order
+// dscal[0] = dtau, dscal[1] = dlam, summed over classes and slices in order
 __global__ void param_sum_kernel(const double* __restrict__ per, double* __restrict__ dscal,
                                  int n_classes) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     double dt = 0.0, dl = 0.0;
-    for (int c = 0; c < n_classes; ++c) {
-        dt += per[c * 3 + 0] + per[c * 3 + 1];
-        dl += per[c * 3 + 2];
-    }
+    for (int c = 0; c < n_classes; ++c)
+        for (int sl = 0; sl < kPgSlices; ++sl) {
+            const double* q = per + ((long long)c * kPgSlices + sl) * 3;
+            dt += q[0] + q[1];
+            dl += q[2];
+        }
     dscal[0] = dt;
     dscal[1] = dl;
 }
@@ -382,7 +391,7 @@ static BwLayout bw_layout(const lmmse_plan_desc& d, int n_classes, const BwGeom&
     L.zc = L.dwc + align256(bw);
     L.gam = L.zc + align256(bw);
     L.per = L.gam + align256(gam);
-    L.total = L.per + align256((size_t)n_classes * 3 * sizeof(double));
+    L.total = L.per + align256((size_t)n_classes * kPgSlices * 3 * sizeof(double));
     return L;
 }
 
@@ -463,8 +472,8 @@ hipError_t launch_backward_fixed(Plan& p, int slots, const float2* hls, const fl
     const long long totg = (long long)p.n_classes * Wn * Wn;
     hipLaunchKernelGGL(gamma_kernel, dim3((unsigned)((totg + 255) / 256)), dim3(256), 0, st, p.w64, zc,
                        gam, p.n_classes, B, Wn);
-    hipLaunchKernelGGL(param_grad_kernel, dim3(p.n_classes), dim3(256), 0, st, zc, gam, p.rd,
-                       p.d_class_off, per, B, Wn);
+    hipLaunchKernelGGL(param_grad_kernel, dim3(p.n_classes * kPgSlices), dim3(256), 0, st, zc, gam,
+                       p.rd, p.d_class_off, per, B, Wn);
     hipLaunchKernelGGL(param_sum_kernel, dim3(1), dim3(64), 0, st, per, p.dscal, p.n_classes);
     return hipGetLastError();
 }
