@@ -57,6 +57,7 @@ struct Plan {
 };
 
 size_t fixed_bank_f32_elems(const Plan& p);    // float4 elements
+size_t hls_bytes(const lmmse_plan_desc& d, int slots);   // H_LS staging, 256-byte multiple
 size_t split_bank_elems(const Plan& p);        // uint16 elements per part
 
 // ---- launchers (return hipError_t of the launch) ----

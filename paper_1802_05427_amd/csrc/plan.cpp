@@ -125,13 +125,15 @@ int check_device() {
     return LMMSE_OK;
 }
 
-size_t hls_bytes(const lmmse_plan_desc& d, int slots) {
-    return (size_t)slots * d.M * d.K * d.N * sizeof(float2);
-}
-
 }  // namespace
 
 namespace lmmse {
+
+// H_LS staging in the workspace, rounded up to 256 bytes so that what follows
+// it (the sample path's filters) stays 16-byte aligned for the LDS copies.
+size_t hls_bytes(const lmmse_plan_desc& d, int slots) {
+    return ((size_t)slots * d.M * d.K * d.N * sizeof(float2) + 255) & ~(size_t)255;
+}
 
 size_t fixed_bank_f32_elems(const Plan& p) { return (size_t)p.n_classes * 2 * p.G16 * p.Rpad * 4; }
 size_t split_bank_elems(const Plan& p) { return (size_t)p.n_classes * p.G16 * p.Rpad * 32; }

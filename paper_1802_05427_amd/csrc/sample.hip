@@ -22,9 +22,11 @@
 // one barrier per pivot.
 //
 // apply_sample_kernel: Hhat[s, m, k, O_b] = W_(s,k,b) h_ls[s, m, k, I_b] for the
-// M antennas, on v_mfma_f32_16x16x4f32 with the operand layout of the fixed
-// path (apply_f32.hip); the loader waves expand the compact complex W into
-// its real embedding in LDS.
+// M antennas (128 per workgroup), on v_mfma_f32_16x16x4f32 with the operand
+// order of the fixed path (apply_f32.hip).  The compact complex FP32 filter is
+// streamed in 16-row chunks into two LDS buffers by the direct global-to-LDS
+// loads, and each MFMA's real-embedded operand is built in registers from one
+// 16-byte complex pair.
 #include "internal.h"
 
 namespace lmmse {
@@ -41,7 +43,7 @@ struct SampleArgs {
     const double2* r_in;    // optional [mat][Wn][Wn] (row-major), used instead of hls
     double2* r_out;         // optional: R (before lam) [mat][Wn][Wn]
     double2* w64;           // optional: W [mat][B][Wn]
-    float2* w32;            // optional: W [mat][B][Wn]
+    float2* w32;            // optional: W [mat][B][Wp], Wp = Wn rounded up to even (pad 0)
     const int* starts;
     const int* offsets;
     int* status;
@@ -217,6 +219,7 @@ __global__ __launch_bounds__(1024) void sample_design_kernel(SampleArgs a) {
 
     // A now holds -A^-1: W[o][j] = delta(off + o, j) + lam (-A^-1)[off + o][j]
     const int off = a.offsets[b];
+    const int wp = (n + 1) & ~1;
 #pragma unroll
     for (int P = 0; P < NBK; ++P)
 #pragma unroll
@@ -232,9 +235,12 @@ __global__ __launch_bounds__(1024) void sample_design_kernel(SampleArgs a) {
                 if (o < 0 || o >= a.B) continue;
                 const double vy = side == 0 ? v.y : -v.y;
                 const double2 w = make_double2((row == col ? 1.0 : 0.0) + a.lam * v.x, a.lam * vy);
-                const long long wi = (mat * a.B + o) * n + col;
-                if (a.w64) a.w64[wi] = w;
-                if (a.w32) a.w32[wi] = make_float2((float)w.x, (float)w.y);
+                if (a.w64) a.w64[(mat * a.B + o) * n + col] = w;
+                if (a.w32) {
+                    float2* wr = a.w32 + (mat * a.B + o) * wp;
+                    wr[col] = make_float2((float)w.x, (float)w.y);
+                    if (col == 0 && wp > n) wr[n] = make_float2(0.f, 0.f);   // pad column
+                }
             }
         }
 }
@@ -244,57 +250,128 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 struct SampleApplyArgs {
     const float2* hls;
-    const float2* w32;      // [mat][B][Wn]
+    const float2* w32;      // [mat][B][Wp] compact complex filters, Wp = Wn rounded up to even
     const int* starts;
     float2* out;
     long long n_tiles;
-    int M, K, N, B, Wn, nb, rgroups, G8, cgroups;
+    int M, K, N, B, Wn, Wp, nb, rgroups, G16, cgroups;
 };
 
 __device__ __forceinline__ float f4s(const float4& v, int i) {
     return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
 }
 
-constexpr int pCT = 2, pMW = 4, pLW = 2;
-constexpr int pCols = 16 * pCT * pMW;    // 128 antennas per workgroup
-constexpr int pXS = 18;
-constexpr int pXBuf = pCols * pXS / 2;
+constexpr int pCT = 2;                   // column tiles per wave
+constexpr int pThreads = 256;            // 4 waves
+constexpr int pCols = 16 * pCT * 4;      // 128 antennas per workgroup
+constexpr int pXP = pCols + 1;           // LS chunk row stride (16-byte slots), slot-major
 
+// Filter chunk cc of this row group into LDS with the direct global-to-LDS
+// loads: 16-byte slot s of the buffer holds W[o][16cc + 2jp .. +1] (one
+// complex pair) with o = s / 8 and jp = (s % 8) ^ (o % 8), a swizzle that
+// makes the 8 rows a lane group reads at one jp fall into distinct banks.
+// Rows are Wp (even) entries long, so every pair is 16-byte aligned and in
+// the row.  Rows past B and pairs past the row read a valid pair instead;
+// they only meet zero LS values or produce discarded outputs.
 template <int RT>
-__device__ __forceinline__ void sample_stage(const SampleApplyArgs& a, int lt, int cc, int st,
-                                             const float2* xbase, long long xstride, int m0,
-                                             const float2* wmat, int rg, float4* ws4, float4* xs4) {
-    constexpr int NL = 64 * pLW;
-    // filter rows [rg*RT*16, +RT*16) of the real embedding, window rows [16cc, 16cc+16)
-    for (int e = lt; e < 2 * RT * 64; e += NL) {
-        const int gg = e / (RT * 64), rem = e - gg * (RT * 64);
-        const int rr = rem >> 2, q = rem & 3;
-        const int row = rg * RT * 16 + rr;
-        const int o = row >> 1, ro = row & 1;
-        const int j0 = 16 * cc + 8 * gg + 2 * q;
-        float2 w0 = make_float2(0.f, 0.f), w1 = make_float2(0.f, 0.f);
-        if (o < a.B) {
-            if (j0 < a.Wn) w0 = wmat[(long long)o * a.Wn + j0];
-            if (j0 + 1 < a.Wn) w1 = wmat[(long long)o * a.Wn + j0 + 1];
+__device__ __forceinline__ void sample_copy_w(const float2* wmat, int B, int Wp, int o0, int cc,
+                                              int wave, int lane, float4* wdst) {
+    constexpr int NV = RT * 64;   // 8 RT rows x 8 slots
+#pragma unroll
+    for (int u = 0; u < (NV + pThreads - 1) / pThreads; ++u) {
+        const int base = u * pThreads + wave * 64;
+        if (base < NV) {
+            const int sl = base + lane, ol = sl >> 3, jp = (sl & 7) ^ (ol & 7);
+            const int o = min(o0 + ol, B - 1);
+            int j = 16 * cc + 2 * jp;
+            if (j >= Wp) j = 0;
+            const float2* src = wmat + (unsigned)(o * Wp + j);
+            __builtin_amdgcn_global_load_lds(
+                src, (__attribute__((address_space(3))) void*)(wdst + base), 16, 0, 0);
         }
-        ws4[e] = ro == 0 ? make_float4(w0.x, -w0.y, w1.x, -w1.y) : make_float4(w0.y, w0.x, w1.y, w1.x);
-    }
-    float2* xs2 = reinterpret_cast<float2*>(xs4);
-    for (int e = lt; e < pCols * 16; e += NL) {
-        const int c = e >> 4, r = e & 15;
-        const int j = cc * 16 + r;
-        const int m = m0 + c;
-        float2 v = make_float2(0.f, 0.f);
-        if (j < a.Wn && m < a.M) v = xbase[m * xstride + st + j];
-        xs2[c * pXS + r] = v;
     }
 }
 
+// LS values of one chunk: 128 antennas x 16 window rows, 8 per thread.
+struct SampleRaw {
+    float2 v[8];
+};
+
+__device__ __forceinline__ void sample_load_x(const SampleApplyArgs& a, const float2* xbase,
+                                              long long xstride, int m0, int cc, int tid,
+                                              SampleRaw& R) {
+    const int r = tid & 15, c0 = tid >> 4, j = 16 * cc + r;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int m = m0 + c0 + 16 * u;
+        R.v[u] = (j < a.Wn && m < a.M) ? xbase[m * xstride + j] : make_float2(0.f, 0.f);
+    }
+}
+
+__device__ __forceinline__ void sample_store_x(const SampleRaw& R, int tid, float4* xs4) {
+    float2* xs2 = reinterpret_cast<float2*>(xs4);
+    const int r = tid & 15, c0 = tid >> 4;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) xs2[2 * ((r >> 1) * pXP + c0 + 16 * u) + (r & 1)] = R.v[u];
+}
+
+// One group of 8 window rows: per row tile the filter pair is read once and
+// expanded to the real embedding [[Re, -Im], [Im, Re]] in registers.
 template <int RT>
-__global__ __launch_bounds__(64 * (pMW + pLW)) void apply_sample_kernel(SampleApplyArgs a) {
-    __shared__ float4 xs4[2 * pXBuf];
-    __shared__ float4 ws4[2 * 2 * RT * 64];
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l16 = lane & 15, q = lane >> 4;
+__device__ __forceinline__ void sample_mfma_group(floatx4 (&acc)[RT][pCT], const float4 (&xv)[pCT],
+                                                  const float4* wb, int gg, int l16, int q) {
+    const int ro = l16 & 1;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+        const int ol = 8 * rt + (l16 >> 1), jp = 4 * gg + q;
+        const float4 w = wb[8 * ol + (jp ^ (ol & 7))];
+        const float4 av = ro == 0 ? make_float4(w.x, -w.y, w.z, -w.w) : make_float4(w.y, w.x, w.w, w.z);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int ct = 0; ct < pCT; ++ct)
+                acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(f4s(av, i), f4s(xv[ct], i),
+                                                                   acc[rt][ct], 0, 0, 0);
+    }
+}
+
+struct SampleCtx {
+    const SampleApplyArgs& a;
+    const float2* xbase;
+    const float2* wmat;
+    long long xstride;
+    int m0, o0, nchunks, tid, wave, lane, l16, q;
+};
+
+// One chunk, as in the fixed-path kernel: LS values into LDS, next chunk's LS
+// values into registers, barrier, first group's MFMAs, the second group's LS
+// operands, the copy of the next filter chunk into wnext, the second group's
+// MFMAs, wait, barrier.
+template <int RT>
+__device__ __forceinline__ void sample_step(const SampleCtx& x, int cc, float4* xs4, float4* wcur,
+                                            float4* wnext, floatx4 (&acc)[RT][pCT], SampleRaw& raw) {
+    sample_store_x(raw, x.tid, xs4);
+    if (cc + 1 < x.nchunks) sample_load_x(x.a, x.xbase, x.xstride, x.m0, cc + 1, x.tid, raw);
+    __syncthreads();
+    float4 xv[pCT];
+#pragma unroll
+    for (int ct = 0; ct < pCT; ++ct) xv[ct] = xs4[x.q * pXP + (x.wave * pCT + ct) * 16 + x.l16];
+    sample_mfma_group<RT>(acc, xv, wcur, 0, x.l16, x.q);
+#pragma unroll
+    for (int ct = 0; ct < pCT; ++ct) xv[ct] = xs4[(4 + x.q) * pXP + (x.wave * pCT + ct) * 16 + x.l16];
+    if (cc + 1 < x.nchunks) sample_copy_w<RT>(x.wmat, x.a.B, x.a.Wp, x.o0, cc + 1, x.wave, x.lane, wnext);
+    if (16 * cc + 8 < x.a.Wn) sample_mfma_group<RT>(acc, xv, wcur, 1, x.l16, x.q);
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's copies have landed
+    __syncthreads();
+}
+
+template <int RT>
+__global__ __launch_bounds__(pThreads, 2) void apply_sample_kernel(SampleApplyArgs a) {
+    __shared__ float4 xs4[8 * pXP];
+    __shared__ float4 wA[RT * 64];
+    __shared__ float4 wB[RT * 64];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     long long t = blockIdx.x;
     const int rg = (int)(t % a.rgroups);
     t /= a.rgroups;
@@ -304,58 +381,36 @@ __global__ __launch_bounds__(64 * (pMW + pLW)) void apply_sample_kernel(SampleAp
     const long long sk = t / a.nb;
     const int k = (int)(sk % a.K);
     const long long s = sk / a.K;
-    const int st = a.starts[b];
-    const int m0 = cg * pCols;
-    const long long xstride = (long long)a.K * a.N;
-    const float2* xbase = a.hls + ((s * a.M) * a.K + k) * (long long)a.N;
-    const float2* wmat = a.w32 + ((sk * a.nb + b) * a.B) * (long long)a.Wn;
-    const int nchunks = (a.Wn + 15) >> 4;
-
-    if (wave >= pMW) {
-        const int lt = tid - 64 * pMW;
-        sample_stage<RT>(a, lt, 0, st, xbase, xstride, m0, wmat, rg, ws4, xs4);
-        __syncthreads();
-        for (int cc = 0; cc < nchunks; ++cc) {
-            const int nb2 = (cc + 1) & 1;
-            if (cc + 1 < nchunks)
-                sample_stage<RT>(a, lt, cc + 1, st, xbase, xstride, m0, wmat, rg,
-                                 ws4 + nb2 * 2 * RT * 64, xs4 + nb2 * pXBuf);
-            __syncthreads();
-        }
-        return;
-    }
+    const SampleCtx x{a,
+                      a.hls + ((s * a.M) * a.K + k) * (long long)a.N + a.starts[b],
+                      a.w32 + ((sk * a.nb + b) * a.B) * (long long)a.Wp,
+                      (long long)a.K * a.N,
+                      cg * pCols,
+                      rg * RT * 8,
+                      a.G16,
+                      tid,
+                      wave,
+                      lane,
+                      lane & 15,
+                      lane >> 4};
     floatx4 acc[RT][pCT];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int ct = 0; ct < pCT; ++ct) acc[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+    SampleRaw raw;
+    sample_copy_w<RT>(x.wmat, a.B, a.Wp, x.o0, 0, wave, lane, wA);
+    sample_load_x(a, x.xbase, x.xstride, x.m0, 0, tid, raw);
+    __builtin_amdgcn_s_waitcnt(0x0F70);
     __syncthreads();
-    for (int cc = 0; cc < nchunks; ++cc) {
-        const int buf = cc & 1;
-        const float4* wb = ws4 + buf * 2 * RT * 64;
-        const float4* xb = xs4 + buf * pXBuf;
-#pragma unroll
-        for (int gg = 0; gg < 2; ++gg) {
-            float4 av[RT], xv[pCT];
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt) av[rt] = wb[gg * RT * 64 + (rt * 16 + l16) * 4 + q];
-#pragma unroll
-            for (int ct = 0; ct < pCT; ++ct)
-                xv[ct] = xb[((wave * pCT + ct) * 16 + l16) * (pXS / 2) + 4 * gg + q];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-                    for (int ct = 0; ct < pCT; ++ct)
-                        acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(f4s(av[rt], i), f4s(xv[ct], i),
-                                                                           acc[rt][ct], 0, 0, 0);
-        }
-        __syncthreads();
+    for (int cc = 0; cc < x.nchunks; cc += 2) {
+        sample_step<RT>(x, cc, xs4, wA, wB, acc, raw);
+        if (cc + 1 < x.nchunks) sample_step<RT>(x, cc + 1, xs4, wB, wA, acc, raw);
     }
+    const int l16 = x.l16, q = x.q;
 #pragma unroll
     for (int ct = 0; ct < pCT; ++ct) {
-        const int m = m0 + (wave * pCT + ct) * 16 + l16;
+        const int m = x.m0 + (wave * pCT + ct) * 16 + l16;
         if (m >= a.M) continue;
         float2* op = a.out + ((s * a.M + m) * a.K + k) * (long long)a.N + (long long)b * a.B;
 #pragma unroll
@@ -422,8 +477,8 @@ hipError_t launch_batched_filters(const Plan& p, int nmat, double2*, double2*, c
 
 size_t sample_workspace_bytes(const lmmse_plan_desc& d, int slots) {
     // H_LS, then the compact FP32 filters of every (slot, user, block)
-    const size_t hls = (size_t)slots * d.M * d.K * d.N * sizeof(float2);
-    const size_t w = (size_t)slots * d.K * (d.N / d.B) * d.B * d.Wn * sizeof(float2);
+    const size_t hls = hls_bytes(d, slots);
+    const size_t w = (size_t)slots * d.K * (d.N / d.B) * d.B * ((d.Wn + 1) & ~1) * sizeof(float2);
     return hls + w;
 }
 
@@ -448,12 +503,13 @@ hipError_t launch_sample_estimate(const Plan& p, int slots, const float2* hls, d
     aa.N = p.d.N;
     aa.B = p.d.B;
     aa.Wn = p.d.Wn;
+    aa.Wp = (p.d.Wn + 1) & ~1;
     aa.nb = p.nb;
     aa.rgroups = p.rgroups;
-    aa.G8 = p.G8;
+    aa.G16 = p.G16;
     aa.cgroups = (p.d.M + pCols - 1) / pCols;
     aa.n_tiles = nmat * aa.cgroups * p.rgroups;
-    const dim3 grid((unsigned)aa.n_tiles), block(64 * (pMW + pLW));
+    const dim3 grid((unsigned)aa.n_tiles), block(pThreads);
     switch (p.RT) {
 #define LMMSE_SA(R) \
     case R: hipLaunchKernelGGL((apply_sample_kernel<R>), grid, block, 0, st, aa); break;

@@ -37,6 +37,7 @@ CASES = [
     dict(M=6, K=2, N=72, N_fft=128, taps=8, tau=3.0, B=12, Wn=24, slots=2, design_tau=4.5),
     dict(M=6, K=2, N=72, N_fft=128, taps=8, tau=3.0, B=12, Wn=12, slots=1, design_tau=2.0),
     dict(M=5, K=3, N=96, N_fft=128, taps=8, tau=2.0, B=16, Wn=48, slots=1, design_tau=3.0),
+    dict(M=6, K=3, N=99, N_fft=128, taps=8, tau=2.0, B=9, Wn=21, slots=2, design_tau=3.0),
     dict(M=16, K=12, N=1200, N_fft=2048, taps=72, tau=4.0, B=100, Wn=150, slots=1, design_tau=8.0),
     # large system: 2B = 264 real rows (three dW row groups), 13 window tiles
     dict(M=2, K=24, N=3300, N_fft=4096, taps=144, tau=32.0, B=132, Wn=198, slots=1, design_tau=24.0),

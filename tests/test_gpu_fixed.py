@@ -99,6 +99,8 @@ def _check_estimate(out, ref, truth):
     dict(M=5, K=3, N=96, N_fft=128, taps=8, tau=2.0, B=12, Wn=24, slots=2),
     dict(M=1, K=1, N=64, N_fft=64, taps=4, tau=1.0, B=16, Wn=32, slots=3),
     dict(M=7, K=4, N=80, N_fft=128, taps=6, tau=2.0, B=10, Wn=20, slots=1),
+    # odd block and window (scalar stores, odd window starts)
+    dict(M=6, K=3, N=99, N_fft=128, taps=8, tau=2.0, B=9, Wn=21, slots=2),
     # paper size, one slot
     dict(M=128, K=12, N=1200, N_fft=2048, taps=72, tau=4.0, B=100, Wn=150, slots=1),
     dict(M=128, K=12, N=1200, N_fft=2048, taps=72, tau=16.0, B=100, Wn=100, slots=1),

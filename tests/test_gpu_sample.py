@@ -28,6 +28,7 @@ CASES = [
     dict(M=5, K=3, N=96, N_fft=128, taps=8, tau=2.0, B=16, Wn=48, slots=1),      # ragged M, Wn <= 64
     dict(M=40, K=2, N=240, N_fft=256, taps=12, tau=3.0, B=60, Wn=120, slots=1),  # Wn <= 128
     dict(M=130, K=2, N=300, N_fft=512, taps=16, tau=4.0, B=100, Wn=150, slots=1),  # 2 column groups
+    dict(M=6, K=3, N=99, N_fft=128, taps=8, tau=2.0, B=9, Wn=21, slots=2),       # odd B, odd Wn
     dict(M=128, K=12, N=1200, N_fft=2048, taps=72, tau=4.0, B=100, Wn=150, slots=1),
     dict(M=128, K=12, N=1200, N_fft=2048, taps=72, tau=16.0, B=100, Wn=100, slots=1),
 ]
@@ -38,7 +39,7 @@ def _plan(c, sigma2):
                 rsource="sample", sigma2=sigma2, max_slots=c["slots"])
 
 
-@pytest.mark.parametrize("c", CASES[:4])
+@pytest.mark.parametrize("c", CASES[:5])
 def test_covariance_and_filters_fp64(dev, c):
     print(f"sample design {c}", flush=True)
     sb = make_slot_batch(M=c["M"], K=c["K"], N=c["N"], N_fft=c["N_fft"], taps=c["taps"], tau=c["tau"],

@@ -31,6 +31,7 @@ def _t(a, dev):
 @pytest.mark.parametrize("cfg", [
     dict(M=8, K=2, N=72, N_fft=128, taps=8, tau=2.0, B=12, Wn=24, slots=2),
     dict(M=5, K=3, N=96, N_fft=128, taps=8, tau=2.0, B=12, Wn=24, slots=1),
+    dict(M=6, K=3, N=99, N_fft=128, taps=8, tau=2.0, B=9, Wn=21, slots=2),
     dict(M=3, K=12, N=1200, N_fft=2048, taps=72, tau=4.0, B=100, Wn=150, slots=1),
     dict(M=128, K=12, N=1200, N_fft=2048, taps=72, tau=4.0, B=100, Wn=150, slots=1),
     dict(M=128, K=12, N=1200, N_fft=2048, taps=72, tau=16.0, B=100, Wn=100, slots=1),
