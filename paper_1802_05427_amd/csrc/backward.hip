@@ -237,27 +237,43 @@ void dw_kernel(DwArgs a) {
     }
 }
 
-// dW_c[o][j] = sum over blocks of class c, then chunks, of the partials (FP64, fixed order)
-__global__ void dw_reduce_kernel(const float2* __restrict__ part, const int* __restrict__ classes,
-                                 double2* __restrict__ dwc, int n_classes, int nb, int nch, int B,
-                                 int Wn) {
-    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+// dW_c[o][j] = sum over the blocks of class c and their column chunks of the
+// FP32 partials, in FP64.  A workgroup takes 64 consecutive (c, o, j)
+// entries; wave w sums the chunks ch = w mod 4 of every block of the class,
+// and the four wave sums are added in a fixed order (deterministic).
+__global__ __launch_bounds__(256) void dw_reduce_kernel(const float2* __restrict__ part,
+                                                        const int* __restrict__ classes,
+                                                        double2* __restrict__ dwc, int n_classes,
+                                                        int nb, int nch, int B, int Wn) {
+    __shared__ double2 red[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const long long idx = (long long)blockIdx.x * 64 + lane;
     const long long per = (long long)B * Wn;
-    if (idx >= per * n_classes) return;
-    const int c = (int)(idx / per);
-    const long long e = idx % per;
     double sx = 0.0, sy = 0.0;
-    for (int b = 0; b < nb; ++b) {
-        if (classes[b] != c) continue;
-        const float2* p = part + (long long)b * nch * per + e;
-#pragma unroll 8
-        for (int ch = 0; ch < nch; ++ch) {
-            const float2 v = p[(long long)ch * per];
-            sx += v.x;
-            sy += v.y;
+    if (idx < per * n_classes) {
+        const int c = (int)(idx / per);
+        const long long e = idx % per;
+        for (int b = 0; b < nb; ++b) {
+            if (classes[b] != c) continue;
+            const float2* p = part + (long long)b * nch * per + e;
+#pragma unroll 4
+            for (int ch = w; ch < nch; ch += 4) {
+                const float2 v = p[(long long)ch * per];
+                sx += v.x;
+                sy += v.y;
+            }
         }
     }
-    dwc[idx] = make_double2(sx, sy);
+    red[w][lane] = make_double2(sx, sy);
+    __syncthreads();
+    if (w == 0 && idx < per * n_classes) {
+        double2 t = red[0][lane];
+        for (int k = 1; k < 4; ++k) {
+            t.x += red[k][lane].x;
+            t.y += red[k][lane].y;
+        }
+        dwc[idx] = t;
+    }
 }
 
 // Z_c = dW_c A^-1.  A^-1 is stored column-major and is Hermitian, so
@@ -465,7 +481,7 @@ hipError_t launch_backward_fixed(Plan& p, int slots, const float2* hls, const fl
             return hipErrorInvalidValue;
     }
     const long long tot = (long long)p.n_classes * B * Wn;
-    hipLaunchKernelGGL(dw_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, part,
+    hipLaunchKernelGGL(dw_reduce_kernel, dim3((unsigned)((tot + 63) / 64)), dim3(256), 0, st, part,
                        p.d_classes, dwc, p.n_classes, p.nb, geo.nch, B, Wn);
     hipLaunchKernelGGL(z_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, dwc, p.ainv,
                        zc, p.n_classes, B, Wn);

@@ -29,14 +29,21 @@ __device__ __forceinline__ double2 zmulc(double2 a, double2 b) {
 }
 __device__ __forceinline__ double2 zconj(double2 a) { return make_double2(a.x, -a.y); }
 
-// r_d and d r_d / d tau for d = 0..n-1.
+// r_d and d r_d / d tau for d = 0..n-1, one wave per d.
 //  uniform (eq. 16):  r_d = (1 - e^{-j a}) / (j a),  a = 2 pi L d / N_fft
 //                         = sin(a)/a - j (2 sin^2(a/2))/a
 //  exponential:       r_d = sum_l p_l e^{-j 2 pi l d / N_fft},  p_l = e^{-l/tau} / S
 //                     dr_d/dtau = sum_l p_l (l - lbar) / tau^2 e^{-j 2 pi l d / N_fft}
-__global__ void rd_kernel(double2* rd, int n, int rsource, double L, double tau, int taps,
-                          int N_fft) {
-    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+// The tap sums are split over the lanes and reduced in a fixed order.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+    return v;
+}
+
+__global__ __launch_bounds__(64) void rd_kernel(double2* rd, int n, int rsource, double L, double tau,
+                                                int taps, int N_fft) {
+    const int d = blockIdx.x, lane = threadIdx.x;
     if (d >= n) return;
     double2 r = make_double2(0.0, 0.0), dr = make_double2(0.0, 0.0);
     if (rsource == LMMSE_R_UNIFORM) {
@@ -49,36 +56,43 @@ __global__ void rd_kernel(double2* rd, int n, int rsource, double L, double tau,
         }
     } else {
         double S = 0.0, S1 = 0.0;
-        for (int l = 0; l < taps; ++l) {
+        for (int l = lane; l < taps; l += 64) {
             const double w = exp(-(double)l / tau);
             S += w;
             S1 += (double)l * w;
         }
+        S = wave_sum(S);
+        S1 = wave_sum(S1);
         const double lbar = S1 / S;
-        for (int l = 0; l < taps; ++l) {
+        double rx = 0.0, ry = 0.0, dx = 0.0, dy = 0.0;
+        for (int l = lane; l < taps; l += 64) {
             const double p = exp(-(double)l / tau) / S;
             const long long m = ((long long)l * d) % N_fft;
             double sn, cs;
             sincospi(2.0 * (double)m / (double)N_fft, &sn, &cs);
-            r.x += p * cs;
-            r.y -= p * sn;
+            rx += p * cs;
+            ry -= p * sn;
             const double dp = p * ((double)l - lbar) / (tau * tau);
-            dr.x += dp * cs;
-            dr.y -= dp * sn;
+            dx += dp * cs;
+            dy -= dp * sn;
         }
+        r = make_double2(wave_sum(rx), wave_sum(ry));
+        dr = make_double2(wave_sum(dx), wave_sum(dy));
     }
-    rd[d] = r;
-    rd[n + d] = dr;
+    if (lane == 0) {
+        rd[d] = r;
+        rd[n + d] = dr;
+    }
 }
 
 // Levinson-Durbin on A[i][j] = a_{i-j}, a_d = r_d + lam delta_d (a_{-d} =
-// conj(a_d)), then the Gohberg-Semencul fill of A^-1.  One wave; LDS holds
+// conj(a_d)), giving x = A^-1 e_0.  One wave; LDS holds
 // a_d and two copies of the predictor.  Predictor of order k: A_{k+1} [1; p]
 // = [P_k; 0], p^(k)_i = p^(k-1)_i + kap conj(p^(k-1)_{k-i}), p^(k)_k = kap,
 // kap = -(a_k + sum_{i<k} p_i a_{k-i}) / P_{k-1}, P_k = P_{k-1} (1 - |kap|^2).
 // A non-positive P (A not positive definite) sets LMMSE_ERR_NOT_PD.
 __global__ __launch_bounds__(64) void toeplitz_inverse_kernel(const double2* __restrict__ rd, int n,
-                                                              double lam, double2* __restrict__ ainv,
+                                                              double lam, double2* __restrict__ xout,
                                                               int* status) {
     extern __shared__ double2 sh[];
     double2* av = sh;            // a_d
@@ -123,30 +137,40 @@ __global__ __launch_bounds__(64) void toeplitz_inverse_kernel(const double2* __r
         if (tid == 0 && atomicCAS(status, 0, LMMSE_ERR_NOT_PD) == 0) status[1] = 0;
         return;
     }
-    // x = A^-1 e_0 = [1; p] / P, in place
+    // x = A^-1 e_0 = [1; p] / P
     const double iP = 1.0 / P;
     for (int i = tid; i < n; i += 64) {
         const double2 v = i == 0 ? make_double2(1.0, 0.0) : cur[i];
-        cur[i] = make_double2(v.x * iP, v.y * iP);
+        xout[i] = make_double2(v.x * iP, v.y * iP);
     }
+}
+
+// Gohberg-Semencul fill of A^-1 from its first column x (y_k = conj(x_{n-1-k})
+// the last column): along a diagonal Ainv[i][j] = Ainv[i-1][j-1] +
+// (x_i conj(x_j) - y_{i-1} conj(y_{j-1})) / x_0, so for i >= j, d = i - j,
+//     Ainv[i][j] = x_d + sum_{s=1..j} (x_{d+s} conj(x_s) - y_{d+s-1} conj(y_{s-1})) / x_0,
+// and Ainv[j][i] = conj(Ainv[i][j]).  One thread per entry, column-major.
+__global__ __launch_bounds__(256) void gs_fill_kernel(const double2* __restrict__ xg, int n,
+                                                      double2* __restrict__ ainv) {
+    extern __shared__ double2 xs[];
+    for (int t = threadIdx.x; t < n; t += blockDim.x) xs[t] = xg[t];
     __syncthreads();
-    const double2* x = cur;
-    const double ix0 = 1.0 / x[0].x;
-    for (int d = tid; d < n; d += 64) {
-        // diagonal i - j = d: start at (d, 0), walk down
-        double2 v = x[d];
-        ainv[d] = v;
-        ainv[(long long)d * n] = zconj(v);
-        for (int s = 1; d + s < n; ++s) {
-            const int i = d + s, j = s;
-            const double2 t1 = zmulc(x[i], x[j]);
-            // y_{i-1} conj(y_{j-1}) with y_k = conj(x_{n-1-k})
-            const double2 t2 = zmulc(x[n - j], x[n - i]);
-            v = zadd(v, make_double2((t1.x - t2.x) * ix0, (t1.y - t2.y) * ix0));
-            ainv[i + (long long)j * n] = v;
-            ainv[j + (long long)i * n] = zconj(v);
-        }
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long long)n * n) return;
+    const int i0 = (int)(idx % n), j0 = (int)(idx / n);
+    const bool up = i0 < j0;
+    const int i = up ? j0 : i0, j = up ? i0 : j0, d = i - j;
+    const double ix0 = 1.0 / xs[0].x;
+    double vx = 0.0, vy = 0.0;
+    for (int s = 1; s <= j; ++s) {
+        const double2 t1 = zmulc(xs[d + s], xs[s]);
+        // y_{d+s-1} conj(y_{s-1}) = conj(x_{n-d-s}) x_{n-s}
+        const double2 t2 = zmulc(xs[n - s], xs[n - d - s]);
+        vx += t1.x - t2.x;
+        vy += t1.y - t2.y;
     }
+    double2 v = make_double2(xs[d].x + vx * ix0, xs[d].y + vy * ix0);
+    ainv[idx] = up ? zconj(v) : v;
 }
 
 // W_c[i][j] = delta(off_c + i, j) - lam Ainv[off_c + i][j].
@@ -254,10 +278,13 @@ hipError_t launch_pack_banks(Plan& p, hipStream_t st) {
 hipError_t launch_fixed_design(Plan& p, double tau, double sigma2, hipStream_t st) {
     const int n = p.d.Wn;
     const double lam = sigma2 / p.d.K;
-    hipLaunchKernelGGL(rd_kernel, dim3((n + 127) / 128), dim3(128), 0, st, p.rd, n, p.d.rsource,
-                       p.d.L, tau, p.d.taps, p.d.N_fft);
+    hipLaunchKernelGGL(rd_kernel, dim3(n), dim3(64), 0, st, p.rd, n, p.d.rsource, p.d.L, tau,
+                       p.d.taps, p.d.N_fft);
     hipLaunchKernelGGL(toeplitz_inverse_kernel, dim3(1), dim3(64), (size_t)3 * n * sizeof(double2),
-                       st, p.rd, n, lam, p.ainv, p.status);
+                       st, p.rd, n, lam, p.rd + 2 * n, p.status);
+    const long long nn = (long long)n * n;
+    hipLaunchKernelGGL(gs_fill_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256),
+                       (size_t)n * sizeof(double2), st, p.rd + 2 * n, n, p.ainv);
     const long long tot = (long long)p.n_classes * p.d.B * n;
     hipLaunchKernelGGL(extract_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
                        p.ainv, p.d_class_off, p.w64, p.n_classes, p.d.B, n, lam);

@@ -43,7 +43,7 @@ struct Plan {
     int* d_class_off = nullptr;  // [n_classes]
     double2* w64 = nullptr;      // [n_classes][B][Wn] FP64 filters
     double2* ainv = nullptr;     // [Wn][Wn] (R_II + lam I)^-1 of the fixed design
-    double2* rd = nullptr;       // [2][Wn] r_d and dr_d/dtau, d = 0..Wn-1
+    double2* rd = nullptr;       // [3][Wn] r_d, dr_d/dtau (d = 0..Wn-1), x = A^-1 e_0
     float4* wf32 = nullptr;      // FP32 bank
     uint16_t* whi = nullptr;     // split bank, hi part
     uint16_t* wlo = nullptr;     // split bank, lo part (FP16: scaled by 2^11)

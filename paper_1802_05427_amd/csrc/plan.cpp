@@ -227,7 +227,7 @@ int lmmse_plan_create(const lmmse_plan_desc* desc, lmmse_plan_t* out) {
         (rc = dev_alloc(p->d_offsets, p->nb)) || (rc = dev_alloc(p->d_bstarts, p->nb)) ||
         (rc = dev_alloc(p->d_class_off, p->n_classes)) || (rc = dev_alloc(p->twiddle, K)) ||
         (rc = dev_alloc(p->status, 2)) || (rc = dev_alloc(p->dscal, 4)) ||
-        (rc = dev_alloc(p->rd, 2 * (size_t)Wn)))
+        (rc = dev_alloc(p->rd, 3 * (size_t)Wn)))
         return fail(rc);
     if (has_bank) {
         if ((rc = dev_alloc(p->w64, (size_t)p->n_classes * desc->B * Wn)) ||
