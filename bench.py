@@ -263,10 +263,12 @@ def main():
             cpu_threads = len(os.sched_getaffinity(0))
         except AttributeError:
             cpu_threads = os.cpu_count() or 1
+        # whole slots, cycling over the distinct ones, until about cpu_seconds of work
         n_done, t_cpu = 0, 0.0
-        while t_cpu < args.cpu_seconds and n_done < uniq:
+        while t_cpu < args.cpu_seconds:
+            i = n_done % uniq
             t1 = time.perf_counter()
-            O.estimate(sb.y[n_done:n_done + 1], sb.pilots, sigma2, B, Wn, args.rsource, **okw)
+            O.estimate(sb.y[i:i + 1], sb.pilots, sigma2, B, Wn, args.rsource, **okw)
             t_cpu += time.perf_counter() - t1
             n_done += 1
         cpu = {"value": round(n_done * M * K * N / t_cpu, 1), "unit": "coeff/s", "cores": cpu_threads,
