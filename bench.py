@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the split-precision, sample-covariance and fwd+bwd lines")
+    ap.add_argument("--fwdbwd-only", action="store_true",
+                    help="only time the fwd+bwd training step (16 slots) and print its line")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
     return ap.parse_args()
@@ -100,6 +102,32 @@ def log(msg, quiet=False):
         print(msg, file=sys.stderr, flush=True)
 
 
+def fwd_bwd(M, K, N, N_fft, B, Wn, taps, sigma2, pil, dev, stream, steps, warmup):
+    """One fwd+bwd training step of the fixed design on 16 slots with tau ~ U[2, 24]:
+    design, despread, filter, loss gradient, backward to h_ls / tau / sigma2."""
+    import torch
+
+    from paper_1802_05427_amd import Plan
+    from synth.torch_slots import draw_batch
+    S2 = 16
+    g = torch.Generator(device=dev)
+    g.manual_seed(180205427)
+    y3, H3, _ = draw_batch(g, S2, M, K, N, N_fft, taps, 2.0, 24.0, sigma2, pil)
+    with Plan(M=M, K=K, N=N, N_fft=N_fft, B=B, Wn=Wn, rsource="exp", taps=taps, tau_rms=8.0,
+              sigma2=1e-4, max_slots=S2) as pl:
+        def step():
+            pl.set_design(8.0, 1e-4)
+            h = pl.despread(y3, pil)
+            o = pl.apply(h)
+            gr = (o - H3) * (2.0 / o.numel())
+            return pl.backward(h, gr, want_params=True)
+        t_ms = time_calls(step, steps, warmup, stream)
+    return {"per_s": round(1e3 / t_ms, 1), "ms": round(t_ms, 4), "slots": S2,
+            "coeffs": S2 * M * K * N,
+            "workload": "16 slots, overlapping 150/100, exponential design (tau, sigma2), "
+                        "tau_rms ~ U[2, 24] per (slot, user), SNR 10 dB"}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -127,6 +155,17 @@ def main():
         return
     M, K, N, N_fft, taps, tau, snr = 128, 12, 1200, 2048, 72, 4.0, 10.0
     B, Wn, S = args.b, args.wn, args.slots
+    if args.fwdbwd_only:
+        from synth import make_pilots
+        pil = torch.from_numpy(make_pilots(K, N)).to(dev)
+        r = fwd_bwd(M, K, N, N_fft, B, Wn, taps, 0.1, pil, dev, torch.cuda.current_stream(),
+                    args.steps, args.warmup)
+        print(json.dumps({"metric": "fwd+bwd steps/s", "value": r["per_s"], "unit": "steps/s",
+                          "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                          "ms_per_step": r["ms"], "higher_is_better": True, "scaling": "weak",
+                          "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+                          "config": {"workload": r["workload"], "slots": r["slots"]}}), flush=True)
+        return
     uniq = min(S, 8)
     t0 = time.time()
     sb = make_slot_batch(M=M, K=K, N=N, N_fft=N_fft, taps=taps, tau=tau, snr_db=snr, slots=uniq,
@@ -237,25 +276,7 @@ def main():
             "value": round(S2 * M * K * N / (t_ms * 1e-3), 1), "ms": round(t_ms, 4), "slots": S2,
             "nmse_gap_db": abs(O.nmse_db(o3u, sb.H[:1]) - O.nmse_db(ref_s, sb.H[:1])),
             "discrepancy_db": round(O.discrepancy_db(o3u, ref_s), 1)}
-        # one fwd+bwd training step of the fixed design (16 slots, tau ~ U[2, 24]):
-        # design, despread, filter, loss gradient, backward to h_ls / tau / sigma2
-        from synth.torch_slots import draw_batch
-        g = torch.Generator(device=dev)
-        g.manual_seed(180205427)
-        y3, H3, _ = draw_batch(g, S2, M, K, N, N_fft, taps, 2.0, 24.0, sigma2, pil)
-        with Plan(M=M, K=K, N=N, N_fft=N_fft, B=B, Wn=Wn, rsource="exp", taps=taps, tau_rms=8.0,
-                  sigma2=1e-4, max_slots=S2) as pl:
-            def step():
-                pl.set_design(8.0, 1e-4)
-                h = pl.despread(y3, pil)
-                o = pl.apply(h)
-                gr = (o - H3) * (2.0 / o.numel())
-                return pl.backward(h, gr, want_params=True)
-            t_ms = time_calls(step, 5, 2, stream)
-        extras["fwd_bwd"] = {"per_s": round(1e3 / t_ms, 1), "ms": round(t_ms, 4), "slots": S2,
-                             "coeffs": S2 * M * K * N,
-                             "workload": "16 slots, overlapping 150/100, exponential design (tau, sigma2), "
-                                         "tau_rms ~ U[2, 24] per (slot, user), SNR 10 dB"}
+        extras["fwd_bwd"] = fwd_bwd(M, K, N, N_fft, B, Wn, taps, sigma2, pil, dev, stream, 5, 2)
 
     cpu = None
     if not args.no_cpu_baseline:
