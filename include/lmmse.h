@@ -52,6 +52,8 @@
  * in FP32 on the matrix cores (LMMSE_FP32), or as split products
  * hi*hi + hi*lo + lo*hi with FP32 accumulation in BF16 (LMMSE_BF16X3) or
  * FP16 (LMMSE_FP16X3).  The sample-covariance path always filters in FP32.
+ * The backward products are FP32 on the matrix cores (fixed designs) or
+ * FP64 on the vector units (sample covariance).
  *
  * Calls with slots == 0 launch nothing and accept NULL data pointers.
  *
@@ -161,6 +163,8 @@ int lmmse_plan_get_desc(lmmse_plan_t plan, lmmse_plan_desc *out);
  * then the FP32 / split copies.  Asynchronous.  A non-positive prediction
  * error (A not positive definite) is reported by lmmse_sync_status. */
 int lmmse_set_design(lmmse_plan_t plan, double tau_rms, double sigma2, void *stream);
+/* On a SAMPLE plan it only records sigma2 (tau_rms ignored, nothing is
+ * launched): the noise variance lmmse_backward differentiates at. */
 
 /* Installs caller filters (LMMSE_R_USER plans): w is device complex128
  * [n_classes][B][Wn], row-major per filter, class order as lmmse_block_plan
@@ -207,15 +211,32 @@ int lmmse_estimate(lmmse_plan_t plan, int slots, const void *y_pilot,
                    const void *pilots, double sigma2, void *h_hat,
                    void *ws, size_t ws_bytes, void *stream);
 
+/* The estimator from LS estimates, h_ls -> h_hat (lmmse_estimate without the
+ * despreading): fixed and user designs filter with the plan's filters
+ * (a fixed design is rebuilt first if sigma2 differs from its own); a
+ * sample-covariance plan forms each window's covariance from h_ls, designs
+ * with lam = sigma2 / K and filters.  Records sigma2 as the plan's design
+ * noise (the value lmmse_backward uses on a sample plan).  ws as for
+ * lmmse_estimate (sample plans; may be NULL otherwise).  This is the
+ * function whose gradients lmmse_backward returns. */
+int lmmse_estimate_ls(lmmse_plan_t plan, int slots, const void *h_ls,
+                      double sigma2, void *h_hat, void *ws, size_t ws_bytes,
+                      void *stream);
+
 /* ---- backward path ------------------------------------------------------- */
 
-/* Gradients of a real loss through the estimator, given g = dL/dRe(h_hat) +
- * j dL/dIm(h_hat) (complex64 [S][M][K][N]).  Writes d_hls (same layout) and,
- * when the pointers are non-NULL, the host doubles *d_tau (EXPONENTIAL
- * design only; NaN otherwise) and *d_sigma2 (fixed and sample designs);
- * requesting them synchronises `stream`.  Fixed designs only: a
- * sample-covariance plan returns UNSUPPORTED (the path through R is not
- * implemented).  ws: lmmse_workspace_size bytes. */
+/* Gradients of a real loss through lmmse_estimate_ls, given g =
+ * dL/dRe(h_hat) + j dL/dIm(h_hat) (complex64 [S][M][K][N]).  Writes d_hls
+ * (same layout) and, when the pointers are non-NULL, the host doubles *d_tau
+ * (EXPONENTIAL design only; NaN otherwise) and *d_sigma2 (fixed and sample
+ * designs); requesting them synchronises `stream`.
+ * Fixed designs: d_hls = sum_b W_b^H g_b (overlapping windows add), and the
+ * design parameters by implicit differentiation of the block solve.
+ * Sample covariance (at the sigma2 of the last lmmse_estimate_ls /
+ * lmmse_estimate / lmmse_set_design): per (slot, user, window) the filter
+ * depends on h_ls through R as well, so d_hls also receives
+ * (Gam + Gam^H) X / M with Gam the window's gradient of R; windows with
+ * Wn <= 160.  ws: lmmse_workspace_size bytes. */
 int lmmse_backward(lmmse_plan_t plan, int slots, const void *h_ls,
                    const void *g, void *d_hls, double *d_tau, double *d_sigma2,
                    void *ws, size_t ws_bytes, void *stream);

@@ -51,6 +51,8 @@ PROTOTYPES = {
     "lmmse_apply": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
     "lmmse_covariance": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
     "lmmse_sample_filters": (c_int, [c_void_p, c_int, c_void_p, c_double, c_void_p, c_void_p]),
+    "lmmse_estimate_ls": (c_int, [c_void_p, c_int, c_void_p, c_double, c_void_p, c_void_p,
+                                  c_size_t, c_void_p]),
     "lmmse_estimate": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_double, c_void_p,
                                c_void_p, c_size_t, c_void_p]),
     "lmmse_backward": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, P_double,

@@ -194,6 +194,16 @@ class Plan:
                                        ws, wsb, _stream_ptr(stream)), "lmmse_estimate")
         return out
 
+    def estimate_ls(self, h_ls, sigma2: float, out=None, stream=None) -> torch.Tensor:
+        """The estimator from LS estimates, h_ls -> h_hat (records sigma2 as the design noise)."""
+        S = self._check_cols(h_ls, "h_ls")
+        out = torch.empty_like(h_ls) if out is None else out
+        self._check_cols(out, "out")
+        ws, wsb = self._workspace(S)
+        check(self._lib.lmmse_estimate_ls(self._h, S, _ptr(h_ls), float(sigma2), _ptr(out), ws, wsb,
+                                          _stream_ptr(stream)), "lmmse_estimate_ls")
+        return out
+
     # ---- backward
     def backward(self, h_ls, g, want_params: bool = True, out=None, stream=None):
         """Returns (d_hls, d_tau, d_sigma2); the scalars are None unless requested."""

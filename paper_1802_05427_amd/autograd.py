@@ -41,6 +41,35 @@ class LmmseFn(torch.autograd.Function):
         return (d_hls if ctx.needs_input_grad[0] else None), gt, gs, None
 
 
+class SampleLmmseFn(torch.autograd.Function):
+    """The sample-covariance estimator as a function of the LS estimates and
+    the noise variance: each (slot, user, window) designs its filter from the
+    window's own covariance over the antennas, so the gradient to h_ls runs
+    through R as well as through the filtering.
+
+        h_hat = SampleLmmseFn.apply(h_ls, sigma2, plan)
+    """
+
+    @staticmethod
+    def forward(ctx, h_ls, sigma2, plan):
+        sig = float(sigma2)
+        out = plan.estimate_ls(h_ls, sig)
+        ctx.save_for_backward(h_ls)
+        ctx.plan = plan
+        ctx.sigma2 = sig
+        return out
+
+    @staticmethod
+    def backward(ctx, g):
+        (h_ls,) = ctx.saved_tensors
+        plan = ctx.plan
+        plan.set_design(float("nan"), ctx.sigma2)
+        want = bool(ctx.needs_input_grad[1])
+        d_hls, _, d_sig = plan.backward(h_ls, g.contiguous(), want_params=want)
+        gs = torch.tensor(d_sig, dtype=torch.float64) if want else None
+        return (d_hls if ctx.needs_input_grad[0] else None), gs, None
+
+
 def lmmse_filter(h_ls, tau_rms, sigma2, plan):
     """Functional form of LmmseFn."""
     return LmmseFn.apply(h_ls, tau_rms, sigma2, plan)

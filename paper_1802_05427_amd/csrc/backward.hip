@@ -412,7 +412,7 @@ static BwLayout bw_layout(const lmmse_plan_desc& d, int n_classes, const BwGeom&
 }
 
 size_t backward_workspace_bytes(const lmmse_plan_desc& d, int slots) {
-    if (d.rsource == LMMSE_R_SAMPLE) return 0;
+    if (d.rsource == LMMSE_R_SAMPLE) return sample_backward_workspace_bytes(d, slots);
     const long long ncols = (long long)slots * d.M * d.K;
     std::vector<int> starts;
     const int nb = d.N / d.B, halo = (d.Wn - d.B) / 2;

@@ -1,0 +1,412 @@
+// Backward of the sample-covariance estimator.  Per (slot s, user k, block b)
+// let X = h_ls[s, :, k, I_b]^T (Wn x M), G = g[s, :, k, O_b]^T (B x M),
+// A = X X^H / M + lam I and W = R_OI A^-1 (eq. 13 on the window).  With the
+// gradient convention dL = Re sum conj(grad z) dz:
+//     dW   = G X^H                           (B x Wn)
+//     Z    = dW A^-1                         (B x Wn)
+//     Gam  = -W^H Z,  then Gam[off + o, :] += Z[o, :]   (gradient of R, Wn x Wn)
+//     dX   = W^H G + (Gam + Gam^H) X / M     (R depends on X: dR = (dX X^H + X dX^H) / M)
+//     dlam = Re tr(-W^H Z), summed over all windows.
+// The window gradients are written per window and combined afterwards in a
+// fixed order (overlapping windows add), so the result does not depend on
+// scheduling.
+//
+// The window products are batched complex GEMMs with FP64 accumulation on the
+// vector units (the solve-side products Z and Gam need FP64; the others reuse
+// the same kernel).  Each operand is a strided view into h_ls, g or a
+// per-window buffer.
+#include <algorithm>
+
+#include "internal.h"
+
+namespace lmmse {
+
+// Matrix view: element (r, c) of batch (s, k, b) sits at
+//   p + s*s_slot + k*s_user + (blk_tab ? blk_tab[b] : b)*s_blk + r*rs + c*cs,
+// conjugated when conj is set.
+struct ZView {
+    const void* p;
+    long long rs, cs, s_slot, s_user, s_blk;
+    const int* blk_tab;
+    int conj;
+};
+
+struct ZGemmArgs {
+    ZView A, B, C;       // C = alpha A B (+ C when beta); C.p is written
+    int m, n, kd;        // C is m x n, the contraction has kd terms
+    int K, nb;           // batch index = (s * K + k) * nb + b
+    int tiles_m, tiles_n;
+    double alpha;
+    int beta;
+};
+
+constexpr int zT = 64;    // output tile edge
+constexpr int zKC = 16;   // contraction chunk
+
+__device__ __forceinline__ long long zbase(const ZView& v, long long bat, int K, int nb) {
+    const int b = (int)(bat % nb);
+    const long long sk = bat / nb;
+    const int k = (int)(sk % K);
+    const long long s = sk / K;
+    return s * v.s_slot + k * v.s_user + (long long)(v.blk_tab ? v.blk_tab[b] : b) * v.s_blk;
+}
+
+template <typename T>
+__device__ __forceinline__ double2 zload(const void* p, long long i, int conj) {
+    const T v = reinterpret_cast<const T*>(p)[i];
+    return make_double2((double)v.x, conj ? -(double)v.y : (double)v.y);
+}
+
+template <typename TA, typename TB, typename TC>
+__global__ __launch_bounds__(256) void zgemm_kernel(ZGemmArgs g) {
+    __shared__ double2 As[zKC][zT];
+    __shared__ double2 Bs[zKC][zT];
+    const int tid = threadIdx.x;
+    long long t = blockIdx.x;
+    const int tn = (int)(t % g.tiles_n);
+    t /= g.tiles_n;
+    const int tm = (int)(t % g.tiles_m);
+    const long long bat = t / g.tiles_m;
+    const int r0 = tm * zT, c0 = tn * zT;
+    const long long abase = zbase(g.A, bat, g.K, g.nb);
+    const long long bbase = zbase(g.B, bat, g.K, g.nb);
+    const long long cbase = zbase(g.C, bat, g.K, g.nb);
+    // loads: consecutive lanes walk the operand's unit-stride index
+    const bool a_rowfast = g.A.rs == 1, b_colfast = g.B.cs == 1;
+    // outputs: consecutive lanes walk C's unit-stride index
+    const bool c_rowfast = g.C.rs == 1;
+    const int tf = tid & 15, ts = tid >> 4;
+    const int ri = c_rowfast ? tf : ts, ci = c_rowfast ? ts : tf;
+
+    double2 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0.0, 0.0);
+
+    double2 pa[4], pb[4];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = tid + 256 * u;
+            const int r = a_rowfast ? (e & 63) : (e >> 4), ka = a_rowfast ? (e >> 6) : (e & 15);
+            const int c = b_colfast ? (e & 63) : (e >> 4), kb = b_colfast ? (e >> 6) : (e & 15);
+            pa[u] = (r0 + r < g.m && k0 + ka < g.kd)
+                        ? zload<TA>(g.A.p, abase + (r0 + r) * g.A.rs + (k0 + ka) * g.A.cs, g.A.conj)
+                        : make_double2(0.0, 0.0);
+            pb[u] = (c0 + c < g.n && k0 + kb < g.kd)
+                        ? zload<TB>(g.B.p, bbase + (k0 + kb) * g.B.rs + (c0 + c) * g.B.cs, g.B.conj)
+                        : make_double2(0.0, 0.0);
+        }
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < g.kd; k0 += zKC) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = tid + 256 * u;
+            const int r = a_rowfast ? (e & 63) : (e >> 4), ka = a_rowfast ? (e >> 6) : (e & 15);
+            const int c = b_colfast ? (e & 63) : (e >> 4), kb = b_colfast ? (e >> 6) : (e & 15);
+            As[ka][r] = pa[u];
+            Bs[kb][c] = pb[u];
+        }
+        __syncthreads();
+        if (k0 + zKC < g.kd) fetch(k0 + zKC);
+#pragma unroll 4
+        for (int kk = 0; kk < zKC; ++kk) {
+            double2 av[4], bv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) av[i] = As[kk][ri + 16 * i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bv[j] = Bs[kk][ci + 16 * j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    acc[i][j].x = fma(av[i].x, bv[j].x, fma(-av[i].y, bv[j].y, acc[i][j].x));
+                    acc[i][j].y = fma(av[i].x, bv[j].y, fma(av[i].y, bv[j].x, acc[i][j].y));
+                }
+        }
+        __syncthreads();
+    }
+    TC* cp = reinterpret_cast<TC*>(const_cast<void*>(g.C.p));
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int r = r0 + ri + 16 * i, c = c0 + ci + 16 * j;
+            if (r >= g.m || c >= g.n) continue;
+            const long long o = cbase + r * g.C.rs + c * g.C.cs;
+            double x = g.alpha * acc[i][j].x, y = g.alpha * acc[i][j].y;
+            if (g.beta) {
+                x += (double)cp[o].x;
+                y += (double)cp[o].y;
+            }
+            if constexpr (sizeof(TC) == sizeof(double2))
+                cp[o] = make_double2(x, y);
+            else
+                cp[o] = make_float2((float)x, (float)y);
+        }
+}
+
+template <typename TA, typename TB, typename TC>
+static hipError_t zgemm(ZGemmArgs g, long long nbat, hipStream_t st) {
+    g.tiles_m = (g.m + zT - 1) / zT;
+    g.tiles_n = (g.n + zT - 1) / zT;
+    const long long blocks = nbat * g.tiles_m * g.tiles_n;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL((zgemm_kernel<TA, TB, TC>), dim3((unsigned)blocks), dim3(256), 0, st, g);
+    return hipGetLastError();
+}
+
+// Per window: dlam partial = Re tr(Gam) (Gam = -W^H Z as computed so far),
+// then Gam[off + o, :] += Z[o, :].
+__global__ __launch_bounds__(256) void gamma_rows_kernel(double2* gam, const double2* z,
+                                                         const int* offsets, double* dlam_w, int B,
+                                                         int Wn, int nb) {
+    __shared__ double red[256];
+    const long long mat = blockIdx.x;
+    const int off = offsets[mat % nb];
+    double2* gm = gam + mat * Wn * Wn;
+    const double2* zm = z + mat * B * Wn;
+    double tr = 0.0;
+    for (int i = threadIdx.x; i < Wn; i += 256) tr += gm[(long long)i * Wn + i].x;
+    red[threadIdx.x] = tr;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) dlam_w[mat] = red[0];
+    // the trace is read before any row is changed
+    for (int e = threadIdx.x; e < B * Wn; e += 256) {
+        const int o = e / Wn, j = e - o * Wn;
+        double2& d = gm[(long long)(off + o) * Wn + j];
+        d.x += zm[e].x;
+        d.y += zm[e].y;
+    }
+}
+
+// dhls[s, m, k, n] = sum over the windows b that hold n, in increasing b, of
+// dxw[(s, k, b)][m][n - start_b].
+__global__ __launch_bounds__(256) void combine_windows_kernel(const float2* dxw, const int* starts,
+                                                              float2* dhls, int M, int K, int N,
+                                                              int B, int Wn, int nb,
+                                                              long long total) {
+    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= total) return;
+    const int n = (int)(e % N);
+    long long r = e / N;
+    const int k = (int)(r % K);
+    r /= K;
+    const int m = (int)(r % M);
+    const long long s = r / M;
+    // a window that holds n starts within ceil(Wn / B) + 1 blocks of n's block
+    const int bc = n / B, halo_blocks = (Wn + B - 1) / B + 1;
+    const int blo = max(0, bc - halo_blocks), bhi = min(nb - 1, bc + halo_blocks);
+    float sx = 0.f, sy = 0.f;
+    for (int b = blo; b <= bhi; ++b) {
+        const int j = n - starts[b];
+        if (j < 0 || j >= Wn) continue;
+        const long long mat = (s * K + k) * nb + b;
+        const float2 v = dxw[(mat * M + m) * Wn + j];
+        sx += v.x;
+        sy += v.y;
+    }
+    dhls[e] = make_float2(sx, sy);
+}
+
+// Fixed-order sum of the per-window dlam partials into out[1]; out[0] (the
+// delay-spread gradient of the fixed design) is NaN here.
+__global__ __launch_bounds__(256) void dlam_sum_kernel(const double* dlam_w, long long nmat,
+                                                       double* out) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (long long i = threadIdx.x; i < nmat; i += 256) s += dlam_w[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = __builtin_nan("");
+        out[1] = red[0];
+    }
+}
+
+namespace {
+size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Per-window buffers of one chunk of slots.
+struct SbLayout {
+    size_t ainv, w64, dw, z, dxw, total;
+};
+
+SbLayout sb_layout(const lmmse_plan_desc& d, int slots) {
+    const long long nmat = (long long)slots * d.K * (d.N / d.B);
+    SbLayout L{};
+    size_t o = 0;
+    L.ainv = o;
+    o += up256((size_t)nmat * d.Wn * d.Wn * sizeof(double2));
+    L.w64 = o;
+    o += up256((size_t)nmat * d.B * d.Wn * sizeof(double2));
+    L.dw = o;
+    o += up256((size_t)nmat * d.B * d.Wn * sizeof(double2));
+    L.z = o;
+    o += up256((size_t)nmat * d.B * d.Wn * sizeof(double2));
+    L.dxw = o;
+    o += up256((size_t)nmat * d.M * d.Wn * sizeof(float2));
+    L.total = o;
+    return L;
+}
+
+// Slots per chunk: as many as fit in the forward estimate's workspace (at
+// least one), so that the backward needs little more memory than the forward.
+int sb_chunk(const lmmse_plan_desc& d, int slots) {
+    if (slots <= 0) return 0;
+    const size_t fwd = sample_workspace_bytes(d, slots), per = sb_layout(d, 1).total;
+    const size_t c = per ? fwd / per : (size_t)slots;
+    return (int)std::min<size_t>(std::max<size_t>(c, 1), (size_t)slots);
+}
+
+size_t dlam_bytes(const lmmse_plan_desc& d, int slots) {
+    return up256((size_t)slots * d.K * (d.N / d.B) * sizeof(double));
+}
+
+ZView hview(const lmmse_plan_desc& d, const float2* p, const int* tab, long long s_blk, int conj,
+            bool transposed) {
+    // element (row, col) = (window or block row, antenna), or its transpose
+    ZView v{};
+    v.p = p;
+    const long long ms = (long long)d.K * d.N;
+    v.rs = transposed ? ms : 1;
+    v.cs = transposed ? 1 : ms;
+    v.s_slot = (long long)d.M * d.K * d.N;
+    v.s_user = d.N;
+    v.s_blk = s_blk;
+    v.blk_tab = tab;
+    v.conj = conj;
+    return v;
+}
+
+ZView wview(const void* p, const lmmse_plan_desc& d, int rows, int cols, bool conj_t) {
+    // per-window buffer [mat][rows][cols]; conj_t: the conjugate transpose
+    ZView v{};
+    v.p = p;
+    const long long per = (long long)rows * cols;
+    v.rs = conj_t ? 1 : cols;
+    v.cs = conj_t ? cols : 1;
+    v.s_blk = per;
+    v.s_user = per * (d.N / d.B);
+    v.s_slot = v.s_user * d.K;
+    v.blk_tab = nullptr;
+    v.conj = conj_t ? 1 : 0;
+    return v;
+}
+}  // namespace
+
+size_t sample_backward_workspace_bytes(const lmmse_plan_desc& d, int slots) {
+    if (slots <= 0) return 0;
+    return dlam_bytes(d, slots) + sb_layout(d, sb_chunk(d, slots)).total;
+}
+
+hipError_t launch_backward_sample(Plan& p, int slots, const float2* hls, const float2* g,
+                                  float2* dhls, double lam, bool want_sigma, void* ws,
+                                  hipStream_t st) {
+    const lmmse_plan_desc& d = p.d;
+    if ((long long)slots * d.K * p.nb == 0) return hipSuccess;
+    const int chunk = sb_chunk(d, slots);
+    const SbLayout L = sb_layout(d, chunk);
+    char* w = (char*)ws;
+    double* dlam = (double*)w;
+    w += dlam_bytes(d, slots);
+    double2* ainv = (double2*)(w + L.ainv);   // A^-1, then Gam
+    double2* w64 = (double2*)(w + L.w64);
+    double2* dw = (double2*)(w + L.dw);
+    double2* z = (double2*)(w + L.z);
+    float2* dxw = (float2*)(w + L.dxw);
+    const int B = d.B, Wn = d.Wn, M = d.M;
+    const long long per_slot = (long long)M * d.K * d.N;
+    hipError_t e;
+
+    for (int s0 = 0; s0 < slots; s0 += chunk) {
+        const int ns = std::min(chunk, slots - s0);
+        const long long nmat = (long long)ns * d.K * p.nb, mat0 = (long long)s0 * d.K * p.nb;
+        const float2* hc = hls + s0 * per_slot;
+        const float2* gc = g + s0 * per_slot;
+
+        e = launch_sample_inverse(p, nmat, mat0, hc, lam, w64, ainv, st);
+        if (e != hipSuccess) return e;
+
+        ZGemmArgs ga{};
+        ga.K = d.K;
+        ga.nb = p.nb;
+        // dW = G X^H
+        ga.A = hview(d, gc, nullptr, B, 0, false);
+        ga.B = hview(d, hc, p.d_starts, 1, 1, true);
+        ga.C = wview(dw, d, B, Wn, false);
+        ga.m = B;
+        ga.n = Wn;
+        ga.kd = M;
+        ga.alpha = 1.0;
+        ga.beta = 0;
+        if ((e = zgemm<float2, float2, double2>(ga, nmat, st)) != hipSuccess) return e;
+        // Z = dW A^-1
+        ga.A = wview(dw, d, B, Wn, false);
+        ga.B = wview(ainv, d, Wn, Wn, false);
+        ga.C = wview(z, d, B, Wn, false);
+        ga.kd = Wn;
+        if ((e = zgemm<double2, double2, double2>(ga, nmat, st)) != hipSuccess) return e;
+        // Gam = -W^H Z (over A^-1, which is no longer needed)
+        ga.A = wview(w64, d, B, Wn, true);
+        ga.B = wview(z, d, B, Wn, false);
+        ga.C = wview(ainv, d, Wn, Wn, false);
+        ga.m = Wn;
+        ga.n = Wn;
+        ga.kd = B;
+        ga.alpha = -1.0;
+        if ((e = zgemm<double2, double2, double2>(ga, nmat, st)) != hipSuccess) return e;
+        hipLaunchKernelGGL(gamma_rows_kernel, dim3((unsigned)nmat), dim3(256), 0, st, ainv, z,
+                           p.d_offsets, dlam + mat0, B, Wn, p.nb);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        // per-window dX, stored [mat][m][j]: W^H G, + Gam X / M, + Gam^H X / M
+        ZView cx{};
+        cx.p = dxw;
+        cx.rs = 1;
+        cx.cs = Wn;
+        cx.s_blk = (long long)M * Wn;
+        cx.s_user = cx.s_blk * p.nb;
+        cx.s_slot = cx.s_user * d.K;
+        ga.A = wview(w64, d, B, Wn, true);
+        ga.B = hview(d, gc, nullptr, B, 0, false);
+        ga.C = cx;
+        ga.m = Wn;
+        ga.n = M;
+        ga.kd = B;
+        ga.alpha = 1.0;
+        ga.beta = 0;
+        if ((e = zgemm<double2, float2, float2>(ga, nmat, st)) != hipSuccess) return e;
+        ga.A = wview(ainv, d, Wn, Wn, false);
+        ga.B = hview(d, hc, p.d_starts, 1, 0, false);
+        ga.kd = Wn;
+        ga.alpha = 1.0 / M;
+        ga.beta = 1;
+        if ((e = zgemm<double2, float2, float2>(ga, nmat, st)) != hipSuccess) return e;
+        ga.A = wview(ainv, d, Wn, Wn, true);
+        if ((e = zgemm<double2, float2, float2>(ga, nmat, st)) != hipSuccess) return e;
+
+        const long long total = ns * per_slot;
+        hipLaunchKernelGGL(combine_windows_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256),
+                           0, st, dxw, p.d_starts, dhls + s0 * per_slot, M, d.K, d.N, B, Wn, p.nb,
+                           total);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (want_sigma) {
+        hipLaunchKernelGGL(dlam_sum_kernel, dim3(1), dim3(256), 0, st, dlam,
+                           (long long)slots * d.K * p.nb, p.dscal);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace lmmse

@@ -92,6 +92,11 @@ hipError_t launch_batched_filters(const Plan& p, int nmat, double2* a_work, doub
 hipError_t launch_sample_estimate(const Plan& p, int slots, const float2* hls, double lam,
                                   float2* out, void* ws, hipStream_t st);
 size_t sample_workspace_bytes(const lmmse_plan_desc& d, int slots);
+// Per (slot, user, block) window of the sample design: W (FP64 [nmat][B][Wn])
+// and A^-1 = (R + lam I)^-1 (FP64 [nmat][Wn][Wn], both triangles).
+hipError_t launch_sample_inverse(const Plan& p, long long nmat, long long mat0, const float2* hls,
+                                 double lam, double2* w64, double2* ainv, hipStream_t st);
+size_t sample_backward_workspace_bytes(const lmmse_plan_desc& d, int slots);
 
 // Backward.
 size_t backward_workspace_bytes(const lmmse_plan_desc& d, int slots);

@@ -291,6 +291,12 @@ int lmmse_plan_get_desc(lmmse_plan_t plan, lmmse_plan_desc* out) {
 
 int lmmse_set_design(lmmse_plan_t plan, double tau_rms, double sigma2, void* stream) {
     if (!plan) return LMMSE_ERR_INVALID_ARG;
+    if (plan->d.rsource == LMMSE_R_SAMPLE) {
+        // only the noise variance: the filters come from each batch's data
+        if (!(sigma2 > 0.0) || !std::isfinite(sigma2)) return LMMSE_ERR_INVALID_ARG;
+        plan->design_sigma2 = sigma2;
+        return LMMSE_OK;
+    }
     if (!fixed_source(plan->d.rsource)) return LMMSE_ERR_UNSUPPORTED;
     if (!(sigma2 > 0.0) || !std::isfinite(sigma2)) return LMMSE_ERR_INVALID_ARG;
     if (plan->d.rsource == LMMSE_R_EXPONENTIAL && (!(tau_rms > 0.0) || !std::isfinite(tau_rms)))
@@ -404,6 +410,30 @@ int lmmse_estimate(lmmse_plan_t plan, int slots, const void* y, const void* pilo
     if (!ws || ws_bytes < hls_bytes(plan->d, slots)) return LMMSE_ERR_WORKSPACE;
     LMMSE_HIP_TRY(launch_despread(*plan, slots, (const float2*)y, (const float2*)pilots, (float2*)ws, st));
     return apply_dispatch(plan, slots, (const float2*)ws, nullptr, false, (float2*)h_hat, st);
+}
+
+int lmmse_estimate_ls(lmmse_plan_t plan, int slots, const void* h_ls, double sigma2, void* h_hat,
+                      void* ws, size_t ws_bytes, void* stream) {
+    if (!plan || slots < 0 || slots > plan->d.max_slots) return LMMSE_ERR_INVALID_ARG;
+    if (!(sigma2 > 0.0) || !std::isfinite(sigma2)) return LMMSE_ERR_INVALID_ARG;
+    if (slots == 0) return LMMSE_OK;
+    if (!h_ls || !h_hat) return LMMSE_ERR_INVALID_ARG;
+    const hipStream_t st = (hipStream_t)stream;
+    if (plan->d.rsource == LMMSE_R_SAMPLE) {
+        // same workspace layout as lmmse_estimate; its LS area stays unused
+        if (!ws || ws_bytes < sample_workspace_bytes(plan->d, slots)) return LMMSE_ERR_WORKSPACE;
+        plan->design_sigma2 = sigma2;
+        LMMSE_HIP_TRY(launch_sample_estimate(*plan, slots, (const float2*)h_ls, sigma2 / plan->d.K,
+                                             (float2*)h_hat, (char*)ws + hls_bytes(plan->d, slots),
+                                             st));
+        return LMMSE_OK;
+    }
+    if (fixed_source(plan->d.rsource) && sigma2 != plan->design_sigma2) {
+        const int rc = lmmse_set_design(plan, plan->design_tau, sigma2, stream);
+        if (rc != LMMSE_OK) return rc;
+    }
+    if (!plan->ready) return LMMSE_ERR_NOT_READY;
+    return apply_dispatch(plan, slots, (const float2*)h_ls, nullptr, false, (float2*)h_hat, st);
 }
 
 int lmmse_backward(lmmse_plan_t plan, int slots, const void* h_ls, const void* g, void* d_hls,

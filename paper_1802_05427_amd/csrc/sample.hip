@@ -44,12 +44,14 @@ struct SampleArgs {
     double2* r_out;         // optional: R (before lam) [mat][Wn][Wn]
     double2* w64;           // optional: W [mat][B][Wn]
     float2* w32;            // optional: W [mat][B][Wp], Wp = Wn rounded up to even (pad 0)
+    double2* ainv;          // optional: A^-1 [mat][Wn][Wn] (row-major, both triangles)
     const int* starts;
     const int* offsets;
     int* status;
     int M, K, N, B, Wn, nb;
     double lam;
     int want_w;
+    long long mat0;         // index of the first matrix (error reports)
 };
 
 // Entry index of kept block (P, Q), P >= Q.
@@ -181,7 +183,7 @@ __global__ __launch_bounds__(1024) void sample_design_kernel(SampleArgs a) {
             const double d = cc[kp].x;                                                     \
             if (!(d > 0.0) || !isfinite(d)) {                                              \
                 if (tid == 0 && atomicCAS(a.status, 0, LMMSE_ERR_NOT_PD) == 0)             \
-                    a.status[1] = (int)mat;                                                \
+                    a.status[1] = (int)(mat + a.mat0);                                                \
                 ok = false; /* every thread reads the same d: uniform exit */              \
                 break;                                                                     \
             }                                                                              \
@@ -227,6 +229,11 @@ __global__ __launch_bounds__(1024) void sample_design_kernel(SampleArgs a) {
             const int i = 32 * P + tr, j = 32 * Q + tc;
             if (i >= n || j >= n) continue;
             const double2 v = A[blk(P, Q)];
+            if (a.ainv) {
+                double2* ai = a.ainv + mat * n * n;
+                ai[(long long)i * n + j] = make_double2(-v.x, -v.y);
+                if (P > Q) ai[(long long)j * n + i] = make_double2(-v.x, v.y);
+            }
             // entry (i, j) and, off the diagonal blocks, its mirror (j, i)
 #pragma unroll
             for (int side = 0; side < (P > Q ? 2 : 1); ++side) {
@@ -471,6 +478,17 @@ hipError_t launch_batched_filters(const Plan& p, int nmat, double2*, double2*, c
     SampleArgs sa = base_args(p, lam);
     sa.r_in = r_win;
     sa.w64 = w_out;
+    sa.want_w = 1;
+    return launch_sample_design(p, nmat, sa, st);
+}
+
+hipError_t launch_sample_inverse(const Plan& p, long long nmat, long long mat0, const float2* hls,
+                                 double lam, double2* w64, double2* ainv, hipStream_t st) {
+    SampleArgs sa = base_args(p, lam);
+    sa.mat0 = mat0;
+    sa.hls = hls;
+    sa.w64 = w64;
+    sa.ainv = ainv;
     sa.want_w = 1;
     return launch_sample_design(p, nmat, sa, st);
 }

@@ -53,8 +53,10 @@ def test_backward_matches_oracle_and_fd(dev, c):
     args = (c["B"], c["Wn"], tau, c["taps"], c["N_fft"], sig, K)
     with Plan(M=c["M"], K=K, N=c["N"], N_fft=c["N_fft"], B=c["B"], Wn=c["Wn"], rsource="exp",
               taps=c["taps"], tau_rms=tau, sigma2=sig, max_slots=c["slots"]) as plan:
-        h = plan.despread(_t(sb.y, dev), _t(sb.pilots, dev))
-        X = h.cpu().numpy().astype(np.complex128)
+        # the same complex64 LS values (the oracle's despreading) feed both sides
+        X32 = O.despread(sb.y, sb.pilots).astype(np.complex64)
+        h = _t(X32, dev)
+        X = X32.astype(np.complex128)
         L0, G = _oracle_loss(X, sb.H, *args)
         d_hls, d_tau, d_sig = plan.backward(h, _t(G.astype(np.complex64), dev))
         d_hls = d_hls.cpu().numpy()
@@ -84,19 +86,20 @@ def test_autograd_function(dev):
                          snr_db=10.0, slots=c["slots"], config_id=3)
     with Plan(M=c["M"], K=c["K"], N=c["N"], N_fft=c["N_fft"], B=c["B"], Wn=c["Wn"], rsource="exp",
               taps=c["taps"], tau_rms=4.0, sigma2=0.05, max_slots=c["slots"]) as plan:
-        h = plan.despread(_t(sb.y, dev), _t(sb.pilots, dev)).requires_grad_(True)
+        X32 = O.despread(sb.y, sb.pilots).astype(np.complex64)
+        h = _t(X32, dev).requires_grad_(True)
         tau = torch.tensor(4.5, dtype=torch.float64, requires_grad=True)
         sig = torch.tensor(0.02, dtype=torch.float64, requires_grad=True)
         H = _t(sb.H.astype(np.complex64), dev)
         out = LmmseFn.apply(h, tau, sig, plan)
         loss = (out - H).abs().pow(2).sum() / out.numel()
         loss.backward()
-        X = h.detach().cpu().numpy().astype(np.complex128)
+        X = X32.astype(np.complex128)
         L0, G = _oracle_loss(X, sb.H.astype(np.complex64).astype(np.complex128), c["B"], c["Wn"], 4.5,
                              c["taps"], c["N_fft"], 0.02, c["K"])
         dX_o, gtau_o, gsig_o = O.grad_fixed_design(X, G, c["B"], c["Wn"], 4.5, c["taps"], c["N_fft"], 0.02,
                                                    c["K"])
-    assert abs(float(loss) - L0) <= 1e-5 * L0
+    assert abs(float(loss.detach()) - L0) <= 1e-5 * L0
     assert abs(float(tau.grad) - gtau_o) <= 1e-3 * abs(gtau_o)
     assert abs(float(sig.grad) - gsig_o) <= 1e-3 * abs(gsig_o)
     ex = np.linalg.norm(h.grad.cpu().numpy() - dX_o) / np.linalg.norm(dX_o)

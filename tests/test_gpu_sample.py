@@ -47,9 +47,10 @@ def test_covariance_and_filters_fp64(dev, c):
     lam = sb.sigma2 / c["K"]
     starts, offs = O.window_starts(c["N"], c["B"], c["Wn"])
     with _plan(c, sb.sigma2) as plan:
-        hls = plan.despread(_t(sb.y, dev), _t(sb.pilots, dev))
-        # the covariance is checked on the GPU's own LS values (complex64)
-        hls_ref = hls.cpu().numpy().astype(np.complex128)
+        # the same complex64 LS values (the oracle's despreading) feed both sides
+        X32 = O.despread(sb.y, sb.pilots).astype(np.complex64)
+        hls = _t(X32, dev)
+        hls_ref = X32.astype(np.complex128)
         r = plan.covariance(hls)
         w = plan.sample_filters(r, sb.sigma2).cpu().numpy()
         # filters from the oracle's own covariances: the design step alone

@@ -1,0 +1,136 @@
+"""GPU gradients of the sample-covariance estimator (the filter of every
+(slot, user, window) designed from that window's own covariance) against
+the FP64 oracle's hand-derived gradients, FP64 central finite differences of
+the oracle loss in sigma2 (relative step 1e-4), through the C ABI and
+through SampleLmmseFn.  Both sides read the same complex64 LS values, the
+oracle's despreading of seeded synthetic slots."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1802_05427_amd import Plan
+from paper_1802_05427_amd.autograd import SampleLmmseFn
+from synth import make_slot_batch
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-3      # gradients within 1e-3 relative of finite differences
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _t(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _oracle_estimate(X, B, Wn, sigma2):
+    """Sample-covariance estimate, block by block (eq. 13 on each window)."""
+    S, M, K, N = X.shape
+    lam = sigma2 / K
+    out = np.zeros_like(X)
+    starts, offs = O.window_starts(N, B, Wn)
+    for s in range(S):
+        for k in range(K):
+            for b, (st, off) in enumerate(zip(starts, offs)):
+                Xw = X[s, :, k, st:st + Wn]
+                R = O.sample_covariance(Xw)
+                W = O.lmmse._filter(R[off:off + B], R, lam)
+                out[s, :, k, b * B:(b + 1) * B] = Xw @ W.T
+    return out
+
+
+CASES = [
+    dict(M=8, K=2, N=72, N_fft=128, taps=8, tau=2.0, B=12, Wn=24, slots=2),      # overlap, M < Wn
+    dict(M=6, K=2, N=72, N_fft=128, taps=8, tau=3.0, B=12, Wn=12, slots=2),      # non-overlapping
+    dict(M=6, K=3, N=99, N_fft=128, taps=8, tau=2.0, B=9, Wn=21, slots=3),       # odd B, odd Wn
+    dict(M=70, K=2, N=240, N_fft=256, taps=12, tau=3.0, B=60, Wn=120, slots=1),  # several GEMM tiles
+    dict(M=20, K=3, N=1200, N_fft=2048, taps=72, tau=4.0, B=100, Wn=150, slots=1),
+]
+
+
+@pytest.mark.parametrize("c", CASES)
+def test_sample_backward_matches_oracle_and_fd(dev, c):
+    print(f"sample backward {c}", flush=True)
+    sb = make_slot_batch(M=c["M"], K=c["K"], N=c["N"], N_fft=c["N_fft"], taps=c["taps"], tau=c["tau"],
+                         snr_db=10.0, slots=c["slots"], config_id=4)
+    B, Wn, sig = c["B"], c["Wn"], 0.05
+    X32 = O.despread(sb.y, sb.pilots).astype(np.complex64)
+    X = X32.astype(np.complex128)
+    L0, G = O.mse_loss_and_grad(_oracle_estimate(X, B, Wn, sig), sb.H)
+    G32 = G.astype(np.complex64)
+    with Plan(M=c["M"], K=c["K"], N=c["N"], N_fft=c["N_fft"], B=B, Wn=Wn, rsource="sample",
+              sigma2=sig, max_slots=c["slots"]) as plan:
+        plan.set_design(float("nan"), sig)
+        d_hls, d_tau, d_sig = plan.backward(_t(X32, dev), _t(G32, dev))
+        st, info = plan.sync_status()
+        d_hls = d_hls.cpu().numpy()
+    assert st == 0, (st, info)
+    dX_o, gsig_o = O.grad_sample_cov(X, G32.astype(np.complex128), B, Wn, sig)
+    ex = np.linalg.norm(d_hls - dX_o) / np.linalg.norm(dX_o)
+    print(f"  dX rel {ex:.2e}  dsig gpu {d_sig:.8e} oracle {gsig_o:.8e}", flush=True)
+    assert np.isnan(d_tau)
+    assert ex < 1e-5
+    assert abs(d_sig - gsig_o) <= 1e-6 * abs(gsig_o)
+    hh = 1e-4
+    fd = (O.mse_loss_and_grad(_oracle_estimate(X, B, Wn, sig * (1 + hh)), sb.H)[0]
+          - O.mse_loss_and_grad(_oracle_estimate(X, B, Wn, sig * (1 - hh)), sb.H)[0]) / (2 * hh * sig)
+    assert abs(d_sig - fd) <= REL * abs(fd)
+
+
+def test_sample_backward_is_not_the_fixed_formula(dev):
+    """The filter depends on h_ls through R: W^H G alone differs from the gradient."""
+    c = CASES[0]
+    sb = make_slot_batch(M=c["M"], K=c["K"], N=c["N"], N_fft=c["N_fft"], taps=c["taps"], tau=c["tau"],
+                         snr_db=10.0, slots=1, config_id=4)
+    X32 = O.despread(sb.y, sb.pilots).astype(np.complex64)
+    G32 = (np.random.default_rng(5).standard_normal(X32.shape)
+           + 1j * np.random.default_rng(6).standard_normal(X32.shape)).astype(np.complex64)
+    with Plan(M=c["M"], K=c["K"], N=c["N"], N_fft=c["N_fft"], B=c["B"], Wn=c["Wn"], rsource="sample",
+              sigma2=0.05, max_slots=1) as plan:
+        plan.set_design(float("nan"), 0.05)
+        d_hls = plan.backward(_t(X32, dev), _t(G32, dev), want_params=False)[0].cpu().numpy()
+    X = X32.astype(np.complex128)
+    G = G32.astype(np.complex128)
+    lam = 0.05 / c["K"]
+    starts, offs = O.window_starts(c["N"], c["B"], c["Wn"])
+    fixed_only = np.zeros_like(X)
+    for k in range(c["K"]):
+        for b, (st, off) in enumerate(zip(starts, offs)):
+            Xw = X[0, :, k, st:st + c["Wn"]]
+            R = O.sample_covariance(Xw)
+            W = O.lmmse._filter(R[off:off + c["B"]], R, lam)
+            fixed_only[0, :, k, st:st + c["Wn"]] += G[0, :, k, b * c["B"]:(b + 1) * c["B"]] @ np.conj(W)
+    dX_o, _ = O.grad_sample_cov(X, G, c["B"], c["Wn"], 0.05)
+    assert np.linalg.norm(d_hls - dX_o) < 1e-5 * np.linalg.norm(dX_o)
+    assert np.linalg.norm(d_hls - fixed_only) > 1e-3 * np.linalg.norm(dX_o)
+
+
+def test_sample_autograd_function(dev):
+    c = CASES[2]
+    sb = make_slot_batch(M=c["M"], K=c["K"], N=c["N"], N_fft=c["N_fft"], taps=c["taps"], tau=c["tau"],
+                         snr_db=10.0, slots=c["slots"], config_id=4)
+    X32 = O.despread(sb.y, sb.pilots).astype(np.complex64)
+    X = X32.astype(np.complex128)
+    H32 = sb.H.astype(np.complex64)
+    with Plan(M=c["M"], K=c["K"], N=c["N"], N_fft=c["N_fft"], B=c["B"], Wn=c["Wn"], rsource="sample",
+              sigma2=0.05, max_slots=c["slots"]) as plan:
+        h = _t(X32, dev).requires_grad_(True)
+        sig = torch.tensor(0.03, dtype=torch.float64, requires_grad=True)
+        out = SampleLmmseFn.apply(h, sig, plan)
+        loss = (out - _t(H32, dev)).abs().pow(2).sum() / out.numel()
+        loss.backward()
+        est = out.detach().cpu().numpy()
+    ref = _oracle_estimate(X, c["B"], c["Wn"], 0.03)
+    L0, G = O.mse_loss_and_grad(ref, H32.astype(np.complex128))
+    dX_o, gsig_o = O.grad_sample_cov(X, G, c["B"], c["Wn"], 0.03)
+    assert O.discrepancy_db(est, ref) < -100
+    assert abs(float(loss.detach()) - L0) <= 1e-5 * L0
+    assert abs(float(sig.grad) - gsig_o) <= 1e-3 * abs(gsig_o)
+    ex = np.linalg.norm(h.grad.cpu().numpy() - dX_o) / np.linalg.norm(dX_o)
+    assert ex < 1e-4
