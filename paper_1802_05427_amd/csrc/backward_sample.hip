@@ -11,152 +11,15 @@
 // fixed order (overlapping windows add), so the result does not depend on
 // scheduling.
 //
-// The window products are batched complex GEMMs with FP64 accumulation on the
-// vector units (the solve-side products Z and Gam need FP64; the others reuse
-// the same kernel).  Each operand is a strided view into h_ls, g or a
-// per-window buffer.
+// The window products are batched complex GEMMs with FP64 accumulation
+// (zgemm.h; the solve-side products Z and Gam need FP64, the others reuse the
+// same kernel).  Each operand is a strided view into h_ls, g or a per-window
+// buffer.
 #include <algorithm>
 
-#include "internal.h"
+#include "zgemm.h"
 
 namespace lmmse {
-
-// Matrix view: element (r, c) of batch (s, k, b) sits at
-//   p + s*s_slot + k*s_user + (blk_tab ? blk_tab[b] : b)*s_blk + r*rs + c*cs,
-// conjugated when conj is set.
-struct ZView {
-    const void* p;
-    long long rs, cs, s_slot, s_user, s_blk;
-    const int* blk_tab;
-    int conj;
-};
-
-struct ZGemmArgs {
-    ZView A, B, C;       // C = alpha A B (+ C when beta); C.p is written
-    int m, n, kd;        // C is m x n, the contraction has kd terms
-    int K, nb;           // batch index = (s * K + k) * nb + b
-    int tiles_m, tiles_n;
-    double alpha;
-    int beta;
-};
-
-constexpr int zT = 64;    // output tile edge
-constexpr int zKC = 16;   // contraction chunk
-
-__device__ __forceinline__ long long zbase(const ZView& v, long long bat, int K, int nb) {
-    const int b = (int)(bat % nb);
-    const long long sk = bat / nb;
-    const int k = (int)(sk % K);
-    const long long s = sk / K;
-    return s * v.s_slot + k * v.s_user + (long long)(v.blk_tab ? v.blk_tab[b] : b) * v.s_blk;
-}
-
-template <typename T>
-__device__ __forceinline__ double2 zload(const void* p, long long i, int conj) {
-    const T v = reinterpret_cast<const T*>(p)[i];
-    return make_double2((double)v.x, conj ? -(double)v.y : (double)v.y);
-}
-
-template <typename TA, typename TB, typename TC>
-__global__ __launch_bounds__(256) void zgemm_kernel(ZGemmArgs g) {
-    __shared__ double2 As[zKC][zT];
-    __shared__ double2 Bs[zKC][zT];
-    const int tid = threadIdx.x;
-    long long t = blockIdx.x;
-    const int tn = (int)(t % g.tiles_n);
-    t /= g.tiles_n;
-    const int tm = (int)(t % g.tiles_m);
-    const long long bat = t / g.tiles_m;
-    const int r0 = tm * zT, c0 = tn * zT;
-    const long long abase = zbase(g.A, bat, g.K, g.nb);
-    const long long bbase = zbase(g.B, bat, g.K, g.nb);
-    const long long cbase = zbase(g.C, bat, g.K, g.nb);
-    // loads: consecutive lanes walk the operand's unit-stride index
-    const bool a_rowfast = g.A.rs == 1, b_colfast = g.B.cs == 1;
-    // outputs: consecutive lanes walk C's unit-stride index
-    const bool c_rowfast = g.C.rs == 1;
-    const int tf = tid & 15, ts = tid >> 4;
-    const int ri = c_rowfast ? tf : ts, ci = c_rowfast ? ts : tf;
-
-    double2 acc[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0.0, 0.0);
-
-    double2 pa[4], pb[4];
-    auto fetch = [&](int k0) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int e = tid + 256 * u;
-            const int r = a_rowfast ? (e & 63) : (e >> 4), ka = a_rowfast ? (e >> 6) : (e & 15);
-            const int c = b_colfast ? (e & 63) : (e >> 4), kb = b_colfast ? (e >> 6) : (e & 15);
-            pa[u] = (r0 + r < g.m && k0 + ka < g.kd)
-                        ? zload<TA>(g.A.p, abase + (r0 + r) * g.A.rs + (k0 + ka) * g.A.cs, g.A.conj)
-                        : make_double2(0.0, 0.0);
-            pb[u] = (c0 + c < g.n && k0 + kb < g.kd)
-                        ? zload<TB>(g.B.p, bbase + (k0 + kb) * g.B.rs + (c0 + c) * g.B.cs, g.B.conj)
-                        : make_double2(0.0, 0.0);
-        }
-    };
-    fetch(0);
-    for (int k0 = 0; k0 < g.kd; k0 += zKC) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int e = tid + 256 * u;
-            const int r = a_rowfast ? (e & 63) : (e >> 4), ka = a_rowfast ? (e >> 6) : (e & 15);
-            const int c = b_colfast ? (e & 63) : (e >> 4), kb = b_colfast ? (e >> 6) : (e & 15);
-            As[ka][r] = pa[u];
-            Bs[kb][c] = pb[u];
-        }
-        __syncthreads();
-        if (k0 + zKC < g.kd) fetch(k0 + zKC);
-#pragma unroll 4
-        for (int kk = 0; kk < zKC; ++kk) {
-            double2 av[4], bv[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) av[i] = As[kk][ri + 16 * i];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) bv[j] = Bs[kk][ci + 16 * j];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    acc[i][j].x = fma(av[i].x, bv[j].x, fma(-av[i].y, bv[j].y, acc[i][j].x));
-                    acc[i][j].y = fma(av[i].x, bv[j].y, fma(av[i].y, bv[j].x, acc[i][j].y));
-                }
-        }
-        __syncthreads();
-    }
-    TC* cp = reinterpret_cast<TC*>(const_cast<void*>(g.C.p));
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int r = r0 + ri + 16 * i, c = c0 + ci + 16 * j;
-            if (r >= g.m || c >= g.n) continue;
-            const long long o = cbase + r * g.C.rs + c * g.C.cs;
-            double x = g.alpha * acc[i][j].x, y = g.alpha * acc[i][j].y;
-            if (g.beta) {
-                x += (double)cp[o].x;
-                y += (double)cp[o].y;
-            }
-            if constexpr (sizeof(TC) == sizeof(double2))
-                cp[o] = make_double2(x, y);
-            else
-                cp[o] = make_float2((float)x, (float)y);
-        }
-}
-
-template <typename TA, typename TB, typename TC>
-static hipError_t zgemm(ZGemmArgs g, long long nbat, hipStream_t st) {
-    g.tiles_m = (g.m + zT - 1) / zT;
-    g.tiles_n = (g.n + zT - 1) / zT;
-    const long long blocks = nbat * g.tiles_m * g.tiles_n;
-    if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL((zgemm_kernel<TA, TB, TC>), dim3((unsigned)blocks), dim3(256), 0, st, g);
-    return hipGetLastError();
-}
 
 // Per window: dlam partial = Re tr(Gam) (Gam = -W^H Z as computed so far),
 // then Gam[off + o, :] += Z[o, :].
@@ -239,7 +102,7 @@ size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Per-window buffers of one chunk of slots.
 struct SbLayout {
-    size_t ainv, w64, dw, z, dxw, total;
+    size_t ainv, w64, dw, z, dxw, panel, total;
 };
 
 SbLayout sb_layout(const lmmse_plan_desc& d, int slots) {
@@ -256,6 +119,8 @@ SbLayout sb_layout(const lmmse_plan_desc& d, int slots) {
     o += up256((size_t)nmat * d.B * d.Wn * sizeof(double2));
     L.dxw = o;
     o += up256((size_t)nmat * d.M * d.Wn * sizeof(float2));
+    L.panel = o;   // panel operands of the workspace-resident design (wide windows)
+    if (d.Wn > kMaxSampleWindowReg) o += up256((size_t)nmat * 2 * d.Wn * 32 * sizeof(double2));
     L.total = o;
     return L;
 }
@@ -335,7 +200,7 @@ hipError_t launch_backward_sample(Plan& p, int slots, const float2* hls, const f
         const float2* hc = hls + s0 * per_slot;
         const float2* gc = g + s0 * per_slot;
 
-        e = launch_sample_inverse(p, nmat, mat0, hc, lam, w64, ainv, st);
+        e = launch_sample_inverse(p, nmat, mat0, hc, lam, w64, ainv, (double2*)(w + L.panel), st);
         if (e != hipSuccess) return e;
 
         ZGemmArgs ga{};

@@ -93,10 +93,25 @@ hipError_t launch_sample_estimate(const Plan& p, int slots, const float2* hls, d
                                   float2* out, void* ws, hipStream_t st);
 size_t sample_workspace_bytes(const lmmse_plan_desc& d, int slots);
 // Per (slot, user, block) window of the sample design: W (FP64 [nmat][B][Wn])
-// and A^-1 = (R + lam I)^-1 (FP64 [nmat][Wn][Wn], both triangles).
+// and A^-1 = (R + lam I)^-1 (FP64 [nmat][Wn][Wn], both triangles); scratch:
+// 2 nmat Wn 32 complex doubles, used by windows wider than the register sweep.
 hipError_t launch_sample_inverse(const Plan& p, long long nmat, long long mat0, const float2* hls,
-                                 double lam, double2* w64, double2* ainv, hipStream_t st);
+                                 double lam, double2* w64, double2* ainv, double2* scratch,
+                                 hipStream_t st);
 size_t sample_backward_workspace_bytes(const lmmse_plan_desc& d, int slots);
+// Windows the register-resident sample design holds, and the limit of the
+// workspace-resident one (sample_large.hip) used above it.
+constexpr int kMaxSampleWindowReg = 160;
+constexpr int kMaxSampleWindowLarge = 256;
+// Workspace-resident sample design of nmat windows: amat [nmat][Wn][Wn] and
+// scratch (large_design_bytes minus amat) are device work areas; w64 / w32
+// may be null; with want_ainv amat ends as A^-1.
+size_t large_design_bytes(const lmmse_plan_desc& d, long long nmat);
+hipError_t launch_sample_large(const Plan& p, long long nmat, long long mat0, const float2* hls,
+                               double lam, double2* amat, double2* scratch, double2* w64,
+                               float2* w32, bool want_ainv, hipStream_t st);
+hipError_t launch_covariance_large(const Plan& p, long long nmat, const float2* hls, double2* r_win,
+                                   hipStream_t st);
 
 // Backward.
 size_t backward_workspace_bytes(const lmmse_plan_desc& d, int slots);

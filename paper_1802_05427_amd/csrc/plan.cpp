@@ -18,7 +18,6 @@ namespace {
 
 constexpr int kMaxK = 64;
 constexpr int kMaxWindow = 1344;     // fixed design: 3 Wn complex doubles of LDS (<= 64 KB)
-constexpr int kMaxSampleWindow = 160;  // sample design: window held in registers
 constexpr int kRTs[] = {1, 2, 4, 8, 9, 13, 15, 17};
 
 #define LMMSE_HIP_TRY(expr)                       \
@@ -72,7 +71,7 @@ int validate(const lmmse_plan_desc* d) {
     if (d->Wn > kMaxWindow) return LMMSE_ERR_UNSUPPORTED;
     const long long cols = (long long)d->max_slots * d->M * d->K;
     if (cols * d->N >= (1LL << 40)) return LMMSE_ERR_UNSUPPORTED;
-    if (d->rsource == LMMSE_R_SAMPLE && d->Wn > kMaxSampleWindow) return LMMSE_ERR_UNSUPPORTED;
+    if (d->rsource == LMMSE_R_SAMPLE && d->Wn > kMaxSampleWindowLarge) return LMMSE_ERR_UNSUPPORTED;
     return LMMSE_OK;
 }
 
@@ -359,7 +358,7 @@ int lmmse_apply(lmmse_plan_t plan, int slots, const void* h_ls, void* h_hat, voi
 
 int lmmse_covariance(lmmse_plan_t plan, int slots, const void* h_ls, void* r_win, void* stream) {
     if (!plan || slots < 0 || slots > plan->d.max_slots) return LMMSE_ERR_INVALID_ARG;
-    if (plan->d.Wn > kMaxSampleWindow) return LMMSE_ERR_UNSUPPORTED;
+    if (plan->d.Wn > kMaxSampleWindowLarge) return LMMSE_ERR_UNSUPPORTED;
     if (slots == 0) return LMMSE_OK;
     if (!h_ls || !r_win) return LMMSE_ERR_INVALID_ARG;
     LMMSE_HIP_TRY(launch_covariance(*plan, slots, (const float2*)h_ls, (double2*)r_win,
@@ -371,7 +370,7 @@ int lmmse_sample_filters(lmmse_plan_t plan, int slots, const void* r_win, double
                          void* w_out, void* stream) {
     if (!plan || slots < 0 || slots > plan->d.max_slots) return LMMSE_ERR_INVALID_ARG;
     if (!(sigma2 >= 0.0) || !std::isfinite(sigma2)) return LMMSE_ERR_INVALID_ARG;
-    if (plan->d.Wn > kMaxSampleWindow) return LMMSE_ERR_UNSUPPORTED;
+    if (plan->d.Wn > kMaxSampleWindowReg) return LMMSE_ERR_UNSUPPORTED;
     if (slots == 0) return LMMSE_OK;
     if (!r_win || !w_out) return LMMSE_ERR_INVALID_ARG;
     const int nmat = slots * plan->d.K * plan->nb;

@@ -27,6 +27,8 @@
 // streamed in 16-row chunks into two LDS buffers by the direct global-to-LDS
 // loads, and each MFMA's real-embedded operand is built in registers from one
 // 16-byte complex pair.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace lmmse {
@@ -466,6 +468,8 @@ static SampleArgs base_args(const Plan& p, double lam) {
 
 hipError_t launch_covariance(const Plan& p, int slots, const float2* hls, double2* r_win,
                              hipStream_t st) {
+    if (p.d.Wn > kMaxSampleWindowReg)
+        return launch_covariance_large(p, (long long)slots * p.d.K * p.nb, hls, r_win, st);
     SampleArgs sa = base_args(p, 0.0);
     sa.hls = hls;
     sa.r_out = r_win;
@@ -483,7 +487,10 @@ hipError_t launch_batched_filters(const Plan& p, int nmat, double2*, double2*, c
 }
 
 hipError_t launch_sample_inverse(const Plan& p, long long nmat, long long mat0, const float2* hls,
-                                 double lam, double2* w64, double2* ainv, hipStream_t st) {
+                                 double lam, double2* w64, double2* ainv, double2* scratch,
+                                 hipStream_t st) {
+    if (p.d.Wn > kMaxSampleWindowReg)
+        return launch_sample_large(p, nmat, mat0, hls, lam, ainv, scratch, w64, nullptr, true, st);
     SampleArgs sa = base_args(p, lam);
     sa.mat0 = mat0;
     sa.hls = hls;
@@ -493,11 +500,26 @@ hipError_t launch_sample_inverse(const Plan& p, long long nmat, long long mat0, 
     return launch_sample_design(p, nmat, sa, st);
 }
 
+// Slots per design chunk of the workspace-resident design (wide windows):
+// up to 2 GiB of window matrices at a time, at least one slot.
+static int large_chunk(const lmmse_plan_desc& d, int slots) {
+    if (slots <= 0) return 0;
+    const size_t per = large_design_bytes(d, (long long)d.K * (d.N / d.B));
+    const size_t c = per ? ((size_t)2 << 30) / per : (size_t)slots;
+    return (int)std::min<size_t>(std::max<size_t>(c, 1), (size_t)slots);
+}
+
+static size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
+
 size_t sample_workspace_bytes(const lmmse_plan_desc& d, int slots) {
-    // H_LS, then the compact FP32 filters of every (slot, user, block)
+    // H_LS, the compact FP32 filters of every (slot, user, block), and for
+    // wide windows the design work area of one chunk of slots
     const size_t hls = hls_bytes(d, slots);
-    const size_t w = (size_t)slots * d.K * (d.N / d.B) * d.B * ((d.Wn + 1) & ~1) * sizeof(float2);
-    return hls + w;
+    const size_t w = up256((size_t)slots * d.K * (d.N / d.B) * d.B * ((d.Wn + 1) & ~1) * sizeof(float2));
+    size_t big = 0;
+    if (d.Wn > kMaxSampleWindowReg && slots > 0)
+        big = large_design_bytes(d, (long long)large_chunk(d, slots) * d.K * (d.N / d.B));
+    return hls + w + big;
 }
 
 hipError_t launch_sample_estimate(const Plan& p, int slots, const float2* hls, double lam,
@@ -505,12 +527,31 @@ hipError_t launch_sample_estimate(const Plan& p, int slots, const float2* hls, d
     const long long nmat = (long long)slots * p.d.K * p.nb;
     if (nmat == 0) return hipSuccess;
     float2* w32 = reinterpret_cast<float2*>(ws);
-    SampleArgs sa = base_args(p, lam);
-    sa.hls = hls;
-    sa.w32 = w32;
-    sa.want_w = 1;
-    hipError_t e = launch_sample_design(p, nmat, sa, st);
-    if (e != hipSuccess) return e;
+    hipError_t e;
+    if (p.d.Wn > kMaxSampleWindowReg) {
+        const size_t wbytes =
+            up256((size_t)nmat * p.d.B * ((p.d.Wn + 1) & ~1) * sizeof(float2));
+        const int chunk = large_chunk(p.d, slots);
+        const long long cm = (long long)chunk * p.d.K * p.nb;
+        double2* amat = reinterpret_cast<double2*>((char*)ws + wbytes);
+        double2* scratch = amat + cm * p.d.Wn * p.d.Wn;
+        const long long per_slot = (long long)p.d.M * p.d.K * p.d.N;
+        const int wp = (p.d.Wn + 1) & ~1;
+        for (int s0 = 0; s0 < slots; s0 += chunk) {
+            const int ns = std::min(chunk, slots - s0);
+            const long long m0 = (long long)s0 * p.d.K * p.nb;
+            e = launch_sample_large(p, (long long)ns * p.d.K * p.nb, m0, hls + s0 * per_slot, lam, amat,
+                                    scratch, nullptr, w32 + m0 * p.d.B * wp, false, st);
+            if (e != hipSuccess) return e;
+        }
+    } else {
+        SampleArgs sa = base_args(p, lam);
+        sa.hls = hls;
+        sa.w32 = w32;
+        sa.want_w = 1;
+        e = launch_sample_design(p, nmat, sa, st);
+        if (e != hipSuccess) return e;
+    }
     SampleApplyArgs aa{};
     aa.hls = hls;
     aa.w32 = w32;

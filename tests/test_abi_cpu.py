@@ -70,7 +70,7 @@ def test_validate_accepts_workloads(lib, kw):
     (dict(B=7), _lib.UNSUPPORTED), (dict(Wn=151), _lib.UNSUPPORTED), (dict(Wn=80), _lib.UNSUPPORTED),
     (dict(Wn=1300), _lib.UNSUPPORTED), (dict(K=65), _lib.UNSUPPORTED),
     (dict(rsource="sample", B=300, Wn=300), _lib.UNSUPPORTED),
-    (dict(rsource="sample", B=100, Wn=200), _lib.UNSUPPORTED),
+    (dict(rsource="sample", B=100, Wn=300), _lib.UNSUPPORTED),
 ])
 def test_validate_rejects(lib, kw, code):
     d = _d(**kw)
@@ -133,8 +133,6 @@ def test_workspace_sizes():
 @pytest.mark.parametrize("kw", [dict(), dict(K=3), dict(B=132, Wn=198, N=3300, N_fft=4096, K=24, M=2)])
 def test_workspace_size_of_an_empty_batch(rsource, kw):
     """Zero slots (and every smaller batch) must size without faulting."""
-    if rsource == "sample" and kw.get("Wn", 150) > 160:
-        pytest.skip("sample covariance needs Wn <= 160")
     d = _d(rsource=rsource, **kw)
     assert workspace_size(d, 0) >= 0
     for s in (1, 2, 3):
@@ -149,3 +147,18 @@ def test_plan_create_without_device_fails_cleanly(lib):
     h = ctypes.c_void_p()
     assert lib.lmmse_plan_create(ctypes.byref(d), ctypes.byref(h)) == _lib.NO_DEVICE
     assert not h.value
+
+
+def test_sample_window_limits():
+    """The sample design holds windows up to 256 (registers up to 160, then the
+    workspace-resident sweep); wider windows are rejected on the host."""
+    d = _d(rsource="sample", N=3300, N_fft=4096, B=132, Wn=198, K=24, M=256, max_slots=32)
+    need = workspace_size(d, 32)
+    # at least H_LS, the FP32 filters and one slot of FP64 window matrices
+    nmat1 = 24 * 25
+    assert need >= 32 * 256 * 24 * 3300 * 8 + 32 * nmat1 * 132 * 198 * 8 + nmat1 * 198 * 198 * 16
+    # the design works through the slots in chunks of at most about 2 GiB
+    assert need < 32 * 256 * 24 * 3300 * 8 + 32 * nmat1 * 132 * 198 * 8 + (3 << 30) \
+        + 32 * nmat1 * 8 + (1 << 20)
+    with pytest.raises(_lib.LmmseError):
+        workspace_size(_d(rsource="sample", N=1040, B=130, Wn=260), 1)

@@ -34,6 +34,14 @@ CASES = [
 ]
 
 
+# windows wider than the register-resident sweep (workspace-resident design)
+LARGE = [
+    dict(M=20, K=2, N=400, N_fft=512, taps=16, tau=4.0, B=100, Wn=200, slots=2),   # M < Wn
+    dict(M=16, K=2, N=3300, N_fft=4096, taps=144, tau=32.0, B=132, Wn=198, slots=1),
+    dict(M=260, K=1, N=480, N_fft=512, taps=16, tau=4.0, B=120, Wn=240, slots=1),  # ragged M
+]
+
+
 def _plan(c, sigma2):
     return Plan(M=c["M"], K=c["K"], N=c["N"], N_fft=c["N_fft"], B=c["B"], Wn=c["Wn"],
                 rsource="sample", sigma2=sigma2, max_slots=c["slots"])
@@ -77,7 +85,25 @@ def test_covariance_and_filters_fp64(dev, c):
                 assert e1 < 1e-9 and e2 < 1e-9, (s, k, b, e1, e2)
 
 
-@pytest.mark.parametrize("c", CASES)
+@pytest.mark.parametrize("c", LARGE)
+def test_covariance_wide_windows(dev, c):
+    print(f"sample covariance {c}", flush=True)
+    sb = make_slot_batch(M=c["M"], K=c["K"], N=c["N"], N_fft=c["N_fft"], taps=c["taps"], tau=c["tau"],
+                         snr_db=10.0, slots=c["slots"], config_id=1)
+    X32 = O.despread(sb.y, sb.pilots).astype(np.complex64)
+    X = X32.astype(np.complex128)
+    starts, _ = O.window_starts(c["N"], c["B"], c["Wn"])
+    with _plan(c, sb.sigma2) as plan:
+        r = plan.covariance(_t(X32, dev)).cpu().numpy()
+    for s in range(c["slots"]):
+        for k in range(c["K"]):
+            for b, st in enumerate(starts):
+                ref = O.sample_covariance(X[s, :, k, st:st + c["Wn"]])
+                err = np.linalg.norm(r[s, k, b] - ref) / np.linalg.norm(ref)
+                assert err < 1e-13, (s, k, b, err)
+
+
+@pytest.mark.parametrize("c", CASES + LARGE)
 @pytest.mark.parametrize("snr", [0.0, 20.0])
 def test_sample_estimate_matches_oracle(dev, c, snr):
     print(f"sample estimate {c} snr={snr}", flush=True)

@@ -51,6 +51,8 @@ CASES = [
     dict(M=6, K=3, N=99, N_fft=128, taps=8, tau=2.0, B=9, Wn=21, slots=3),       # odd B, odd Wn
     dict(M=70, K=2, N=240, N_fft=256, taps=12, tau=3.0, B=60, Wn=120, slots=1),  # several GEMM tiles
     dict(M=20, K=3, N=1200, N_fft=2048, taps=72, tau=4.0, B=100, Wn=150, slots=1),
+    # wider than the register-resident design: 7 sweep panels in the workspace
+    dict(M=20, K=2, N=400, N_fft=512, taps=16, tau=4.0, B=100, Wn=200, slots=2),
 ]
 
 
