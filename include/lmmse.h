@@ -37,7 +37,9 @@
  *                        profile of Sec. IV-A on integer taps l < taps:
  *                        r_d = sum_l p_l exp(-j2 pi l d/N_fft), p_l ~ e^{-l/tau}
  *   LMMSE_R_SAMPLE       raw sample covariance over the M antennas, per
- *                        (slot, user, window): R = (1/M) sum_m h h^H
+ *                        (slot, user, window): R = (1/M) sum_m h h^H;
+ *                        windows up to 256 (up to 160 held in registers,
+ *                        wider ones in the workspace)
  *   LMMSE_R_USER         filters supplied by the caller (lmmse_set_filters)
  * For a fixed design every block whose window sits at the same offset
  * start_b - b*B shares one filter ("class"); there are at most 3 classes
@@ -51,7 +53,8 @@
  * kept rows, the inverse alone gives the filter.  The filtering GEMM runs
  * in FP32 on the matrix cores (LMMSE_FP32), or as split products
  * hi*hi + hi*lo + lo*hi with FP32 accumulation in BF16 (LMMSE_BF16X3) or
- * FP16 (LMMSE_FP16X3).  The sample-covariance path always filters in FP32.
+ * FP16 (LMMSE_FP16X3); the sample-covariance path writes each window's
+ * filter as hi / lo parts and filters with the same split products.
  * The backward products are FP32 on the matrix cores (fixed designs) or
  * FP64 on the vector units (sample covariance).
  *
@@ -190,14 +193,15 @@ int lmmse_apply(lmmse_plan_t plan, int slots, const void *h_ls, void *h_hat,
  * the antennas (Sec. III-B, eq. 13's R estimated from the data), products of
  * the complex64 LS values accumulated in FP64, stored as complex128
  * [S][K][N/B][Wn][Wn] (full matrix, both triangles).  Any plan with
- * Wn <= 160 (else UNSUPPORTED). */
+ * Wn <= 256 (else UNSUPPORTED). */
 int lmmse_covariance(lmmse_plan_t plan, int slots, const void *h_ls,
                      void *r_win, void *stream);
 
 /* Batched FP64 block filters from window correlations r_win (complex128
  * [S][K][N/B][Wn][Wn], e.g. from lmmse_covariance): for block b,
  * W = R[off_b : off_b + B, :] (R + (sigma2/K) I)^-1, stored as complex128
- * [S][K][N/B][B][Wn]. */
+ * [S][K][N/B][B][Wn].  Windows with Wn <= 160 (the register-resident
+ * design; else UNSUPPORTED). */
 int lmmse_sample_filters(lmmse_plan_t plan, int slots, const void *r_win,
                          double sigma2, void *w_out, void *stream);
 
@@ -235,8 +239,9 @@ int lmmse_estimate_ls(lmmse_plan_t plan, int slots, const void *h_ls,
  * Sample covariance (at the sigma2 of the last lmmse_estimate_ls /
  * lmmse_estimate / lmmse_set_design): per (slot, user, window) the filter
  * depends on h_ls through R as well, so d_hls also receives
- * (Gam + Gam^H) X / M with Gam the window's gradient of R; windows with
- * Wn <= 160.  ws: lmmse_workspace_size bytes. */
+ * (Gam + Gam^H) X / M with Gam the window's gradient of R (the gradient
+ * of the FP64 design, whatever the filtering precision).  ws:
+ * lmmse_workspace_size bytes. */
 int lmmse_backward(lmmse_plan_t plan, int slots, const void *h_ls,
                    const void *g, void *d_hls, double *d_tau, double *d_sigma2,
                    void *ws, size_t ws_bytes, void *stream);

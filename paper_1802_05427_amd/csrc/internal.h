@@ -109,7 +109,13 @@ constexpr int kMaxSampleWindowLarge = 256;
 size_t large_design_bytes(const lmmse_plan_desc& d, long long nmat);
 hipError_t launch_sample_large(const Plan& p, long long nmat, long long mat0, const float2* hls,
                                double lam, double2* amat, double2* scratch, double2* w64,
-                               float2* w32, bool want_ainv, hipStream_t st);
+                               float2* w32, uint32_t* whi, uint32_t* wlo, bool want_ainv,
+                               hipStream_t st);
+// Split-precision filtering of the sample path with per-window filter parts
+// whi / wlo [mat][B][Wq] (Wq = Wn rounded up to 4).
+hipError_t launch_apply_sample_split(const Plan& p, long long nmat, const float2* hls,
+                                     const uint32_t* whi, const uint32_t* wlo, float2* out,
+                                     hipStream_t st);
 hipError_t launch_covariance_large(const Plan& p, long long nmat, const float2* hls, double2* r_win,
                                    hipStream_t st);
 

@@ -30,6 +30,7 @@
 #include <algorithm>
 
 #include "internal.h"
+#include "split.h"
 
 namespace lmmse {
 
@@ -47,6 +48,9 @@ struct SampleArgs {
     double2* w64;           // optional: W [mat][B][Wn]
     float2* w32;            // optional: W [mat][B][Wp], Wp = Wn rounded up to even (pad 0)
     double2* ainv;          // optional: A^-1 [mat][Wn][Wn] (row-major, both triangles)
+    uint32_t* whi;          // optional: split W, hi parts [mat][B][Wq] packed (re, im) 16-bit
+    uint32_t* wlo;          // and lo parts (FP16: scaled by 2^11); Wq = Wn rounded up to 4
+    int split_fp16;         // split format: FP16 (else BF16)
     const int* starts;
     const int* offsets;
     int* status;
@@ -223,7 +227,7 @@ __global__ __launch_bounds__(1024) void sample_design_kernel(SampleArgs a) {
 
     // A now holds -A^-1: W[o][j] = delta(off + o, j) + lam (-A^-1)[off + o][j]
     const int off = a.offsets[b];
-    const int wp = (n + 1) & ~1;
+    const int wp = (n + 1) & ~1, wq = (n + 3) & ~3;
 #pragma unroll
     for (int P = 0; P < NBK; ++P)
 #pragma unroll
@@ -250,6 +254,8 @@ __global__ __launch_bounds__(1024) void sample_design_kernel(SampleArgs a) {
                     wr[col] = make_float2((float)w.x, (float)w.y);
                     if (col == 0 && wp > n) wr[n] = make_float2(0.f, 0.f);   // pad column
                 }
+                if (a.whi) store_split_w(a.whi, a.wlo, (mat * a.B + o) * wq, col, n, wq, w,
+                                         a.split_fp16);
             }
         }
 }
@@ -490,7 +496,8 @@ hipError_t launch_sample_inverse(const Plan& p, long long nmat, long long mat0, 
                                  double lam, double2* w64, double2* ainv, double2* scratch,
                                  hipStream_t st) {
     if (p.d.Wn > kMaxSampleWindowReg)
-        return launch_sample_large(p, nmat, mat0, hls, lam, ainv, scratch, w64, nullptr, true, st);
+        return launch_sample_large(p, nmat, mat0, hls, lam, ainv, scratch, w64, nullptr, nullptr,
+                                   nullptr, true, st);
     SampleArgs sa = base_args(p, lam);
     sa.mat0 = mat0;
     sa.hls = hls;
@@ -511,11 +518,19 @@ static int large_chunk(const lmmse_plan_desc& d, int slots) {
 
 static size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Compact filters of every (slot, user, block): FP32 [mat][B][Wp] (Wp = Wn
+// rounded up to even), or hi and lo parts [mat][B][Wq] each (Wq = Wn
+// rounded up to 4) of packed 16-bit pairs.
+static size_t filter_area_bytes(const lmmse_plan_desc& d, long long nmat) {
+    if (d.precision == LMMSE_FP32) return up256((size_t)nmat * d.B * ((d.Wn + 1) & ~1) * sizeof(float2));
+    return up256(2 * (size_t)nmat * d.B * ((d.Wn + 3) & ~3) * sizeof(uint32_t));
+}
+
 size_t sample_workspace_bytes(const lmmse_plan_desc& d, int slots) {
-    // H_LS, the compact FP32 filters of every (slot, user, block), and for
-    // wide windows the design work area of one chunk of slots
+    // H_LS, the compact filters of every (slot, user, block), and for wide
+    // windows the design work area of one chunk of slots
     const size_t hls = hls_bytes(d, slots);
-    const size_t w = up256((size_t)slots * d.K * (d.N / d.B) * d.B * ((d.Wn + 1) & ~1) * sizeof(float2));
+    const size_t w = filter_area_bytes(d, (long long)slots * d.K * (d.N / d.B));
     size_t big = 0;
     if (d.Wn > kMaxSampleWindowReg && slots > 0)
         big = large_design_bytes(d, (long long)large_chunk(d, slots) * d.K * (d.N / d.B));
@@ -526,32 +541,39 @@ hipError_t launch_sample_estimate(const Plan& p, int slots, const float2* hls, d
                                   float2* out, void* ws, hipStream_t st) {
     const long long nmat = (long long)slots * p.d.K * p.nb;
     if (nmat == 0) return hipSuccess;
-    float2* w32 = reinterpret_cast<float2*>(ws);
+    const bool split = p.d.precision != LMMSE_FP32;
+    const int wp = (p.d.Wn + 1) & ~1, wq = (p.d.Wn + 3) & ~3;
+    float2* w32 = split ? nullptr : reinterpret_cast<float2*>(ws);
+    uint32_t* whi = split ? reinterpret_cast<uint32_t*>(ws) : nullptr;
+    uint32_t* wlo = split ? whi + nmat * p.d.B * wq : nullptr;
     hipError_t e;
     if (p.d.Wn > kMaxSampleWindowReg) {
-        const size_t wbytes =
-            up256((size_t)nmat * p.d.B * ((p.d.Wn + 1) & ~1) * sizeof(float2));
         const int chunk = large_chunk(p.d, slots);
         const long long cm = (long long)chunk * p.d.K * p.nb;
-        double2* amat = reinterpret_cast<double2*>((char*)ws + wbytes);
+        double2* amat = reinterpret_cast<double2*>((char*)ws + filter_area_bytes(p.d, nmat));
         double2* scratch = amat + cm * p.d.Wn * p.d.Wn;
         const long long per_slot = (long long)p.d.M * p.d.K * p.d.N;
-        const int wp = (p.d.Wn + 1) & ~1;
         for (int s0 = 0; s0 < slots; s0 += chunk) {
             const int ns = std::min(chunk, slots - s0);
             const long long m0 = (long long)s0 * p.d.K * p.nb;
             e = launch_sample_large(p, (long long)ns * p.d.K * p.nb, m0, hls + s0 * per_slot, lam, amat,
-                                    scratch, nullptr, w32 + m0 * p.d.B * wp, false, st);
+                                    scratch, nullptr, split ? nullptr : w32 + m0 * p.d.B * wp,
+                                    split ? whi + m0 * p.d.B * wq : nullptr,
+                                    split ? wlo + m0 * p.d.B * wq : nullptr, false, st);
             if (e != hipSuccess) return e;
         }
     } else {
         SampleArgs sa = base_args(p, lam);
         sa.hls = hls;
         sa.w32 = w32;
+        sa.whi = whi;
+        sa.wlo = wlo;
+        sa.split_fp16 = p.d.precision == LMMSE_FP16X3 ? 1 : 0;
         sa.want_w = 1;
         e = launch_sample_design(p, nmat, sa, st);
         if (e != hipSuccess) return e;
     }
+    if (split) return launch_apply_sample_split(p, nmat, hls, whi, wlo, out, st);
     SampleApplyArgs aa{};
     aa.hls = hls;
     aa.w32 = w32;

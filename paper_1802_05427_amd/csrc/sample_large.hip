@@ -18,6 +18,7 @@
 //      when asked for, A^-1 itself.
 #include <algorithm>
 
+#include "split.h"
 #include "zgemm.h"
 
 namespace lmmse {
@@ -105,7 +106,8 @@ __global__ __launch_bounds__(1024) void sweep_panel_kernel(double2* a, double2* 
 // leaves it; optionally A^-1 = -S in place.
 __global__ __launch_bounds__(256) void large_filters_kernel(double2* a, const int* offsets, int B,
                                                             int Wn, int nb, double lam, double2* w64,
-                                                            float2* w32, int negate) {
+                                                            float2* w32, uint32_t* whi, uint32_t* wlo,
+                                                            int fp16, int negate) {
     const long long mat = blockIdx.x;
     double2* am = a + mat * Wn * Wn;
     const int off = offsets[mat % nb];
@@ -120,6 +122,7 @@ __global__ __launch_bounds__(256) void large_filters_kernel(double2* a, const in
         const double2 w = make_double2((off + o == j ? 1.0 : 0.0) + lam * s.x, lam * s.y);
         if (w64) w64[(mat * B + o) * Wn + j] = w;
         if (w32) w32[(mat * B + o) * wp + j] = make_float2((float)w.x, (float)w.y);
+        if (whi) store_split_w(whi, wlo, (mat * B + o) * ((Wn + 3) & ~3), j, Wn, (Wn + 3) & ~3, w, fp16);
     }
     if (negate) {
         __syncthreads();   // every read of S above is done
@@ -137,7 +140,8 @@ size_t large_design_bytes(const lmmse_plan_desc& d, long long nmat) {
 
 hipError_t launch_sample_large(const Plan& p, long long nmat, long long mat0, const float2* hls,
                                double lam, double2* amat, double2* scratch, double2* w64,
-                               float2* w32, bool want_ainv, hipStream_t st) {
+                               float2* w32, uint32_t* whi, uint32_t* wlo, bool want_ainv,
+                               hipStream_t st) {
     const lmmse_plan_desc& d = p.d;
     const int Wn = d.Wn;
     if (nmat == 0) return hipSuccess;
@@ -178,7 +182,8 @@ hipError_t launch_sample_large(const Plan& p, long long nmat, long long mat0, co
         if ((e = zgemm<double2, double2, double2>(ga, nmat, st)) != hipSuccess) return e;
     }
     hipLaunchKernelGGL(large_filters_kernel, dim3((unsigned)nmat), dim3(256), 0, st, amat,
-                       p.d_offsets, d.B, Wn, p.nb, lam, w64, w32, want_ainv ? 1 : 0);
+                       p.d_offsets, d.B, Wn, p.nb, lam, w64, w32, whi, wlo,
+                       d.precision == LMMSE_FP16X3 ? 1 : 0, want_ainv ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -57,3 +57,35 @@ def test_split_estimate_matches_oracle(dev, prec, cfg, snr):
         print(f"  discrepancy {disc:.1f} dB, NMSE gap {gap:.2e} dB", flush=True)
         assert gap < SPLIT_GAP_DB
         assert disc < SPLIT_DISC_DB[prec]
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16x3"])
+@pytest.mark.parametrize("cfg", [
+    dict(M=8, K=2, N=72, N_fft=128, taps=8, tau=2.0, B=12, Wn=24, slots=2),
+    dict(M=6, K=3, N=99, N_fft=128, taps=8, tau=2.0, B=9, Wn=21, slots=2),          # odd B, Wn
+    dict(M=130, K=2, N=300, N_fft=512, taps=16, tau=4.0, B=100, Wn=150, slots=1),   # 2 antenna groups
+    dict(M=20, K=2, N=400, N_fft=512, taps=16, tau=4.0, B=100, Wn=200, slots=1),    # wide window
+    dict(M=40, K=2, N=3300, N_fft=4096, taps=144, tau=32.0, B=132, Wn=198, slots=1),
+])
+@pytest.mark.parametrize("snr", [0.0, 20.0])
+def test_split_sample_estimate_matches_oracle(dev, prec, cfg, snr):
+    """Sample-covariance path: FP64 per-window design, split-precision filter."""
+    c = cfg
+    print(f"split sample {prec} {c} snr={snr}", flush=True)
+    sb = make_slot_batch(M=c["M"], K=c["K"], N=c["N"], N_fft=c["N_fft"], taps=c["taps"], tau=c["tau"],
+                         snr_db=snr, slots=c["slots"], config_id=4)
+    with Plan(M=c["M"], K=c["K"], N=c["N"], N_fft=c["N_fft"], B=c["B"], Wn=c["Wn"], rsource="sample",
+              sigma2=sb.sigma2, max_slots=c["slots"], precision=prec) as plan:
+        y, pil = _t(sb.y, dev), _t(sb.pilots, dev)
+        out = plan.estimate(y, pil, sb.sigma2).cpu().numpy()
+        X32 = O.despread(sb.y, sb.pilots).astype(np.complex64)
+        out2 = plan.estimate_ls(_t(X32, dev), sb.sigma2).cpu().numpy()
+        st, info = plan.sync_status()
+    assert st == 0
+    ref = O.estimate(sb.y, sb.pilots, sb.sigma2, c["B"], c["Wn"], "sample")
+    for o in (out, out2):
+        disc = O.discrepancy_db(o, ref)
+        gap = abs(O.nmse_db(o, sb.H) - O.nmse_db(ref, sb.H))
+        print(f"  discrepancy {disc:.1f} dB, NMSE gap {gap:.2e} dB", flush=True)
+        assert gap < SPLIT_GAP_DB
+        assert disc < SPLIT_DISC_DB[prec]
