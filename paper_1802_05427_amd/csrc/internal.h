@@ -94,7 +94,8 @@ hipError_t launch_sample_estimate(const Plan& p, int slots, const float2* hls, d
 size_t sample_workspace_bytes(const lmmse_plan_desc& d, int slots);
 // Per (slot, user, block) window of the sample design: W (FP64 [nmat][B][Wn])
 // and A^-1 = (R + lam I)^-1 (FP64 [nmat][Wn][Wn], both triangles); scratch:
-// 2 nmat Wn 32 complex doubles, used by windows wider than the register sweep.
+// 2 nmat Wn kSweepPanel complex doubles, used by windows wider than the
+// register sweep.
 hipError_t launch_sample_inverse(const Plan& p, long long nmat, long long mat0, const float2* hls,
                                  double lam, double2* w64, double2* ainv, double2* scratch,
                                  hipStream_t st);
@@ -103,6 +104,7 @@ size_t sample_backward_workspace_bytes(const lmmse_plan_desc& d, int slots);
 // workspace-resident one (sample_large.hip) used above it.
 constexpr int kMaxSampleWindowReg = 160;
 constexpr int kMaxSampleWindowLarge = 256;
+constexpr int kSweepPanel = 64;   // pivots per panel of the workspace-resident sweep
 // Workspace-resident sample design of nmat windows: amat [nmat][Wn][Wn] and
 // scratch (large_design_bytes minus amat) are device work areas; w64 / w32
 // may be null; with want_ainv amat ends as A^-1.

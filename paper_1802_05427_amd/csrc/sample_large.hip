@@ -3,15 +3,16 @@
 // workspace as FP64 [mat][Wn][Wn] (both triangles):
 //
 //   1. R = X X^H / M with X = h_ls[s, :, k, I_b]^T: a batched GEMM with FP64
-//      accumulation of the exact products of the FP32 LS values;
+//      accumulation of the exact products of the FP32 LS values, on the
+//      lower tiles only (the upper ones are their mirror);
 //   2. A = R + lam I;
-//   3. the Hermitian sweep of all Wn pivots, in panels of 32 pivots K (rest
+//   3. the Hermitian sweep of all Wn pivots, in panels of 64 pivots K (rest
 //      R): sweeping a panel at once maps
 //          A_KK -> -A_KK^-1,  A_RK -> A_RK A_KK^-1,  A_KR -> A_KK^-1 A_KR,
 //          A_RR -> A_RR - A_RK A_KK^-1 A_KR,
 //      which equals sweeping its pivots one by one.  The panel kernel sweeps
-//      the 32 x 32 diagonal block in LDS and forms F = A_RK A_KK^-1; the
-//      update of A_RR is a rank-32 GEMM, A += (-1) F P^H with P the old
+//      the 64 x 64 diagonal block in LDS and forms F = A_RK A_KK^-1; the
+//      update of A_RR is a rank-64 GEMM, A += (-1) F P^H with P the old
 //      panel columns (rows of K zero in F and P, so the K rows and columns
 //      are left alone).  After all panels A holds -A^-1;
 //   4. W = (I - lam A^-1)[off rows] (FP64 and compact FP32 copies) and,
@@ -23,7 +24,8 @@
 
 namespace lmmse {
 
-constexpr int kPW = 32;   // pivots per panel
+constexpr int kPW = kSweepPanel;
+constexpr int kPR = 16;   // window rows per staging step of the panel kernel
 
 // A = R + lam I on the diagonal of every window.
 __global__ __launch_bounds__(256) void add_diag_kernel(double2* a, int Wn, double lam) {
@@ -31,25 +33,27 @@ __global__ __launch_bounds__(256) void add_diag_kernel(double2* a, int Wn, doubl
     for (int i = threadIdx.x; i < Wn; i += 256) am[(long long)i * Wn + i].x += lam;
 }
 
-// Panel step over pivots [k0, k0 + kw) of every window: sweeps A_KK, writes
-// A_KK, A_RK = F, A_KR = F^H, and the GEMM operands F and P (old panel
-// columns), both [mat][Wn][kPW] with zero rows in K and zero columns >= kw.
+// Panel step over pivots [k0, k0 + kw) of every window: sweeps A_KK in LDS,
+// then, 16 window rows at a time, forms F = A_RK A_KK^-1 and the GEMM
+// operands F and P (old panel columns), both [mat][Wn][kPW] with zero rows in
+// K and zero columns >= kw, and writes A_RK = F, A_KR = F^H and A_KK.
+// Every read of a panel column happens before this thread group overwrites it:
+// rows are staged, then written, one group at a time, and A_KR lies outside
+// the panel columns.
 __global__ __launch_bounds__(1024) void sweep_panel_kernel(double2* a, double2* f, double2* pold,
                                                            int Wn, int k0, int kw, int* status,
                                                            long long mat0) {
     __shared__ double2 D[kPW][kPW];
-    __shared__ double2 Pc[kMaxSampleWindowLarge][kPW];
+    __shared__ double2 Pr[kPR][kPW];
     const long long mat = blockIdx.x;
     double2* am = a + mat * Wn * Wn;
     const int tid = threadIdx.x;
-    for (int e = tid; e < Wn * kPW; e += 1024) {
-        const int i = e / kPW, t = e - i * kPW;
-        Pc[i][t] = t < kw ? am[(long long)i * Wn + k0 + t] : make_double2(0.0, 0.0);
+    constexpr int EPT = kPW * kPW / 1024;   // entries of D per thread
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+        const int e = tid + 1024 * u, i = e / kPW, j = e - i * kPW;
+        D[i][j] = (i < kw && j < kw) ? am[(long long)(k0 + i) * Wn + k0 + j] : make_double2(0.0, 0.0);
     }
-    __syncthreads();
-    const int di = tid / kPW, dj = tid - di * kPW;   // this thread's entry of D
-    const bool live = di < kw && dj < kw;
-    D[di][dj] = live ? Pc[k0 + di][dj] : make_double2(0.0, 0.0);
     __syncthreads();
     for (int p = 0; p < kw; ++p) {
         const double d = D[p][p].x;
@@ -59,47 +63,66 @@ __global__ __launch_bounds__(1024) void sweep_panel_kernel(double2* a, double2* 
             return;
         }
         const double invd = 1.0 / d;
-        const double2 v = D[di][dj], aip = D[di][p], apj = D[p][dj];
-        __syncthreads();
-        if (live) {
-            double2 r;
-            if (di == p && dj == p) {
-                r = make_double2(-invd, 0.0);
-            } else if (di == p) {
-                r = make_double2(apj.x * invd, apj.y * invd);
-            } else if (dj == p) {
-                r = make_double2(aip.x * invd, aip.y * invd);
+        double2 r[EPT];
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) {
+            const int e = tid + 1024 * u, i = e / kPW, j = e - i * kPW;
+            const double2 v = D[i][j], aip = D[i][p], apj = D[p][j];
+            if (i == p && j == p) {
+                r[u] = make_double2(-invd, 0.0);
+            } else if (i == p) {
+                r[u] = make_double2(apj.x * invd, apj.y * invd);
+            } else if (j == p) {
+                r[u] = make_double2(aip.x * invd, aip.y * invd);
             } else {
                 const double px = aip.x * apj.x - aip.y * apj.y, py = aip.x * apj.y + aip.y * apj.x;
-                r = make_double2(v.x - px * invd, v.y - py * invd);
+                r[u] = make_double2(v.x - px * invd, v.y - py * invd);
             }
-            D[di][dj] = r;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) {
+            const int e = tid + 1024 * u, i = e / kPW, j = e - i * kPW;
+            if (i < kw && j < kw) D[i][j] = r[u];
         }
         __syncthreads();
     }
-    // D = -A_KK^-1; F = A_RK A_KK^-1 = -A_RK D
+    // D = -A_KK^-1; F = A_RK A_KK^-1 = -A_RK D, kPR rows at a time
     double2* fm = f + mat * Wn * kPW;
     double2* pm = pold + mat * Wn * kPW;
-    for (int e = tid; e < Wn * kPW; e += 1024) {
-        const int i = e / kPW, t = e - i * kPW;
-        const bool inK = i >= k0 && i < k0 + kw;
-        double2 fv = make_double2(0.0, 0.0), pv = make_double2(0.0, 0.0);
-        if (!inK && t < kw) {
-            double sx = 0.0, sy = 0.0;
-            for (int q = 0; q < kw; ++q) {
-                const double2 x = Pc[i][q], y = D[q][t];
-                sx = fma(x.x, y.x, fma(-x.y, y.y, sx));
-                sy = fma(x.x, y.y, fma(x.y, y.x, sy));
-            }
-            fv = make_double2(-sx, -sy);
-            pv = Pc[i][t];
-            am[(long long)i * Wn + k0 + t] = fv;
-            am[(long long)(k0 + t) * Wn + i] = make_double2(fv.x, -fv.y);
+    const int ri = tid / kPW, t = tid - ri * kPW;   // this thread's (row, column) of a group
+    for (int i0 = 0; i0 < Wn; i0 += kPR) {
+        {
+            const int i = i0 + ri;
+            Pr[ri][t] = (i < Wn && t < kw) ? am[(long long)i * Wn + k0 + t] : make_double2(0.0, 0.0);
         }
-        fm[e] = fv;
-        pm[e] = pv;
+        __syncthreads();
+        const int i = i0 + ri;
+        if (i < Wn) {
+            const bool inK = i >= k0 && i < k0 + kw;
+            double2 fv = make_double2(0.0, 0.0), pv = make_double2(0.0, 0.0);
+            if (!inK && t < kw) {
+                double sx = 0.0, sy = 0.0;
+                for (int q = 0; q < kw; ++q) {
+                    const double2 x = Pr[ri][q], y = D[q][t];
+                    sx = fma(x.x, y.x, fma(-x.y, y.y, sx));
+                    sy = fma(x.x, y.y, fma(x.y, y.x, sy));
+                }
+                fv = make_double2(-sx, -sy);
+                pv = Pr[ri][t];
+                am[(long long)i * Wn + k0 + t] = fv;
+                am[(long long)(k0 + t) * Wn + i] = make_double2(fv.x, -fv.y);
+            }
+            fm[(long long)i * kPW + t] = fv;
+            pm[(long long)i * kPW + t] = pv;
+        }
+        __syncthreads();
     }
-    if (live) am[(long long)(k0 + di) * Wn + k0 + dj] = D[di][dj];
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+        const int e = tid + 1024 * u, i = e / kPW, j = e - i * kPW;
+        if (i < kw && j < kw) am[(long long)(k0 + i) * Wn + k0 + j] = D[i][j];
+    }
 }
 
 // W[o][j] = delta(off + o, j) + lam S[off + o][j] with S = -A^-1 as the sweep
@@ -161,7 +184,9 @@ hipError_t launch_sample_large(const Plan& p, long long nmat, long long mat0, co
     ga.kd = d.M;
     ga.alpha = 1.0 / d.M;
     ga.beta = 0;
+    ga.herm = 1;
     if ((e = zgemm<float2, float2, double2>(ga, nmat, st)) != hipSuccess) return e;
+    ga.herm = 0;
     hipLaunchKernelGGL(add_diag_kernel, dim3((unsigned)nmat), dim3(256), 0, st, amat, Wn, lam);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     double2* f = scratch;
@@ -204,6 +229,7 @@ hipError_t launch_covariance_large(const Plan& p, long long nmat, const float2* 
     ga.kd = d.M;
     ga.alpha = 1.0 / d.M;
     ga.beta = 0;
+    ga.herm = 1;
     return zgemm<float2, float2, double2>(ga, nmat, st);
 }
 

@@ -24,6 +24,7 @@ struct ZGemmArgs {
     int tiles_m, tiles_n;
     double alpha;
     int beta;
+    int herm;            // C Hermitian (square): compute the lower tiles, mirror them
 };
 
 constexpr int zT = 64;    // output tile edge
@@ -49,10 +50,24 @@ __global__ __launch_bounds__(256) void zgemm_kernel(ZGemmArgs g) {
     __shared__ double2 Bs[zKC][zT];
     const int tid = threadIdx.x;
     long long t = blockIdx.x;
-    const int tn = (int)(t % g.tiles_n);
-    t /= g.tiles_n;
-    const int tm = (int)(t % g.tiles_m);
-    const long long bat = t / g.tiles_m;
+    int tm, tn;
+    long long bat;
+    if (g.herm) {   // lower tiles (tn <= tm) of a square C, row by row
+        const int per = g.tiles_m * (g.tiles_m + 1) / 2;
+        int q = (int)(t % per);
+        bat = t / per;
+        tm = 0;
+        while (q > tm) {
+            q -= tm + 1;
+            ++tm;
+        }
+        tn = q;
+    } else {
+        tn = (int)(t % g.tiles_n);
+        t /= g.tiles_n;
+        tm = (int)(t % g.tiles_m);
+        bat = t / g.tiles_m;
+    }
     const int r0 = tm * zT, c0 = tn * zT;
     const long long abase = zbase(g.A, bat, g.K, g.nb);
     const long long bbase = zbase(g.B, bat, g.K, g.nb);
@@ -131,6 +146,13 @@ __global__ __launch_bounds__(256) void zgemm_kernel(ZGemmArgs g) {
                 cp[o] = make_double2(x, y);
             else
                 cp[o] = make_float2((float)x, (float)y);
+            if (g.herm && tm != tn) {   // the mirrored entry of an off-diagonal tile
+                const long long om = cbase + c * g.C.rs + r * g.C.cs;
+                if constexpr (sizeof(TC) == sizeof(double2))
+                    cp[om] = make_double2(x, -y);
+                else
+                    cp[om] = make_float2((float)x, (float)-y);
+            }
         }
 }
 
@@ -138,7 +160,9 @@ template <typename TA, typename TB, typename TC>
 inline hipError_t zgemm(ZGemmArgs g, long long nbat, hipStream_t st) {
     g.tiles_m = (g.m + zT - 1) / zT;
     g.tiles_n = (g.n + zT - 1) / zT;
-    const long long blocks = nbat * g.tiles_m * g.tiles_n;
+    if (g.herm && (g.m != g.n || g.beta)) return hipErrorInvalidValue;
+    const long long blocks =
+        nbat * (g.herm ? (long long)g.tiles_m * (g.tiles_m + 1) / 2 : (long long)g.tiles_m * g.tiles_n);
     if (blocks == 0) return hipSuccess;
     hipLaunchKernelGGL((zgemm_kernel<TA, TB, TC>), dim3((unsigned)blocks), dim3(256), 0, st, g);
     return hipGetLastError();
