@@ -75,15 +75,17 @@ int validate(const lmmse_plan_desc* d) {
     return LMMSE_OK;
 }
 
+// Row tiles per workgroup: padded tiles, charged 5% per row group (each
+// group re-reads the window's inputs and redoes their staging).
 void choose_row_tiles(int B, int max_rt, int& RT, int& rgroups) {
     const int T = (2 * B + 15) / 16;
-    long long best_pad = -1;
+    double best = -1.0;
     for (int rt : kRTs) {
         if (rt > max_rt) continue;
         const int g = (T + rt - 1) / rt;
-        const long long padded = (long long)g * rt;
-        if (best_pad < 0 || padded < best_pad || (padded == best_pad && g < rgroups)) {
-            best_pad = padded;
+        const double cost = (double)g * rt * (1.0 + 0.05 * g);
+        if (best < 0.0 || cost < best) {
+            best = cost;
             RT = rt;
             rgroups = g;
         }

@@ -204,6 +204,7 @@ hipError_t launch_sample_large(const Plan& p, long long nmat, long long mat0, co
         ga.kd = kw;
         ga.alpha = -1.0;
         ga.beta = 1;
+        ga.herm = 1;   // F P^H = A_RK A_KK^-1 A_RK^H is Hermitian
         if ((e = zgemm<double2, double2, double2>(ga, nmat, st)) != hipSuccess) return e;
     }
     hipLaunchKernelGGL(large_filters_kernel, dim3((unsigned)nmat), dim3(256), 0, st, amat,

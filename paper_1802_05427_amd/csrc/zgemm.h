@@ -24,7 +24,8 @@ struct ZGemmArgs {
     int tiles_m, tiles_n;
     double alpha;
     int beta;
-    int herm;            // C Hermitian (square): compute the lower tiles, mirror them
+    int herm;            // C and the update Hermitian (square): compute the lower
+                         // tiles, mirror them
 };
 
 constexpr int zT = 64;    // output tile edge
@@ -160,7 +161,7 @@ template <typename TA, typename TB, typename TC>
 inline hipError_t zgemm(ZGemmArgs g, long long nbat, hipStream_t st) {
     g.tiles_m = (g.m + zT - 1) / zT;
     g.tiles_n = (g.n + zT - 1) / zT;
-    if (g.herm && (g.m != g.n || g.beta)) return hipErrorInvalidValue;
+    if (g.herm && g.m != g.n) return hipErrorInvalidValue;
     const long long blocks =
         nbat * (g.herm ? (long long)g.tiles_m * (g.tiles_m + 1) / 2 : (long long)g.tiles_m * g.tiles_n);
     if (blocks == 0) return hipSuccess;
