@@ -5,7 +5,7 @@
 //     dW   = G X^H                           (B x Wn)
 //     Z    = dW A^-1                         (B x Wn)
 //     Gam  = -W^H Z,  then Gam[off + o, :] += Z[o, :]   (gradient of R, Wn x Wn)
-//     dX   = W^H G + (Gam + Gam^H) X / M     (R depends on X: dR = (dX X^H + X dX^H) / M)
+//     dX   = W^H G + S X,  S = (Gam + Gam^H) / M   (R depends on X: dR = (dX X^H + X dX^H) / M)
 //     dlam = Re tr(-W^H Z), summed over all windows.
 // The window gradients are written per window and combined afterwards in a
 // fixed order (overlapping windows add), so the result does not depend on
@@ -22,10 +22,10 @@
 namespace lmmse {
 
 // Per window: dlam partial = Re tr(Gam) (Gam = -W^H Z as computed so far),
-// then Gam[off + o, :] += Z[o, :].
+// then Gam[off + o, :] += Z[o, :], then Gam -> S = (Gam + Gam^H) / M in place.
 __global__ __launch_bounds__(256) void gamma_rows_kernel(double2* gam, const double2* z,
                                                          const int* offsets, double* dlam_w, int B,
-                                                         int Wn, int nb) {
+                                                         int Wn, int nb, double invM) {
     __shared__ double red[256];
     const long long mat = blockIdx.x;
     const int off = offsets[mat % nb];
@@ -46,6 +46,16 @@ __global__ __launch_bounds__(256) void gamma_rows_kernel(double2* gam, const dou
         double2& d = gm[(long long)(off + o) * Wn + j];
         d.x += zm[e].x;
         d.y += zm[e].y;
+    }
+    __syncthreads();
+    // each pair (i, j), (j, i) with i >= j by one thread
+    for (int e = threadIdx.x; e < Wn * Wn; e += 256) {
+        const int i = e / Wn, j = e - i * Wn;
+        if (j > i) continue;
+        const double2 a = gm[(long long)i * Wn + j], b = gm[(long long)j * Wn + i];
+        const double2 sv = make_double2((a.x + b.x) * invM, (a.y - b.y) * invM);
+        gm[(long long)i * Wn + j] = sv;
+        gm[(long long)j * Wn + i] = make_double2(sv.x, -sv.y);
     }
 }
 
@@ -232,9 +242,10 @@ hipError_t launch_backward_sample(Plan& p, int slots, const float2* hls, const f
         ga.alpha = -1.0;
         if ((e = zgemm<double2, double2, double2>(ga, nmat, st)) != hipSuccess) return e;
         hipLaunchKernelGGL(gamma_rows_kernel, dim3((unsigned)nmat), dim3(256), 0, st, ainv, z,
-                           p.d_offsets, dlam + mat0, B, Wn, p.nb);
+                           p.d_offsets, dlam + mat0, B, Wn, p.nb, 1.0 / M);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        // per-window dX, stored [mat][m][j]: W^H G, + Gam X / M, + Gam^H X / M
+        // per-window dX, stored [mat][m][j]: W^H G + S X, in FP32 arithmetic
+        // (the result is the FP32 gradient; FP64 stays where the solve is)
         ZView cx{};
         cx.p = dxw;
         cx.rs = 1;
@@ -250,15 +261,12 @@ hipError_t launch_backward_sample(Plan& p, int slots, const float2* hls, const f
         ga.kd = B;
         ga.alpha = 1.0;
         ga.beta = 0;
-        if ((e = zgemm<double2, float2, float2>(ga, nmat, st)) != hipSuccess) return e;
+        if ((e = zgemm<double2, float2, float2, float>(ga, nmat, st)) != hipSuccess) return e;
         ga.A = wview(ainv, d, Wn, Wn, false);
         ga.B = hview(d, hc, p.d_starts, 1, 0, false);
         ga.kd = Wn;
-        ga.alpha = 1.0 / M;
         ga.beta = 1;
-        if ((e = zgemm<double2, float2, float2>(ga, nmat, st)) != hipSuccess) return e;
-        ga.A = wview(ainv, d, Wn, Wn, true);
-        if ((e = zgemm<double2, float2, float2>(ga, nmat, st)) != hipSuccess) return e;
+        if ((e = zgemm<double2, float2, float2, float>(ga, nmat, st)) != hipSuccess) return e;
 
         const long long total = ns * per_slot;
         hipLaunchKernelGGL(combine_windows_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256),

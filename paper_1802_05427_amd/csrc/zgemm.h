@@ -39,16 +39,33 @@ __device__ __forceinline__ long long zbase(const ZView& v, long long bat, int K,
     return s * v.s_slot + k * v.s_user + (long long)(v.blk_tab ? v.blk_tab[b] : b) * v.s_blk;
 }
 
-template <typename T>
-__device__ __forceinline__ double2 zload(const void* p, long long i, int conj) {
+// Complex accumulator / LDS element of a precision: FP64 (double2) or FP32 (float2).
+template <typename R>
+struct Cx;
+template <>
+struct Cx<double> {
+    using T = double2;
+    __device__ static T make(double x, double y) { return make_double2(x, y); }
+};
+template <>
+struct Cx<float> {
+    using T = float2;
+    __device__ static T make(double x, double y) { return make_float2((float)x, (float)y); }
+};
+
+template <typename R, typename T>
+__device__ __forceinline__ typename Cx<R>::T zload(const void* p, long long i, int conj) {
     const T v = reinterpret_cast<const T*>(p)[i];
-    return make_double2((double)v.x, conj ? -(double)v.y : (double)v.y);
+    return Cx<R>::make((double)v.x, conj ? -(double)v.y : (double)v.y);
 }
 
-template <typename TA, typename TB, typename TC>
+// R: the arithmetic precision (double: FP64 products and sums; float: FP32,
+// for products whose result only needs FP32 accuracy).
+template <typename TA, typename TB, typename TC, typename R = double>
 __global__ __launch_bounds__(256) void zgemm_kernel(ZGemmArgs g) {
-    __shared__ double2 As[zKC][zT];
-    __shared__ double2 Bs[zKC][zT];
+    using CT = typename Cx<R>::T;
+    __shared__ CT As[zKC][zT];
+    __shared__ CT Bs[zKC][zT];
     const int tid = threadIdx.x;
     long long t = blockIdx.x;
     int tm, tn;
@@ -80,13 +97,13 @@ __global__ __launch_bounds__(256) void zgemm_kernel(ZGemmArgs g) {
     const int tf = tid & 15, ts = tid >> 4;
     const int ri = c_rowfast ? tf : ts, ci = c_rowfast ? ts : tf;
 
-    double2 acc[4][4];
+    CT acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0.0, 0.0);
+        for (int j = 0; j < 4; ++j) acc[i][j] = Cx<R>::make(0.0, 0.0);
 
-    double2 pa[4], pb[4];
+    CT pa[4], pb[4];
     auto fetch = [&](int k0) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -94,11 +111,11 @@ __global__ __launch_bounds__(256) void zgemm_kernel(ZGemmArgs g) {
             const int r = a_rowfast ? (e & 63) : (e >> 4), ka = a_rowfast ? (e >> 6) : (e & 15);
             const int c = b_colfast ? (e & 63) : (e >> 4), kb = b_colfast ? (e >> 6) : (e & 15);
             pa[u] = (r0 + r < g.m && k0 + ka < g.kd)
-                        ? zload<TA>(g.A.p, abase + (r0 + r) * g.A.rs + (k0 + ka) * g.A.cs, g.A.conj)
-                        : make_double2(0.0, 0.0);
+                        ? zload<R, TA>(g.A.p, abase + (r0 + r) * g.A.rs + (k0 + ka) * g.A.cs, g.A.conj)
+                        : Cx<R>::make(0.0, 0.0);
             pb[u] = (c0 + c < g.n && k0 + kb < g.kd)
-                        ? zload<TB>(g.B.p, bbase + (k0 + kb) * g.B.rs + (c0 + c) * g.B.cs, g.B.conj)
-                        : make_double2(0.0, 0.0);
+                        ? zload<R, TB>(g.B.p, bbase + (k0 + kb) * g.B.rs + (c0 + c) * g.B.cs, g.B.conj)
+                        : Cx<R>::make(0.0, 0.0);
         }
     };
     fetch(0);
@@ -115,7 +132,7 @@ __global__ __launch_bounds__(256) void zgemm_kernel(ZGemmArgs g) {
         if (k0 + zKC < g.kd) fetch(k0 + zKC);
 #pragma unroll 4
         for (int kk = 0; kk < zKC; ++kk) {
-            double2 av[4], bv[4];
+            CT av[4], bv[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) av[i] = As[kk][ri + 16 * i];
 #pragma unroll
@@ -157,7 +174,7 @@ __global__ __launch_bounds__(256) void zgemm_kernel(ZGemmArgs g) {
         }
 }
 
-template <typename TA, typename TB, typename TC>
+template <typename TA, typename TB, typename TC, typename R = double>
 inline hipError_t zgemm(ZGemmArgs g, long long nbat, hipStream_t st) {
     g.tiles_m = (g.m + zT - 1) / zT;
     g.tiles_n = (g.n + zT - 1) / zT;
@@ -165,7 +182,7 @@ inline hipError_t zgemm(ZGemmArgs g, long long nbat, hipStream_t st) {
     const long long blocks =
         nbat * (g.herm ? (long long)g.tiles_m * (g.tiles_m + 1) / 2 : (long long)g.tiles_m * g.tiles_n);
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL((zgemm_kernel<TA, TB, TC>), dim3((unsigned)blocks), dim3(256), 0, st, g);
+    hipLaunchKernelGGL((zgemm_kernel<TA, TB, TC, R>), dim3((unsigned)blocks), dim3(256), 0, st, g);
     return hipGetLastError();
 }
 
