@@ -48,15 +48,34 @@ __global__ __launch_bounds__(256) void gamma_rows_kernel(double2* gam, const dou
         d.y += zm[e].y;
     }
     __syncthreads();
-    // each pair (i, j), (j, i) with i >= j by one thread
-    for (int e = threadIdx.x; e < Wn * Wn; e += 256) {
-        const int i = e / Wn, j = e - i * Wn;
-        if (j > i) continue;
-        const double2 a = gm[(long long)i * Wn + j], b = gm[(long long)j * Wn + i];
-        const double2 sv = make_double2((a.x + b.x) * invM, (a.y - b.y) * invM);
-        gm[(long long)i * Wn + j] = sv;
-        gm[(long long)j * Wn + i] = make_double2(sv.x, -sv.y);
-    }
+    // S over 32 x 32 tile pairs (I, J), I >= J, both tiles staged in LDS so
+    // that every global access walks a row
+    __shared__ double2 t1[32][33], t2[32][33];
+    const int nt = (Wn + 31) / 32;
+    for (int I = 0; I < nt; ++I)
+        for (int J = 0; J <= I; ++J) {
+            for (int e = threadIdx.x; e < 1024; e += 256) {
+                const int r = e >> 5, c = e & 31;
+                const int i1 = 32 * I + r, j1 = 32 * J + c, i2 = 32 * J + r, j2 = 32 * I + c;
+                t1[r][c] = (i1 < Wn && j1 < Wn) ? gm[(long long)i1 * Wn + j1] : make_double2(0.0, 0.0);
+                t2[r][c] = (i2 < Wn && j2 < Wn) ? gm[(long long)i2 * Wn + j2] : make_double2(0.0, 0.0);
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < 1024; e += 256) {
+                const int r = e >> 5, c = e & 31;
+                const int i1 = 32 * I + r, j1 = 32 * J + c, i2 = 32 * J + r, j2 = 32 * I + c;
+                // S[i1][j1] = (Gam[i1][j1] + conj(Gam[j1][i1])) / M, Gam[j1][i1] = t2[c][r]
+                if (i1 < Wn && j1 < Wn) {
+                    const double2 a = t1[r][c], b = t2[c][r];
+                    gm[(long long)i1 * Wn + j1] = make_double2((a.x + b.x) * invM, (a.y - b.y) * invM);
+                }
+                if (I != J && i2 < Wn && j2 < Wn) {
+                    const double2 a = t2[r][c], b = t1[c][r];
+                    gm[(long long)i2 * Wn + j2] = make_double2((a.x + b.x) * invM, (a.y - b.y) * invM);
+                }
+            }
+            __syncthreads();
+        }
 }
 
 // dhls[s, m, k, n] = sum over the windows b that hold n, in increasing b, of
