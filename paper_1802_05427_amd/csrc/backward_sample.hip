@@ -149,7 +149,7 @@ SbLayout sb_layout(const lmmse_plan_desc& d, int slots) {
     L.dxw = o;
     o += up256((size_t)nmat * d.M * d.Wn * sizeof(float2));
     L.panel = o;   // panel operands of the workspace-resident design (wide windows)
-    if (d.Wn > kMaxSampleWindowReg) o += up256((size_t)nmat * 2 * d.Wn * kSweepPanel * sizeof(double2));
+    if (d.Wn > kMaxSampleWindowReg) o += up256(sweep_scratch_bytes(d.Wn, nmat));
     L.total = o;
     return L;
 }

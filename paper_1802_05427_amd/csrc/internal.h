@@ -94,8 +94,8 @@ hipError_t launch_sample_estimate(const Plan& p, int slots, const float2* hls, d
 size_t sample_workspace_bytes(const lmmse_plan_desc& d, int slots);
 // Per (slot, user, block) window of the sample design: W (FP64 [nmat][B][Wn])
 // and A^-1 = (R + lam I)^-1 (FP64 [nmat][Wn][Wn], both triangles); scratch:
-// 2 nmat Wn kSweepPanel complex doubles, used by windows wider than the
-// register sweep.
+// sweep_scratch_bytes(Wn, nmat), used by windows wider than the register
+// sweep.
 hipError_t launch_sample_inverse(const Plan& p, long long nmat, long long mat0, const float2* hls,
                                  double lam, double2* w64, double2* ainv, double2* scratch,
                                  hipStream_t st);
@@ -106,9 +106,10 @@ constexpr int kMaxSampleWindowReg = 160;
 constexpr int kMaxSampleWindowLarge = 256;
 constexpr int kSweepPanel = 64;   // pivots per panel of the workspace-resident sweep
 // Workspace-resident sample design of nmat windows: amat [nmat][Wn][Wn] and
-// scratch (large_design_bytes minus amat) are device work areas; w64 / w32
+// scratch (sweep_scratch_bytes) are device work areas; w64 / w32 / whi, wlo
 // may be null; with want_ainv amat ends as A^-1.
 size_t large_design_bytes(const lmmse_plan_desc& d, long long nmat);
+size_t sweep_scratch_bytes(int Wn, long long nmat);   // the scratch part of it
 hipError_t launch_sample_large(const Plan& p, long long nmat, long long mat0, const float2* hls,
                                double lam, double2* amat, double2* scratch, double2* w64,
                                float2* w32, uint32_t* whi, uint32_t* wlo, bool want_ainv,

@@ -11,10 +11,11 @@
 //          A_KK -> -A_KK^-1,  A_RK -> A_RK A_KK^-1,  A_KR -> A_KK^-1 A_KR,
 //          A_RR -> A_RR - A_RK A_KK^-1 A_KR,
 //      which equals sweeping its pivots one by one.  The panel kernel sweeps
-//      the 64 x 64 diagonal block in LDS and forms F = A_RK A_KK^-1; the
-//      update of A_RR is a rank-64 GEMM, A += (-1) F P^H with P the old
-//      panel columns (rows of K zero in F and P, so the K rows and columns
-//      are left alone).  After all panels A holds -A^-1;
+//      the 64 x 64 diagonal block in LDS and copies the old panel columns P;
+//      F = A_RK A_KK^-1 = P A_KK^-1 and the update of A_RR, A += (-1) F P^H,
+//      are batched GEMMs (rows of K zero in F and P, so the K rows and
+//      columns are left alone), and a small kernel writes A_RK = F,
+//      A_KR = F^H.  After all panels A holds -A^-1;
 //   4. W = (I - lam A^-1)[off rows] (FP64 and compact FP32 copies) and,
 //      when asked for, A^-1 itself.
 #include <algorithm>
@@ -33,22 +34,26 @@ __global__ __launch_bounds__(256) void add_diag_kernel(double2* a, int Wn, doubl
     for (int i = threadIdx.x; i < Wn; i += 256) am[(long long)i * Wn + i].x += lam;
 }
 
-// Panel step over pivots [k0, k0 + kw) of every window: sweeps A_KK in LDS,
-// then, 16 window rows at a time, forms F = A_RK A_KK^-1 and the GEMM
-// operands F and P (old panel columns), both [mat][Wn][kPW] with zero rows in
-// K and zero columns >= kw, and writes A_RK = F, A_KR = F^H and A_KK.
-// Every read of a panel column happens before this thread group overwrites it:
-// rows are staged, then written, one group at a time, and A_KR lies outside
-// the panel columns.
-__global__ __launch_bounds__(1024) void sweep_panel_kernel(double2* a, double2* f, double2* pold,
+// Panel step over pivots [k0, k0 + kw) of every window, first part: sweeps
+// A_KK in LDS into dsw = -A_KK^-1 ([mat][kPW][kPW], zero past kw), writes it
+// to A_KK, and copies the old panel columns into P ([mat][Wn][kPW], zero
+// rows in K and zero columns >= kw).  F = P A_KK^-1 = P (-dsw) is then a
+// batched GEMM, and panel_writeback_kernel stores A_RK = F, A_KR = F^H.
+__global__ __launch_bounds__(1024) void sweep_panel_kernel(double2* a, double2* dsw, double2* pold,
                                                            int Wn, int k0, int kw, int* status,
                                                            long long mat0) {
     __shared__ double2 D[kPW][kPW];
-    __shared__ double2 Pr[kPR][kPW];
     const long long mat = blockIdx.x;
     double2* am = a + mat * Wn * Wn;
     const int tid = threadIdx.x;
     constexpr int EPT = kPW * kPW / 1024;   // entries of D per thread
+    // old panel columns (rows in K zero)
+    double2* pm = pold + mat * Wn * kPW;
+    for (int e = tid; e < Wn * kPW; e += 1024) {
+        const int i = e / kPW, t = e - i * kPW;
+        const bool inK = i >= k0 && i < k0 + kw;
+        pm[e] = (!inK && t < kw) ? am[(long long)i * Wn + k0 + t] : make_double2(0.0, 0.0);
+    }
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
         const int e = tid + 1024 * u, i = e / kPW, j = e - i * kPW;
@@ -87,41 +92,31 @@ __global__ __launch_bounds__(1024) void sweep_panel_kernel(double2* a, double2* 
         }
         __syncthreads();
     }
-    // D = -A_KK^-1; F = A_RK A_KK^-1 = -A_RK D, kPR rows at a time
-    double2* fm = f + mat * Wn * kPW;
-    double2* pm = pold + mat * Wn * kPW;
-    const int ri = tid / kPW, t = tid - ri * kPW;   // this thread's (row, column) of a group
-    for (int i0 = 0; i0 < Wn; i0 += kPR) {
-        {
-            const int i = i0 + ri;
-            Pr[ri][t] = (i < Wn && t < kw) ? am[(long long)i * Wn + k0 + t] : make_double2(0.0, 0.0);
-        }
-        __syncthreads();
-        const int i = i0 + ri;
-        if (i < Wn) {
-            const bool inK = i >= k0 && i < k0 + kw;
-            double2 fv = make_double2(0.0, 0.0), pv = make_double2(0.0, 0.0);
-            if (!inK && t < kw) {
-                double sx = 0.0, sy = 0.0;
-                for (int q = 0; q < kw; ++q) {
-                    const double2 x = Pr[ri][q], y = D[q][t];
-                    sx = fma(x.x, y.x, fma(-x.y, y.y, sx));
-                    sy = fma(x.x, y.y, fma(x.y, y.x, sy));
-                }
-                fv = make_double2(-sx, -sy);
-                pv = Pr[ri][t];
-                am[(long long)i * Wn + k0 + t] = fv;
-                am[(long long)(k0 + t) * Wn + i] = make_double2(fv.x, -fv.y);
-            }
-            fm[(long long)i * kPW + t] = fv;
-            pm[(long long)i * kPW + t] = pv;
-        }
-        __syncthreads();
-    }
+    double2* dm = dsw + mat * kPW * kPW;
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
         const int e = tid + 1024 * u, i = e / kPW, j = e - i * kPW;
+        dm[e] = D[i][j];
         if (i < kw && j < kw) am[(long long)(k0 + i) * Wn + k0 + j] = D[i][j];
+    }
+}
+
+// A_RK = F and A_KR = F^H for the rows outside the panel.
+__global__ __launch_bounds__(256) void panel_writeback_kernel(double2* a, const double2* f, int Wn,
+                                                              int k0, int kw) {
+    const long long mat = blockIdx.x;
+    double2* am = a + mat * Wn * Wn;
+    const double2* fm = f + mat * Wn * kPW;
+    for (int e = threadIdx.x; e < Wn * kPW; e += 256) {   // row i, column t: rows of A_RK
+        const int i = e / kPW, t = e - i * kPW;
+        if (t < kw && !(i >= k0 && i < k0 + kw)) am[(long long)i * Wn + k0 + t] = fm[e];
+    }
+    for (int e = threadIdx.x; e < Wn * kPW; e += 256) {   // row k0 + t, column i: rows of A_KR
+        const int t = e / Wn, i = e - t * Wn;
+        if (t < kw && !(i >= k0 && i < k0 + kw)) {
+            const double2 v = fm[(long long)i * kPW + t];
+            am[(long long)(k0 + t) * Wn + i] = make_double2(v.x, -v.y);
+        }
     }
 }
 
@@ -156,9 +151,12 @@ __global__ __launch_bounds__(256) void large_filters_kernel(double2* a, const in
     }
 }
 
+size_t sweep_scratch_bytes(int Wn, long long nmat) {
+    return (size_t)nmat * (2 * (size_t)Wn * kPW + (size_t)kPW * kPW) * sizeof(double2);
+}
+
 size_t large_design_bytes(const lmmse_plan_desc& d, long long nmat) {
-    const size_t per = (size_t)d.Wn * d.Wn * sizeof(double2) + 2 * (size_t)d.Wn * kPW * sizeof(double2);
-    return (size_t)nmat * per;
+    return (size_t)nmat * d.Wn * d.Wn * sizeof(double2) + sweep_scratch_bytes(d.Wn, nmat);
 }
 
 hipError_t launch_sample_large(const Plan& p, long long nmat, long long mat0, const float2* hls,
@@ -189,18 +187,36 @@ hipError_t launch_sample_large(const Plan& p, long long nmat, long long mat0, co
     ga.herm = 0;
     hipLaunchKernelGGL(add_diag_kernel, dim3((unsigned)nmat), dim3(256), 0, st, amat, Wn, lam);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    // scratch: F and P [nmat][Wn][kPW], then -A_KK^-1 [nmat][kPW][kPW]
     double2* f = scratch;
-    double2* pold = scratch + nmat * Wn * kPW;
-    const long long pp = (long long)Wn * kPW;
+    double2* pold = f + nmat * Wn * kPW;
+    double2* dsw = pold + nmat * Wn * kPW;
+    const long long pp = (long long)Wn * kPW, dd = (long long)kPW * kPW;
     for (int k0 = 0; k0 < Wn; k0 += kPW) {
         const int kw = std::min(kPW, Wn - k0);
-        hipLaunchKernelGGL(sweep_panel_kernel, dim3((unsigned)nmat), dim3(1024), 0, st, amat, f, pold,
-                           Wn, k0, kw, p.status, mat0);
+        hipLaunchKernelGGL(sweep_panel_kernel, dim3((unsigned)nmat), dim3(1024), 0, st, amat, dsw,
+                           pold, Wn, k0, kw, p.status, mat0);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        // F = P A_KK^-1 = -P dsw (rows of K vanish with P's)
+        ga.A = ZView{pold, kPW, 1, pp * p.nb * d.K, pp * p.nb, pp, nullptr, 0};
+        ga.B = ZView{dsw, kPW, 1, dd * p.nb * d.K, dd * p.nb, dd, nullptr, 0};
+        ga.C = ZView{f, kPW, 1, pp * p.nb * d.K, pp * p.nb, pp, nullptr, 0};
+        ga.m = Wn;
+        ga.n = kPW;
+        ga.kd = kw;
+        ga.alpha = -1.0;
+        ga.beta = 0;
+        ga.herm = 0;
+        if ((e = zgemm<double2, double2, double2>(ga, nmat, st)) != hipSuccess) return e;
+        hipLaunchKernelGGL(panel_writeback_kernel, dim3((unsigned)nmat), dim3(256), 0, st, amat, f,
+                           Wn, k0, kw);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         // A += (-1) F P^H over the whole window (F, P vanish on the panel's rows)
         ga.A = ZView{f, kPW, 1, pp * p.nb * d.K, pp * p.nb, pp, nullptr, 0};
         ga.B = ZView{pold, 1, kPW, pp * p.nb * d.K, pp * p.nb, pp, nullptr, 1};
         ga.C = ZView{amat, Wn, 1, per * p.nb * d.K, per * p.nb, per, nullptr, 0};
+        ga.m = Wn;
+        ga.n = Wn;
         ga.kd = kw;
         ga.alpha = -1.0;
         ga.beta = 1;

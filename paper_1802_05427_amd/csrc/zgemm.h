@@ -216,12 +216,18 @@ __global__ __launch_bounds__(256) void zgemm_mfma_kernel(ZGemmArgs g) {
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32, li = lane & 15, lk = lane >> 4;
 
     zd4 cre[2][2], cim[2][2];
+    // 16 x 16 sub-tiles this wave computes (wave-uniform): those with rows and
+    // columns in range and, on a diagonal tile of a Hermitian product, on or
+    // below the diagonal (the upper ones are written as mirrors)
+    bool live[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             cre[i][j] = zd4{0.0, 0.0, 0.0, 0.0};
             cim[i][j] = zd4{0.0, 0.0, 0.0, 0.0};
+            const int ri = wr + 16 * i, cj = wc + 16 * j;
+            live[i][j] = r0 + ri < g.m && c0 + cj < g.n && !(g.herm && tm == tn && ri < cj);
         }
 
     double2 pa[4], pb[4];
@@ -263,6 +269,7 @@ __global__ __launch_bounds__(256) void zgemm_mfma_kernel(ZGemmArgs g) {
             for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
+                    if (!live[i][j]) continue;
                     cre[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].x, cre[i][j], 0, 0, 0);
                     cre[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[i].y, b[j].y, cre[i][j], 0, 0, 0);
                     cim[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].y, cim[i][j], 0, 0, 0);
@@ -278,8 +285,11 @@ __global__ __launch_bounds__(256) void zgemm_mfma_kernel(ZGemmArgs g) {
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
+                if (!live[i][j]) continue;
                 const int r = r0 + wr + 16 * i + 4 * v + lk, c = c0 + wc + 16 * j + li;
                 if (r >= g.m || c >= g.n) continue;
+                // mirrors: every sub-tile off the diagonal of a Hermitian product
+                const bool mirror = g.herm && (tm != tn || wr + 16 * i > wc + 16 * j);
                 const long long o = cbase + r * g.C.rs + c * g.C.cs;
                 double x = g.alpha * cre[i][j][v], y = g.alpha * cim[i][j][v];
                 if (g.beta) {
@@ -290,7 +300,7 @@ __global__ __launch_bounds__(256) void zgemm_mfma_kernel(ZGemmArgs g) {
                     cp[o] = make_double2(x, y);
                 else
                     cp[o] = make_float2((float)x, (float)y);
-                if (g.herm && tm != tn) {
+                if (mirror) {
                     const long long om = cbase + c * g.C.rs + r * g.C.cs;
                     if constexpr (sizeof(TC) == sizeof(double2))
                         cp[om] = make_double2(x, -y);
