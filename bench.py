@@ -51,9 +51,10 @@ def parse():
     return ap.parse_args()
 
 
+# the files holding each filtering kernel's device code
 KERNEL_SOURCES = {
-    "fp32": ("apply_f32.hip", "chunk_io.h", "dft.h", "internal.h"),
-    "split": ("apply_split.hip", "chunk_io.h", "dft.h", "internal.h"),
+    "fp32": ("apply_f32.hip", "chunk_io.h", "dft.h"),
+    "split": ("apply_split.hip", "chunk_io.h", "dft.h", "split.h"),
 }
 
 
