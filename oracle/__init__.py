@@ -7,8 +7,9 @@ CPU-baseline leg do.  It shares no code with the HIP library.
 Everything here is plain NumPy/SciPy in complex128, written step by step from
 the paper (Sec. IV-A: LS eq. 8-9, LMMSE eq. 12-15, fixed design eq. 16 /
 r_d and eq. 17; Sec. IV-B: partitioning of the correlation matrix into small
-overlapping or non-overlapping blocks, Tables I-II) plus the readings of the
-points the paper leaves open, which are listed in each function.
+overlapping or non-overlapping blocks, Tables I-II; the comb-pilot 3W / 12W
+estimators of Sec. IV-B in comb.py) plus the readings of the points the paper
+leaves open, which are listed in each function.
 """
 from .lmmse import (  # noqa: F401
     apply_filters,
@@ -28,6 +29,14 @@ from .lmmse import (  # noqa: F401
     sample_covariance,
     toeplitz_from_r,
     window_starts,
+)
+from .comb import (  # noqa: F401
+    comb_estimate,
+    comb_filters,
+    comb_groups,
+    comb_ls,
+    comb_ls_hold,
+    zero_order_hold,
 )
 from .grad import (  # noqa: F401
     dr_exponential_dtau,

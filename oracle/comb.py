@@ -1,0 +1,97 @@
+"""FP64 oracle of the comb-pilot estimators 3W-LMMSE and 12W-LMMSE (Sec. IV-B,
+Tables I-II, the 3W weights and P, zero-order hold of Sec. IV-C).  Test
+infrastructure only, like the rest of this package.
+
+Pilot structure (Sec. II, eq. 6): a pilot OFDM symbol carries the pilot of
+UE s (0-based here) on the comb tones s, s + S, s + 2S, ... (N/S tones), so
+the received pilot symbol is y[slot][m][n] = H_{u(n)}[n] x[n] + w with u(n) =
+n mod S; x[n] is the pilot on subcarrier n (that of its UE).
+
+Readings:
+  * P in the 3W weights is the inverse (R_II + sigma^2/sigma_s^2 I)^-1, as in
+    eq. 13 / eq. 17 (the printed P lacks the inverse).
+  * One unit-modulus pilot symbol per LS value: sigma_s^2 = 1, so the
+    regulariser is lam = sigma2 itself.
+  * Zero-order hold (3W): every subcarrier without an estimate takes the
+    latest estimated subcarrier below it; subcarriers below the first
+    estimate take the first one.
+  * 3W outputs of a UE's last tone that fall past subcarrier N are dropped
+    (the table is printed for UE 1 only, whose outputs all fit).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .lmmse import C128, _filter, comb_group_table, toeplitz_from_r
+
+
+def comb_ls(y: np.ndarray, pilots: np.ndarray) -> np.ndarray:
+    """LS on every subcarrier of the pilot symbol, eq. 9: Y(k) / X(k).
+    y: [S][M][N], pilots: [N].  Returns complex128 [S][M][N]."""
+    return np.asarray(y).astype(C128) / np.asarray(pilots).astype(C128)[None, None, :]
+
+
+def comb_groups(N: int, S: int, ue: int, kind: str):
+    """The groups of UE `ue` (0-based) as 0-based (outputs, LS tones) lists,
+    from the 1-based tables (Tables I and II).  3W outputs that fall past the
+    band (UE offsets of S/3 and more on the last tone) are dropped."""
+    rows = comb_group_table(N, S, ue + 1, kind)
+    return [([o - 1 for o in outs if o <= N], [t - 1 for t in ls]) for (_, outs, _, ls) in rows]
+
+
+def comb_filters(N: int, S: int, ue: int, kind: str, r_of_d, lam: float):
+    """W_b = R_OI (R_II + lam I)^-1 of every group b of UE `ue`, with
+    R[a, b] = r(a - b) over the subcarrier indices (eq. 13, eq. 17)."""
+    out = []
+    for outs, tones in comb_groups(N, S, ue, kind):
+        R_oi = toeplitz_from_r(r_of_d, outs, tones)
+        R_ii = toeplitz_from_r(r_of_d, tones, tones)
+        out.append(_filter(R_oi, R_ii, lam))
+    return out
+
+
+def zero_order_hold(vals: np.ndarray, have: np.ndarray) -> np.ndarray:
+    """Fill the subcarriers without an estimate (have[n] False) from the
+    latest estimated one below, or from the first one below none."""
+    vals = np.array(vals, dtype=C128)
+    idx = np.flatnonzero(have)
+    if idx.size == 0:
+        raise ValueError("no estimate to hold")
+    out = vals.copy()
+    last = idx[0]
+    for n in range(vals.shape[-1]):
+        if have[n]:
+            last = n
+        out[..., n] = vals[..., last]
+    return out
+
+
+def comb_estimate(y, pilots, sigma2: float, S: int, ues, kind: str, r_of_d) -> np.ndarray:
+    """3W / 12W estimate of the UEs `ues` (0-based comb offsets).
+    y: [slots][M][N] pilot symbol, pilots: [N].  Returns [slots][M][len(ues)][N]."""
+    ls = comb_ls(y, pilots)
+    nsl, M, N = ls.shape
+    out = np.zeros((nsl, M, len(ues), N), dtype=C128)
+    for ui, ue in enumerate(ues):
+        Ws = comb_filters(N, S, ue, kind, r_of_d, sigma2)
+        have = np.zeros(N, dtype=bool)
+        est = np.zeros((nsl, M, N), dtype=C128)
+        for W, (outs, tones) in zip(Ws, comb_groups(N, S, ue, kind)):
+            est[:, :, outs] = ls[:, :, tones] @ W.T
+            have[outs] = True
+        out[:, :, ui, :] = est if have.all() else zero_order_hold(est, have)
+    return out
+
+
+def comb_ls_hold(y, pilots, S: int, ues) -> np.ndarray:
+    """The LS values on each UE's tones held over the subcarriers between
+    them (the zero-order-hold LS baseline of Sec. IV-C)."""
+    ls = comb_ls(y, pilots)
+    nsl, M, N = ls.shape
+    out = np.zeros((nsl, M, len(ues), N), dtype=C128)
+    for ui, ue in enumerate(ues):
+        have = np.zeros(N, dtype=bool)
+        have[ue::S] = True
+        est = np.where(have[None, None, :], ls, 0)
+        out[:, :, ui, :] = zero_order_hold(est, have)
+    return out

@@ -11,6 +11,8 @@ from .slots import (  # noqa: F401
     PILOT_SEED,
     SlotBatch,
     exponential_pdp,
+    CombBatch,
+    make_comb_batch,
     make_config_batch,
     make_pilots,
     make_slot_batch,

@@ -141,3 +141,48 @@ def make_config_batch(name: str, slots: int | None = None, **over) -> SlotBatch:
                            first_slot=c.get("first_slot", 0),
                            want_truth=c.get("want_truth", True),
                            noiseless=c.get("noiseless", False))
+
+
+@dataclass
+class CombBatch:
+    y: np.ndarray            # [S][M][N] complex64, the received comb pilot symbol
+    pilots: np.ndarray       # [N] complex64, pilot of the UE owning each subcarrier
+    sigma2: float
+    H: np.ndarray            # [S][M][K][N] complex128 truth of the active UEs
+    meta: dict = field(default_factory=dict)
+
+
+def make_comb_batch(M: int, K: int, N: int, N_fft: int, powers_db, snr_db: float | None,
+                    slots: int = 1, comb: int = 12, config_id: int = 5,
+                    seed_base: int = PILOT_SEED, pilot_seed: int = PILOT_SEED) -> CombBatch:
+    """Comb pilots (Sec. II, eq. 6): UE k < K owns the subcarriers k, k + comb,
+    k + 2 comb, ... of one pilot OFDM symbol and sends a unit-modulus QPSK
+    pilot there; subcarriers of inactive comb offsets carry noise only.
+    Channel taps at integer delays 0..len(powers_db)-1 with the given powers
+    in dB (normalised to sum 1), CN per (slot, antenna, UE)."""
+    p = 10.0 ** (np.asarray(powers_db, dtype=np.float64) / 10.0)
+    p = p / p.sum()
+    taps = p.size
+    rng0 = np.random.Generator(np.random.PCG64(pilot_seed + 7))
+    bits = rng0.integers(0, 2, size=(N, 2))
+    pil = (((1 - 2 * bits[:, 0]) + 1j * (1 - 2 * bits[:, 1])) / np.sqrt(2.0)).astype(np.complex64)
+    sigma2 = 0.0 if snr_db is None else float(10.0 ** (-snr_db / 10.0))
+    y = np.empty((slots, M, N), dtype=np.complex64)
+    H = np.empty((slots, M, K, N), dtype=np.complex128)
+    owner = np.arange(N) % comb
+    for i in range(slots):
+        rng = np.random.Generator(np.random.PCG64(slot_seed(config_id, i, seed_base)))
+        g = rng.standard_normal((M, K, taps, 2))
+        h = (g[..., 0] + 1j * g[..., 1]) * np.sqrt(p / 2.0)
+        Hi = np.fft.fft(h, n=N_fft, axis=-1)[..., :N]
+        H[i] = Hi
+        yi = np.zeros((M, N), dtype=np.complex128)
+        for k in range(K):
+            sel = owner == k
+            yi[:, sel] = Hi[:, k, sel] * pil[sel].astype(np.complex128)
+        if sigma2 > 0:
+            w = rng.standard_normal((M, N, 2))
+            yi = yi + (w[..., 0] + 1j * w[..., 1]) * np.sqrt(sigma2 / 2.0)
+        y[i] = yi.astype(np.complex64)
+    meta = dict(M=M, K=K, N=N, N_fft=N_fft, comb=comb, powers_db=list(powers_db), snr_db=snr_db)
+    return CombBatch(y=y, pilots=pil, sigma2=sigma2, H=H, meta=meta)

@@ -1,0 +1,102 @@
+"""Pins of the comb-pilot 3W / 12W oracle (Sec. IV-B, Tables I-II, the
+printed 3W weight placements, zero-order hold of Sec. IV-C): index maps from
+the printed tables, the printed r_d placements of W(1..3) and P, filter
+sharing as the text states it, exact recovery in the rank-one special case,
+a brute-force hold, and the relative accuracy the text reports for Fig. 7(a)
+as a statistical shape check."""
+import numpy as np
+import pytest
+
+import oracle as O
+from synth import make_comb_batch
+
+
+def _r_test(d):
+    # a generic Hermitian correlation (r_{-d} = conj(r_d)) with distinct values
+    return O.r_exponential(d, 3.0, 12, 256)
+
+
+def test_groups_follow_tables_one_and_two():
+    g3 = O.comb_groups(1200, 12, 0, "3w")
+    assert g3[0] == ([0, 4, 8], [0, 12, 24]) and g3[1] == ([12, 16, 20], [0, 12, 24])
+    assert g3[2] == ([24, 28, 32], [12, 24, 36]) and g3[3] == ([36, 40, 44], [24, 36, 48])
+    assert g3[98] == ([1176, 1180, 1184], [1164, 1176, 1188])
+    assert g3[99] == ([1188, 1192, 1196], [1164, 1176, 1188])
+    g12 = O.comb_groups(1200, 12, 0, "12w")
+    for b in range(6):
+        assert g12[b] == (list(range(12 * b, 12 * b + 12)), list(range(0, 133, 12)))
+    assert g12[6][1] == list(range(12, 145, 12)) and g12[7][1] == list(range(24, 157, 12))
+    for b in range(93, 100):
+        assert g12[b][1] == list(range(1056, 1189, 12))
+    # Table II row 100 printed as 1190:1:1200; 100 groups of 12 tile 1..1200
+    assert g12[99][0] == list(range(1188, 1200))
+
+
+def test_3w_weights_match_the_printed_placements():
+    lam = 0.03
+    r = {d: complex(_r_test(np.array([d]))[0]) for d in range(-40, 41)}
+    P = np.array([[r[0], r[-12], r[-24]], [r[12], r[0], r[-12]], [r[24], r[12], r[0]]])
+    Pinv = np.linalg.inv(P + lam * np.eye(3))
+    W1 = np.array([[r[0], r[-12], r[-24]], [r[4], r[-8], r[-20]], [r[8], r[-4], r[-16]]]) @ Pinv
+    W2 = np.array([[r[12], r[0], r[-12]], [r[16], r[4], r[-8]], [r[20], r[8], r[-4]]]) @ Pinv
+    W3 = np.array([[r[24], r[12], r[0]], [r[28], r[16], r[4]], [r[32], r[20], r[8]]]) @ Pinv
+    for ue in range(4):   # the text: W(1..3) serve every UE
+        Ws = O.comb_filters(1200, 12, ue, "3w", _r_test, lam)
+        assert np.allclose(Ws[0], W1, atol=1e-12)
+        for b in range(1, 99):
+            assert np.allclose(Ws[b], W2, atol=1e-12)
+        assert np.allclose(Ws[99], W3, atol=1e-12)
+
+
+def test_12w_has_twelve_filters_per_ue_and_they_differ_between_ues():
+    sets = []
+    for ue in range(4):
+        Ws = O.comb_filters(1200, 12, ue, "12w", _r_test, 0.01)
+        distinct = []
+        for w in Ws:
+            if not any(np.allclose(w, c) for c in distinct):
+                distinct.append(w)
+        assert len(distinct) == 12
+        assert all(np.allclose(Ws[b], Ws[6]) for b in range(6, 94))
+        sets.append(distinct)
+    assert not np.allclose(sets[0][0], sets[1][0])
+
+
+@pytest.mark.parametrize("kind", ["3w", "12w"])
+def test_rank_one_correlation_recovers_a_flat_channel(kind):
+    """One tap: H is flat, r_d = 1; with a tiny regulariser the filter
+    averages the window's LS values, which all equal H."""
+    cb = make_comb_batch(M=2, K=3, N=240, N_fft=256, powers_db=[0.0], snr_db=None, slots=1)
+    est = O.comb_estimate(cb.y, cb.pilots, 1e-6, 12, range(3), kind,
+                          lambda d: np.ones(np.shape(d), complex))
+    assert np.abs(est - cb.H).max() <= 1e-5 * np.abs(cb.H).max()
+
+
+def test_zero_order_hold_brute_force():
+    have = np.zeros(10, dtype=bool)
+    have[[3, 4, 8]] = True
+    v = np.arange(10) + 0j
+    out = O.zero_order_hold(v, have)
+    assert list(out.real) == [3, 3, 3, 3, 4, 4, 4, 4, 8, 8]
+
+
+def test_ls_is_exact_without_noise():
+    cb = make_comb_batch(M=3, K=4, N=240, N_fft=256, powers_db=[0, -3, -6], snr_db=None, slots=2)
+    ls = O.comb_ls(cb.y, cb.pilots)
+    for k in range(4):
+        assert np.allclose(ls[:, :, k::12], cb.H[:, :, k, k::12], atol=1e-6)
+
+
+def test_relative_accuracy_matches_fig7a_text():
+    """Statistical shape check on a Table III-like system (16 antennas, 4
+    active UEs, 6 taps at delays 0..5 with the listed powers, assumed L = 8):
+    the text reports 12W about 7 dB and 3W about 3.8 dB better than LS."""
+    cb = make_comb_batch(M=16, K=4, N=1200, N_fft=2048, powers_db=[-2, -8, -10, -12, -15, -18],
+                         snr_db=20.0, slots=4)
+    rd = lambda d: O.r_uniform(d, 8.0, 2048)
+    ls = O.nmse_db(O.comb_ls_hold(cb.y, cb.pilots, 12, range(4)), cb.H)
+    w3 = O.nmse_db(O.comb_estimate(cb.y, cb.pilots, cb.sigma2, 12, range(4), "3w", rd), cb.H)
+    w12 = O.nmse_db(O.comb_estimate(cb.y, cb.pilots, cb.sigma2, 12, range(4), "12w", rd), cb.H)
+    assert 5.5 < ls - w12 < 8.5
+    assert 2.5 < ls - w3 < 5.0
+    assert w12 < w3 < ls
