@@ -254,6 +254,73 @@ int lmmse_backward(lmmse_plan_t plan, int slots, const void *h_ls,
  * sample path, the class for fixed designs) or -1. */
 int lmmse_sync_status(lmmse_plan_t plan, void *stream, int *info);
 
+/* ---- comb-pilot 3W / 12W estimators (Sec. IV-B, Tables I-II) ------------- */
+
+/* The paper's own partitioned estimators for comb pilots.  One pilot OFDM
+ * symbol carries the pilot of UE k (0-based) on the comb tones k, k + S,
+ * k + 2S, ... (S = comb spacing, N / S tones; eq. 6), so
+ *   y[slot][m][n] = H_k[n] x[n] + w,  k = n mod S,
+ * and the LS value of UE k on its tone t is y[t] / x[t] (eq. 9).  Group b of
+ * a UE (one per tone) filters the `win` consecutive tones starting at
+ *   wst_b = clamp(b - (win - 1) / 2, 0, N/S - win)
+ * (win = 3 for 3W, 12 for 12W; Tables I and II) with
+ *   W_b = R_OI (R_II + sigma2 I)^-1,  R[a][c] = r(a - c)
+ * (eq. 13 / eq. 17 with a unit-modulus pilot: sigma_s^2 = 1; the 3W weights
+ * W(1..3) with P read as the inverse), r from eq. 16 (UNIFORM, length L) or
+ * the exponential tap sum (EXPONENTIAL).  Outputs of group b:
+ *   LMMSE_COMB_3W:  subcarriers k + S b + j S/3, j = 0..2 (those below N),
+ *                   and every subcarrier without an estimate takes the
+ *                   latest estimate below it (zero-order hold, Sec. IV-C),
+ *                   the first estimate below the first one;
+ *   LMMSE_COMB_12W: the S subcarriers S b .. S b + S - 1.
+ * W_b depends only on b - wst_b (and, for 12W, on k): each UE has `win`
+ * filter classes, designed in FP64 on the device when the plan is made and
+ * applied in FP32. */
+typedef enum lmmse_comb_kind {
+    LMMSE_COMB_3W = 0,
+    LMMSE_COMB_12W = 1
+} lmmse_comb_kind;
+
+typedef struct lmmse_comb_desc {
+    int M;           /* BS antennas                                   (>= 1) */
+    int K;           /* active UEs = comb offsets 0..K-1           (1..comb) */
+    int comb;        /* comb spacing S: N % S == 0; 3W: S % 3 == 0;
+                        12W: S <= 16                                         */
+    int N;           /* used subcarriers; N / S >= win and <= 4096          */
+    int N_fft;       /* FFT size (>= N)                                      */
+    int kind;        /* lmmse_comb_kind                                      */
+    int rsource;     /* LMMSE_R_UNIFORM or LMMSE_R_EXPONENTIAL               */
+    int taps;        /* EXPONENTIAL: integer taps (1..N_fft)                 */
+    double tau_rms;  /* EXPONENTIAL: profile decay (> 0)                     */
+    double L;        /* UNIFORM: assumed channel length in samples (> 0)     */
+    double sigma2;   /* noise variance per resource element (> 0)            */
+    int max_slots;   /* largest batch any call will pass (>= 1)              */
+} lmmse_comb_desc;
+
+typedef struct lmmse_comb *lmmse_comb_t;
+
+/* Host-only check of a descriptor: OK, INVALID_ARG or UNSUPPORTED. */
+int lmmse_comb_validate(const lmmse_comb_desc *desc);
+
+/* Validates, allocates the plan's filters on the current device and designs
+ * them (synchronously).  Errors: INVALID_ARG, UNSUPPORTED, NO_DEVICE, HIP,
+ * NOT_PD. */
+int lmmse_comb_create(const lmmse_comb_desc *desc, lmmse_comb_t *out);
+
+/* Frees the plan (synchronises the device first). */
+int lmmse_comb_destroy(lmmse_comb_t comb);
+
+/* Copies the FP64 filter classes to device complex128
+ * [K][win][nout][win] (class c = b - wst_b; nout = 3 for 3W, S for 12W;
+ * rows of 3W outputs past N are still designed).  Asynchronous. */
+int lmmse_comb_get_filters(lmmse_comb_t comb, void *w_out, void *stream);
+
+/* y: complex64 [slots][M][N] pilot symbol; pilots: complex64 [N], the pilot
+ * on each subcarrier (nonzero); h_hat: complex64 [slots][M][K][N].  One
+ * launch on `stream`. */
+int lmmse_comb_estimate(lmmse_comb_t comb, int slots, const void *y,
+                        const void *pilots, void *h_hat, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

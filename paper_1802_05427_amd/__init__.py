@@ -4,6 +4,7 @@ thin torch binding.  Importing this package does not touch the GPU; creating
 a Plan loads the library and fails loudly if it has not been built.
 """
 from ._lib import LmmseError, load  # noqa: F401
-from .api import Plan, block_plan, make_desc, workspace_size  # noqa: F401
+from .api import CombPlan, Plan, block_plan, comb_validate, make_desc, workspace_size  # noqa: F401
 
-__all__ = ["Plan", "block_plan", "make_desc", "workspace_size", "LmmseError", "load"]
+__all__ = ["Plan", "CombPlan", "block_plan", "comb_validate", "make_desc", "workspace_size",
+           "LmmseError", "load"]

@@ -34,6 +34,20 @@ class PlanDesc(ctypes.Structure):
 
 P_desc = ctypes.POINTER(PlanDesc)
 
+# lmmse_comb_kind
+COMB_3W, COMB_12W = range(2)
+
+
+class CombDesc(ctypes.Structure):
+    _fields_ = [
+        ("M", c_int), ("K", c_int), ("comb", c_int), ("N", c_int), ("N_fft", c_int),
+        ("kind", c_int), ("rsource", c_int), ("taps", c_int),
+        ("tau_rms", c_double), ("L", c_double), ("sigma2", c_double), ("max_slots", c_int),
+    ]
+
+
+P_cdesc = ctypes.POINTER(CombDesc)
+
 # name -> (restype, argtypes); mirrors include/lmmse.h
 PROTOTYPES = {
     "lmmse_status_string": (ctypes.c_char_p, [c_int]),
@@ -58,6 +72,11 @@ PROTOTYPES = {
     "lmmse_backward": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, P_double,
                                P_double, c_void_p, c_size_t, c_void_p]),
     "lmmse_sync_status": (c_int, [c_void_p, c_void_p, P_int]),
+    "lmmse_comb_validate": (c_int, [P_cdesc]),
+    "lmmse_comb_create": (c_int, [P_cdesc, ctypes.POINTER(c_void_p)]),
+    "lmmse_comb_destroy": (c_int, [c_void_p]),
+    "lmmse_comb_get_filters": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "lmmse_comb_estimate": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
 }
 
 _LIB = None

@@ -13,7 +13,7 @@ import math
 import torch
 
 from . import _lib
-from ._lib import PlanDesc, check
+from ._lib import CombDesc, PlanDesc, check
 
 _RSOURCE = {"uniform": _lib.R_UNIFORM, "exp": _lib.R_EXPONENTIAL,
             "sample": _lib.R_SAMPLE, "user": _lib.R_USER}
@@ -225,3 +225,82 @@ class Plan:
         info = ctypes.c_int(-1)
         st = self._lib.lmmse_sync_status(self._h, _stream_ptr(stream), ctypes.byref(info))
         return st, info.value
+
+
+_COMB_KIND = {"3w": _lib.COMB_3W, "12w": _lib.COMB_12W}
+
+
+def make_comb_desc(M, K, N, N_fft, comb=12, kind="12w", rsource="uniform", L=8.0, tau_rms=1.0,
+                   taps=1, sigma2=0.1, max_slots=1) -> CombDesc:
+    return CombDesc(M=int(M), K=int(K), comb=int(comb), N=int(N), N_fft=int(N_fft),
+                    kind=_COMB_KIND[kind] if isinstance(kind, str) else int(kind),
+                    rsource=_RSOURCE[rsource] if isinstance(rsource, str) else int(rsource),
+                    taps=int(taps), tau_rms=float(tau_rms), L=float(L), sigma2=float(sigma2),
+                    max_slots=int(max_slots))
+
+
+def comb_validate(**kw) -> int:
+    """Status of a comb descriptor (host only)."""
+    d = make_comb_desc(**kw)
+    return _lib.load().lmmse_comb_validate(ctypes.byref(d))
+
+
+class CombPlan:
+    """Comb-pilot 3W / 12W estimator on the current GPU (see include/lmmse.h)."""
+
+    def __init__(self, **kw):
+        self._lib = _lib.load()
+        self.desc = make_comb_desc(**kw)
+        h = ctypes.c_void_p()
+        check(self._lib.lmmse_comb_create(ctypes.byref(self.desc), ctypes.byref(h)),
+              "lmmse_comb_create")
+        self._h = h
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        d = self.desc
+        self.win = 3 if d.kind == _lib.COMB_3W else 12
+        self.nout = 3 if d.kind == _lib.COMB_3W else d.comb
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.lmmse_comb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def get_filters(self, stream=None) -> torch.Tensor:
+        """FP64 filter classes, complex128 [K][win][nout][win]."""
+        d = self.desc
+        w = torch.empty((d.K, self.win, self.nout, self.win), dtype=torch.complex128, device=self.device)
+        check(self._lib.lmmse_comb_get_filters(self._h, _ptr(w), _stream_ptr(stream)),
+              "lmmse_comb_get_filters")
+        return w
+
+    def estimate(self, y, pilots, out=None, stream=None) -> torch.Tensor:
+        """y: complex64 [S][M][N] comb pilot symbol; pilots: complex64 [N].
+        Returns complex64 [S][M][K][N]."""
+        d = self.desc
+        if (y.dtype != torch.complex64 or y.device.type != "cuda" or not y.is_contiguous()
+                or y.dim() != 3 or tuple(y.shape[1:]) != (d.M, d.N) or y.shape[0] > d.max_slots):
+            raise ValueError(f"y must be a contiguous complex64 CUDA [S<={d.max_slots}, {d.M}, {d.N}] tensor")
+        if (pilots.dtype != torch.complex64 or pilots.device.type != "cuda"
+                or not pilots.is_contiguous() or tuple(pilots.shape) != (d.N,)):
+            raise ValueError(f"pilots must be a contiguous complex64 CUDA [{d.N}] tensor")
+        S = int(y.shape[0])
+        shape = (S, d.M, d.K, d.N)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.complex64, device=y.device)
+        elif tuple(out.shape) != shape or out.dtype != torch.complex64 or not out.is_contiguous():
+            raise ValueError(f"out must be a contiguous complex64 {shape} tensor")
+        check(self._lib.lmmse_comb_estimate(self._h, S, _ptr(y), _ptr(pilots), _ptr(out),
+                                            _stream_ptr(stream)), "lmmse_comb_estimate")
+        return out

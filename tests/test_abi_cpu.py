@@ -162,3 +162,19 @@ def test_sample_window_limits():
         + 32 * nmat1 * 8 + (1 << 20)
     with pytest.raises(_lib.LmmseError):
         workspace_size(_d(rsource="sample", N=1040, B=130, Wn=260), 1)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(), _lib.OK), (dict(kind="3w"), _lib.OK), (dict(rsource="exp", tau_rms=2.0, taps=6), _lib.OK),
+    (dict(K=0), _lib.INVALID_ARG), (dict(kind=5), _lib.INVALID_ARG), (dict(sigma2=0.0), _lib.INVALID_ARG),
+    (dict(rsource="sample"), _lib.INVALID_ARG), (dict(L=-1.0), _lib.INVALID_ARG),
+    (dict(K=13), _lib.UNSUPPORTED), (dict(N=1210), _lib.UNSUPPORTED),
+    (dict(comb=8, N=1200, kind="3w"), _lib.UNSUPPORTED), (dict(comb=18, N=1206 * 3, N_fft=4096), _lib.UNSUPPORTED),
+    (dict(N=120), _lib.UNSUPPORTED), (dict(N=2400, N_fft=2048), _lib.UNSUPPORTED),
+])
+def test_comb_validate(kw, code):
+    from paper_1802_05427_amd import comb_validate
+    base = dict(M=16, K=4, N=1200, N_fft=2048, comb=12, kind="12w", rsource="uniform", L=8.0,
+                sigma2=0.01, max_slots=4)
+    base.update(kw)
+    assert comb_validate(**base) == code
