@@ -46,6 +46,8 @@ def parse():
                     help="only time the fwd+bwd training step (16 slots) and print its line")
     ap.add_argument("--large-only", action="store_true",
                     help="only run the large sample-covariance workload (M=256, K=24, N=3300)")
+    ap.add_argument("--comb-only", action="store_true",
+                    help="only run the comb-pilot 3W / 12W lines")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
     return ap.parse_args()
@@ -213,6 +215,47 @@ def large_sample(dev, stream, precision="fp16x3", slots=32, steps=3, warmup=1):
     return res
 
 
+def comb_lines(dev, stream, steps=20, warmup=3):
+    """The paper's comb-pilot estimators (Sec. IV-B): one pilot symbol with
+    comb spacing 12, 4 active UEs, the paper-sized band (N=1200 of 2048),
+    128 antennas, 64 slots, the 6-tap profile of the paper's simulation setup
+    (delays 0..5, -2/-8/-10/-12/-15/-18 dB) at SNR 20 dB, design from eq. 16
+    with L = 8.  HBM-bound: 8 B written per output coefficient plus the comb
+    tones read (8/12 B per output)."""
+    import numpy as np
+    import torch
+
+    import oracle as O
+    from paper_1802_05427_amd import CombPlan
+    from synth import make_comb_batch
+    M, K, N, Nf, S, slots, uniq = 128, 4, 1200, 2048, 12, 64, 4
+    cb = make_comb_batch(M=M, K=K, N=N, N_fft=Nf, powers_db=[-2, -8, -10, -12, -15, -18],
+                         snr_db=20.0, slots=uniq, comb=S)
+    y = torch.from_numpy(cb.y).to(dev).repeat(slots // uniq, 1, 1).contiguous()
+    pil = torch.from_numpy(cb.pilots).to(dev)
+    coeffs = slots * M * K * N
+    res = {}
+    rd = lambda d: O.r_uniform(d, 8.0, Nf)
+    for kind in ("3w", "12w"):
+        with CombPlan(M=M, K=K, N=N, N_fft=Nf, comb=S, kind=kind, rsource="uniform", L=8.0,
+                      sigma2=cb.sigma2, max_slots=slots) as pl:
+            out = torch.empty((slots, M, K, N), dtype=torch.complex64, device=dev)
+            t_ms = time_calls(lambda: pl.estimate(y, pil, out=out), steps, warmup, stream)
+            o1 = out[:1].cpu().numpy()
+        ref = O.comb_estimate(cb.y[:1], cb.pilots, cb.sigma2, S, range(K), kind, rd)
+        gbs = coeffs * (8.0 + 8.0 / S) / (t_ms * 1e-3) / 1e9
+        res[kind] = {"value": round(coeffs / (t_ms * 1e-3), 1), "ms": round(t_ms, 4),
+                     "hbm_GBs": round(gbs, 1), "hbm_frac": round(gbs / PEAK["hbm_GBs"], 4),
+                     "nmse_db": round(O.nmse_db(o1, cb.H[:1]), 3),
+                     "nmse_gap_db": abs(O.nmse_db(o1, cb.H[:1]) - O.nmse_db(ref, cb.H[:1])),
+                     "discrepancy_db": round(O.discrepancy_db(o1, ref), 1)}
+    ls = O.nmse_db(O.comb_ls_hold(cb.y[:1], cb.pilots, S, range(K)), cb.H[:1])
+    res["ls_hold_nmse_db"] = round(ls, 3)
+    res["workload"] = (f"comb pilots (spacing {S}), M={M}, {K} active UEs, N={N} of {Nf}, {slots} slots, "
+                       "6-tap profile, SNR 20 dB, eq. 16 design with L=8")
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -237,6 +280,11 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": 4 * n, "launches": 5}), flush=True)
+        return
+    if args.comb_only:
+        r = comb_lines(dev, torch.cuda.current_stream())
+        print(json.dumps({"metric": "channel coeffs estimated/s, comb-pilot 3W / 12W", "detail": r}),
+              flush=True)
         return
     if args.large_only:
         r = large_sample(dev, torch.cuda.current_stream(), steps=max(2, min(args.steps, 5)),
@@ -374,6 +422,7 @@ def main():
         del y, out
         torch.cuda.empty_cache()
         extras["large_sample"] = large_sample(dev, stream)
+        extras["comb"] = comb_lines(dev, stream)
 
     cpu = None
     if not args.no_cpu_baseline:
