@@ -120,57 +120,62 @@ __global__ __launch_bounds__(256) void comb_design_kernel(lmmse_comb_desc d, int
     }
 }
 
-// One (column c = slot * M + antenna, UE k) per workgroup: the UE's comb LS
-// values and filter classes into LDS, then one group per thread.
-__global__ __launch_bounds__(128) void comb_apply_kernel(lmmse_comb_desc d, int win, int nout,
-                                                         int ntones, const float2* y,
+constexpr int kCombCols = 8;   // columns per workgroup (filter classes loaded once)
+
+// UE k = blockIdx.y and kCombCols columns (c = slot * M + antenna) per
+// workgroup: the UE's filter classes into LDS once, then per column its comb
+// LS values into LDS and one output subcarrier per thread (consecutive
+// threads write consecutive subcarriers).  Subcarrier p belongs to group
+// b = (p - k) / S (12W: p / S) and takes output j of it: 12W j = p mod S;
+// 3W the latest of the group's outputs at or below p (j = 0 below the first
+// tone: the hold).
+__global__ __launch_bounds__(256) void comb_apply_kernel(lmmse_comb_desc d, int win, int nout,
+                                                         int ntones, long long ncols, const float2* y,
                                                          const float2* pilots, const float2* w32,
                                                          float2* out) {
     extern __shared__ float2 sm[];
-    float2* ls = sm;                        // [ntones]
-    float2* wc = sm + ntones;               // [win][nout][win]
-    const long long c = blockIdx.x;
+    float2* wc = sm;                        // [win][nout][win]
+    float2* ls = sm + win * nout * win;     // [ntones]
     const int k = blockIdx.y, tid = threadIdx.x, S = d.comb, N = d.N;
-    const float2* yc = y + c * N;
-    for (int i = tid; i < ntones; i += 128) {
-        const int t = k + S * i;
-        const float2 v = yc[t], x = pilots[t];
-        const float inv = 1.0f / (x.x * x.x + x.y * x.y);
-        // eq. 9: Y / X = Y conj(X) / |X|^2
-        ls[i] = make_float2((v.x * x.x + v.y * x.y) * inv, (v.y * x.x - v.x * x.y) * inv);
-    }
     const int nw = win * nout * win;
-    for (int e = tid; e < nw; e += 128) wc[e] = w32[(size_t)k * nw + e];
-    __syncthreads();
-    float2* oc = out + (c * d.K + k) * (long long)N;
-    for (int b = tid; b < ntones; b += 128) {
-        const int wst = min(max(b - (win - 1) / 2, 0), ntones - win), cls = b - wst;
-        const float2* W = wc + cls * nout * win;
-        float2 acc[kCombOutMax];
-#pragma unroll
-        for (int o = 0; o < kCombOutMax; ++o) {
-            acc[o] = make_float2(0.f, 0.f);
-            if (o < nout)
-                for (int j = 0; j < win; ++j) {
-                    const float2 w = W[o * win + j], x = ls[wst + j];
-                    acc[o].x += w.x * x.x - w.y * x.y;
-                    acc[o].y += w.x * x.y + w.y * x.x;
-                }
+    for (int e = tid; e < nw; e += 256) wc[e] = w32[(size_t)k * nw + e];
+    const long long c0 = (long long)blockIdx.x * kCombCols;
+    for (int cc = 0; cc < kCombCols; ++cc) {
+        const long long c = c0 + cc;
+        if (c >= ncols) break;   // uniform
+        const float2* yc = y + c * N;
+        for (int i = tid; i < ntones; i += 256) {
+            const int t = k + S * i;
+            const float2 v = yc[t], x = pilots[t];
+            const float inv = 1.0f / (x.x * x.x + x.y * x.y);
+            // eq. 9: Y / X = Y conj(X) / |X|^2
+            ls[i] = make_float2((v.x * x.x + v.y * x.y) * inv, (v.y * x.x - v.x * x.y) * inv);
         }
-        if (d.kind == LMMSE_COMB_12W) {
-#pragma unroll
-            for (int o = 0; o < kCombOutMax; ++o)
-                if (o < nout) oc[S * b + o] = acc[o];
-        } else {
-            // the group's S subcarriers from its first tone, held from the
-            // estimate at or below each; the first group also fills below it
-            const int p0 = k + S * b, step = S / 3;
-            const int lo = b == 0 ? 0 : p0, hi = min(p0 + S, N);
-            for (int p = lo; p < hi; ++p) {
-                const int j = p < p0 ? 0 : min((p - p0) / step, 2);
-                oc[p] = j == 0 ? acc[0] : (j == 1 ? acc[1] : acc[2]);
+        __syncthreads();
+        float2* oc = out + (c * d.K + k) * (long long)N;
+        for (int p = tid; p < N; p += 256) {
+            int b, j;
+            if (d.kind == LMMSE_COMB_12W) {
+                b = p / S;
+                j = p - b * S;
+            } else if (p < k) {
+                b = 0;
+                j = 0;
+            } else {
+                b = min((p - k) / S, ntones - 1);
+                j = min((p - k - S * b) / (S / 3), 2);
             }
+            const int wst = min(max(b - (win - 1) / 2, 0), ntones - win);
+            const float2* W = wc + ((b - wst) * nout + j) * win;
+            float2 acc = make_float2(0.f, 0.f);
+            for (int i = 0; i < win; ++i) {
+                const float2 w = W[i], x = ls[wst + i];
+                acc.x += w.x * x.x - w.y * x.y;
+                acc.y += w.x * x.y + w.y * x.x;
+            }
+            oc[p] = acc;
         }
+        __syncthreads();
     }
 }
 
@@ -272,8 +277,9 @@ int lmmse_comb_estimate(lmmse_comb_t c, int slots, const void* y, const void* pi
     const CombPlan& p = c->p;
     const long long ncols = (long long)slots * p.d.M;
     const size_t shm = ((size_t)p.ntones + (size_t)p.win * p.nout * p.win) * sizeof(float2);
-    hipLaunchKernelGGL(lmmse::comb_apply_kernel, dim3((unsigned)ncols, p.d.K), dim3(128), shm,
-                       (hipStream_t)stream, p.d, p.win, p.nout, p.ntones, (const float2*)y,
+    const long long nblk = (ncols + lmmse::kCombCols - 1) / lmmse::kCombCols;
+    hipLaunchKernelGGL(lmmse::comb_apply_kernel, dim3((unsigned)nblk, p.d.K), dim3(256), shm,
+                       (hipStream_t)stream, p.d, p.win, p.nout, p.ntones, ncols, (const float2*)y,
                        (const float2*)pilots, p.w32, (float2*)h_hat);
     return hipGetLastError() == hipSuccess ? LMMSE_OK : LMMSE_ERR_HIP;
 }
