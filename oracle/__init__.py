@@ -8,7 +8,8 @@ Everything here is plain NumPy/SciPy in complex128, written step by step from
 the paper (Sec. IV-A: LS eq. 8-9, LMMSE eq. 12-15, fixed design eq. 16 /
 r_d and eq. 17; Sec. IV-B: partitioning of the correlation matrix into small
 overlapping or non-overlapping blocks, Tables I-II; the comb-pilot 3W / 12W
-estimators of Sec. IV-B in comb.py) plus the readings of the points the paper
+estimators of Sec. IV-B in comb.py; MMSE detection, eq. 20-22, in detect.py)
+plus the readings of the points the paper
 leaves open, which are listed in each function.
 """
 from .lmmse import (  # noqa: F401
@@ -38,6 +39,7 @@ from .comb import (  # noqa: F401
     comb_ls_hold,
     zero_order_hold,
 )
+from .detect import mmse_detect, qpsk_decide  # noqa: F401
 from .grad import (  # noqa: F401
     dr_exponential_dtau,
     grad_fixed_design,

@@ -14,6 +14,7 @@ from .slots import (  # noqa: F401
     CombBatch,
     make_comb_batch,
     make_config_batch,
+    make_data_symbols,
     make_pilots,
     make_slot_batch,
     slot_seed,

@@ -186,3 +186,20 @@ def make_comb_batch(M: int, K: int, N: int, N_fft: int, powers_db, snr_db: float
         y[i] = yi.astype(np.complex64)
     meta = dict(M=M, K=K, N=N, N_fft=N_fft, comb=comb, powers_db=list(powers_db), snr_db=snr_db)
     return CombBatch(y=y, pilots=pil, sigma2=sigma2, H=H, meta=meta)
+
+
+def make_data_symbols(H: np.ndarray, T: int, snr_db: float | None, seed: int = PILOT_SEED + 99):
+    """Data OFDM symbols for detection (eq. 7 per subcarrier): unit-power
+    QPSK X[s][t][k][n] from every user, received as Y[s][m][t][n] =
+    sum_k H[s][m][k][n] X[s][t][k][n] + w, w ~ CN(0, sigma2).
+    Returns (Y complex64, X complex128, sigma2)."""
+    S, M, K, N = H.shape
+    rng = np.random.Generator(np.random.PCG64(seed))
+    bits = rng.integers(0, 2, size=(S, T, K, N, 2))
+    X = ((1 - 2 * bits[..., 0]) + 1j * (1 - 2 * bits[..., 1])) / np.sqrt(2.0)
+    Y = np.einsum("smkn,stkn->smtn", H, X)
+    sigma2 = 0.0 if snr_db is None else float(10.0 ** (-snr_db / 10.0))
+    if sigma2 > 0:
+        w = rng.standard_normal((S, M, T, N, 2))
+        Y = Y + (w[..., 0] + 1j * w[..., 1]) * np.sqrt(sigma2 / 2.0)
+    return Y.astype(np.complex64), X, sigma2
