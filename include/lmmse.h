@@ -321,6 +321,21 @@ int lmmse_comb_get_filters(lmmse_comb_t comb, void *w_out, void *stream);
 int lmmse_comb_estimate(lmmse_comb_t comb, int slots, const void *y,
                         const void *pilots, void *h_hat, void *stream);
 
+/* ---- MMSE MIMO detection (Sec. III-C, eq. 20-22) ------------------------- */
+
+/* Per (slot s, data subcarrier n), with H = h_hat[s][:][:][n] (M x K) and
+ * Y = y_data[s][:][:][n] (M x T), writes X = x_out[s][:][:][n] (T x K as
+ * [T][K]) solving (H^H H + sigma2 I) X^T = H^H Y (eq. 22) by Cholesky in
+ * FP32, the paper's single-precision route.  h_hat: complex64
+ * [slots][M][K][N] (the estimator's layout); y_data: complex64
+ * [slots][M][T][N]; x_out: complex64 [slots][T][K][N]; sigma2 > 0 is the
+ * noise variance per resource element with unit-power symbols.  K <= 16 and
+ * T <= 16 (else UNSUPPORTED).  One launch on `stream`; a non-positive pivot
+ * yields NaN symbols for that subcarrier. */
+int lmmse_mmse_detect(int slots, int M, int K, int T, int N, const void *h_hat,
+                      const void *y_data, double sigma2, void *x_out,
+                      void *stream);
+
 #ifdef __cplusplus
 }
 #endif

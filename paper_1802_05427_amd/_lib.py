@@ -77,6 +77,8 @@ PROTOTYPES = {
     "lmmse_comb_destroy": (c_int, [c_void_p]),
     "lmmse_comb_get_filters": (c_int, [c_void_p, c_void_p, c_void_p]),
     "lmmse_comb_estimate": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "lmmse_mmse_detect": (c_int, [c_int, c_int, c_int, c_int, c_int, c_void_p, c_void_p, c_double,
+                                  c_void_p, c_void_p]),
 }
 
 _LIB = None

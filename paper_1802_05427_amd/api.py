@@ -304,3 +304,26 @@ class CombPlan:
         check(self._lib.lmmse_comb_estimate(self._h, S, _ptr(y), _ptr(pilots), _ptr(out),
                                             _stream_ptr(stream)), "lmmse_comb_estimate")
         return out
+
+
+def mmse_detect(h_hat: torch.Tensor, y_data: torch.Tensor, sigma2: float, out=None,
+                stream=None) -> torch.Tensor:
+    """MMSE MIMO detection (eq. 22) per (slot, subcarrier).
+    h_hat: complex64 [S, M, K, N]; y_data: complex64 [S, M, T, N].
+    Returns complex64 [S, T, K, N]."""
+    for t, name in ((h_hat, "h_hat"), (y_data, "y_data")):
+        if t.dtype != torch.complex64 or t.device.type != "cuda" or not t.is_contiguous() or t.dim() != 4:
+            raise ValueError(f"{name} must be a contiguous complex64 CUDA 4-d tensor")
+    S, M, K, N = h_hat.shape
+    if y_data.shape[0] != S or y_data.shape[1] != M or y_data.shape[3] != N:
+        raise ValueError("y_data must be [S, M, T, N] matching h_hat")
+    T = int(y_data.shape[2])
+    shape = (S, T, K, N)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.complex64, device=h_hat.device)
+    elif tuple(out.shape) != shape or out.dtype != torch.complex64 or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous complex64 {shape} tensor")
+    lib = _lib.load()
+    check(lib.lmmse_mmse_detect(int(S), int(M), int(K), T, int(N), _ptr(h_hat), _ptr(y_data),
+                                float(sigma2), _ptr(out), _stream_ptr(stream)), "lmmse_mmse_detect")
+    return out

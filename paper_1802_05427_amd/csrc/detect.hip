@@ -1,0 +1,169 @@
+// MMSE MIMO detection (Sec. III-C, eq. 20-22): per (slot s, data
+// subcarrier n), with H = h_hat[s, :, :, n] (M x K) and Y = y[s, :, :, n]
+// (M x T), the detected symbols solve
+//     (H^H H + sigma2 I) X = H^H Y                                  (eq. 22)
+// by a Cholesky factorisation A = L L^H and two triangular solves per data
+// symbol, in FP32 (the paper's LAPACKE_cposv is the single-precision
+// complex routine).
+//
+// One workgroup per (slot, 16 consecutive subcarriers).  Antennas are
+// streamed through LDS 8 at a time (each (antenna, user) row of 16
+// subcarriers is one 128-byte load); thread (l, i) accumulates row i of
+// [H^H H | H^H Y] for subcarrier l in registers.  The rows go to LDS (over
+// the staging area, after the last antenna), one
+// thread per subcarrier factors A in place, and one thread per (subcarrier,
+// data symbol) solves and writes its K symbols.
+#include <algorithm>
+
+#include "internal.h"
+
+namespace lmmse {
+
+constexpr int dNB = 16;   // subcarriers per workgroup
+constexpr int dMC = 8;    // antennas per LDS stage
+constexpr int dMaxK = 16, dMaxT = 16;
+
+__device__ __forceinline__ float2 cmul_conj_a(float2 a, float2 b) {   // conj(a) b
+    return make_float2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+
+__global__ __launch_bounds__(256) void mmse_detect_kernel(const float2* h, const float2* y, float2* x,
+                                                          int M, int K, int T, int N, float sigma2,
+                                                          int nblk) {
+    extern __shared__ float2 sm[];
+    const int KT = K + T;
+    float2* Hs = sm;                         // [dMC][K][dNB]
+    float2* Ys = Hs + dMC * K * dNB;         // [dMC][T][dNB]
+    float2* Gs = sm;                         // [dNB][K][KT], after the antenna loop
+    const int tid = threadIdx.x, l = tid & (dNB - 1), i = tid / dNB;
+    const long long s = blockIdx.x / nblk;
+    const int n0 = (int)(blockIdx.x % nblk) * dNB;
+    const float2* hs = h + s * (long long)M * K * N;
+    const float2* ys = y + s * (long long)M * T * N;
+
+    float2 acc[dMaxK + dMaxT];
+#pragma unroll
+    for (int c = 0; c < dMaxK + dMaxT; ++c) acc[c] = make_float2(0.f, 0.f);
+
+    for (int m0 = 0; m0 < M; m0 += dMC) {
+        for (int e = tid; e < dMC * KT * dNB; e += 256) {
+            const int ll = e % dNB, r = e / dNB, mm = r / KT, q = r - mm * KT;
+            const int m = m0 + mm, n = n0 + ll;
+            float2 v = make_float2(0.f, 0.f);
+            if (m < M && n < N)
+                v = q < K ? hs[((long long)m * K + q) * N + n] : ys[((long long)m * T + (q - K)) * N + n];
+            if (q < K)
+                Hs[(mm * K + q) * dNB + ll] = v;
+            else
+                Ys[(mm * T + (q - K)) * dNB + ll] = v;
+        }
+        __syncthreads();
+        if (i < K) {
+            for (int mm = 0; mm < dMC; ++mm) {
+                const float2 hi = Hs[(mm * K + i) * dNB + l];
+#pragma unroll
+                for (int c = 0; c < dMaxK + dMaxT; ++c) {
+                    if (c < KT) {
+                        const float2 v =
+                            c < K ? Hs[(mm * K + c) * dNB + l] : Ys[(mm * T + (c - K)) * dNB + l];
+                        const float2 p = cmul_conj_a(hi, v);
+                        acc[c].x += p.x;
+                        acc[c].y += p.y;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (i < K) {
+        float2* g = Gs + (l * K + i) * KT;
+#pragma unroll
+        for (int c = 0; c < dMaxK + dMaxT; ++c)
+            if (c < KT) g[c] = acc[c];
+        g[i].x += sigma2;
+    }
+    __syncthreads();
+    float2* G = Gs + l * K * KT;   // this subcarrier's [A | B]
+    if (i == 0) {
+        // A = L L^H in place (lower triangle), L_jj real
+        for (int j = 0; j < K; ++j) {
+            float d = G[j * KT + j].x;
+            for (int q = 0; q < j; ++q) {
+                const float2 v = G[j * KT + q];
+                d -= v.x * v.x + v.y * v.y;
+            }
+            d = d > 0.f ? sqrtf(d) : __builtin_nanf("");
+            G[j * KT + j] = make_float2(d, 0.f);
+            const float inv = 1.0f / d;
+            for (int r = j + 1; r < K; ++r) {
+                float2 v = G[r * KT + j];
+                for (int q = 0; q < j; ++q) {   // v -= L_rq conj(L_jq)
+                    const float2 a = G[r * KT + q], b = G[j * KT + q];
+                    v.x -= a.x * b.x + a.y * b.y;
+                    v.y -= a.y * b.x - a.x * b.y;
+                }
+                G[r * KT + j] = make_float2(v.x * inv, v.y * inv);
+            }
+        }
+    }
+    __syncthreads();
+    const int t = i;
+    if (t < T && n0 + l < N) {
+        float2 z[dMaxK];
+        // L z = b (every index compile-time after unrolling: z stays in registers)
+#pragma unroll
+        for (int r = 0; r < dMaxK; ++r) {
+            z[r] = make_float2(0.f, 0.f);
+            if (r < K) {
+                float2 v = G[r * KT + K + t];
+#pragma unroll
+                for (int q = 0; q < r; ++q) {
+                    const float2 a = G[r * KT + q];
+                    v.x -= a.x * z[q].x - a.y * z[q].y;
+                    v.y -= a.x * z[q].y + a.y * z[q].x;
+                }
+                const float inv = 1.0f / G[r * KT + r].x;
+                z[r] = make_float2(v.x * inv, v.y * inv);
+            }
+        }
+        // L^H x = z
+#pragma unroll
+        for (int r = dMaxK - 1; r >= 0; --r) {
+            if (r < K) {
+                float2 v = z[r];
+#pragma unroll
+                for (int q = r + 1; q < dMaxK; ++q) {   // v -= conj(L_qr) x_q
+                    if (q < K) {
+                        const float2 a = G[q * KT + r];
+                        v.x -= a.x * z[q].x + a.y * z[q].y;
+                        v.y -= a.x * z[q].y - a.y * z[q].x;
+                    }
+                }
+                const float inv = 1.0f / G[r * KT + r].x;
+                z[r] = make_float2(v.x * inv, v.y * inv);
+            }
+        }
+        float2* xs = x + (s * T + t) * (long long)K * N + n0 + l;
+#pragma unroll
+        for (int k = 0; k < dMaxK; ++k)
+            if (k < K) xs[(long long)k * N] = z[k];
+    }
+}
+
+}  // namespace lmmse
+
+extern "C" int lmmse_mmse_detect(int slots, int M, int K, int T, int N, const void* h_hat,
+                                 const void* y_data, double sigma2, void* x_out, void* stream) {
+    if (slots < 0 || M < 1 || K < 1 || T < 1 || N < 1) return LMMSE_ERR_INVALID_ARG;
+    if (!(sigma2 > 0.0) || !(sigma2 < 1e30)) return LMMSE_ERR_INVALID_ARG;
+    if (K > lmmse::dMaxK || T > lmmse::dMaxT) return LMMSE_ERR_UNSUPPORTED;
+    if (slots == 0) return LMMSE_OK;
+    if (!h_hat || !y_data || !x_out) return LMMSE_ERR_INVALID_ARG;
+    const int nblk = (N + lmmse::dNB - 1) / lmmse::dNB;
+    const size_t shm = std::max((size_t)lmmse::dMC * (K + T) * lmmse::dNB,
+                                (size_t)lmmse::dNB * K * (K + T)) * sizeof(float2);
+    hipLaunchKernelGGL(lmmse::mmse_detect_kernel, dim3((unsigned)((long long)slots * nblk)), dim3(256),
+                       shm, (hipStream_t)stream, (const float2*)h_hat, (const float2*)y_data,
+                       (float2*)x_out, M, K, T, N, (float)sigma2, nblk);
+    return hipGetLastError() == hipSuccess ? LMMSE_OK : LMMSE_ERR_HIP;
+}
