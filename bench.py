@@ -46,6 +46,8 @@ def parse():
                     help="only time the fwd+bwd training step (16 slots) and print its line")
     ap.add_argument("--large-only", action="store_true",
                     help="only run the large sample-covariance workload (M=256, K=24, N=3300)")
+    ap.add_argument("--detect-only", action="store_true",
+                    help="only run the MMSE detection line")
     ap.add_argument("--comb-only", action="store_true",
                     help="only run the comb-pilot 3W / 12W lines")
     ap.add_argument("--copy-probe", action="store_true",
@@ -256,6 +258,50 @@ def comb_lines(dev, stream, steps=20, warmup=3):
     return res
 
 
+def detect_line(dev, stream, steps=20, warmup=3):
+    """MMSE detection (eq. 22) downstream of the estimator on the paper-sized
+    system: 64 slots, 128 antennas, 12 users, N=1200, 12 QPSK data symbols
+    per slot, SNR 10 dB.  HBM-bound: H (M K), Y (M T) read and X (T K)
+    written per subcarrier, 8 B each."""
+    import numpy as np
+    import torch
+
+    import oracle as O
+    from paper_1802_05427_amd import mmse_detect
+    from synth import make_pilots
+    from synth.torch_slots import draw_batch
+    M, K, N, Nf, T, S = 128, 12, 1200, 2048, 12, 64
+    sigma2 = 0.1
+    pil = torch.from_numpy(make_pilots(K, N)).to(dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(180205427 + 8)
+    Hs = []
+    for s0 in range(0, S, 16):
+        Hs.append(draw_batch(g, 16, M, K, N, Nf, 72, 4.0, 4.0, 0.0, pil)[1])
+    H = torch.cat(Hs).contiguous()
+    del Hs
+    bits = torch.randint(0, 2, (S, T, K, N, 2), generator=g, device=dev).float()
+    X = torch.complex(1 - 2 * bits[..., 0], 1 - 2 * bits[..., 1]) / np.sqrt(2.0)
+    Y = torch.zeros((S, M, T, N), dtype=torch.complex64, device=dev)
+    for k in range(K):   # Y[s, m, t, n] = sum_k H[s, m, k, n] X[s, t, k, n]
+        Y += H[:, :, k, None, :] * X[:, None, :, k, :]
+    Y += torch.complex(torch.randn(Y.shape, generator=g, device=dev),
+                       torch.randn(Y.shape, generator=g, device=dev)) * float(np.sqrt(sigma2 / 2))
+    out = torch.empty((S, T, K, N), dtype=torch.complex64, device=dev)
+    t_ms = time_calls(lambda: mmse_detect(H, Y, sigma2, out=out), steps, warmup, stream)
+    ref = O.mmse_detect(H[:1].cpu().numpy().astype(np.complex128), Y[:1].cpu().numpy().astype(np.complex128),
+                        sigma2)
+    got = out[:1].cpu().numpy()
+    byts = S * N * 8.0 * (M * K + M * T + T * K)
+    gbs = byts / (t_ms * 1e-3) / 1e9
+    ser = float(np.mean(np.abs(O.qpsk_decide(got) - X[:1].cpu().numpy()) > 1e-3))
+    return {"workload": f"MMSE detection, {S} slots, M={M}, K={K}, N={N}, {T} data symbols, SNR 10 dB",
+            "ms": round(t_ms, 4), "subcarriers_per_s": round(S * N / (t_ms * 1e-3), 1),
+            "hbm_GBs": round(gbs, 1), "hbm_frac": round(gbs / PEAK["hbm_GBs"], 4),
+            "rel_err_vs_oracle": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+            "symbol_error_rate": ser}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -280,6 +326,10 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": 4 * n, "launches": 5}), flush=True)
+        return
+    if args.detect_only:
+        print(json.dumps({"metric": "MMSE detection", "detail": detect_line(dev, torch.cuda.current_stream())}),
+              flush=True)
         return
     if args.comb_only:
         r = comb_lines(dev, torch.cuda.current_stream())
@@ -423,6 +473,7 @@ def main():
         torch.cuda.empty_cache()
         extras["large_sample"] = large_sample(dev, stream)
         extras["comb"] = comb_lines(dev, stream)
+        extras["detect"] = detect_line(dev, stream)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -9,10 +9,10 @@
 // One workgroup per (slot, 16 consecutive subcarriers).  Antennas are
 // streamed through LDS 8 at a time (each (antenna, user) row of 16
 // subcarriers is one 128-byte load); thread (l, i) accumulates row i of
-// [H^H H | H^H Y] for subcarrier l in registers.  The rows go to LDS (over
-// the staging area, after the last antenna), one
-// thread per subcarrier factors A in place, and one thread per (subcarrier,
-// data symbol) solves and writes its K symbols.
+// [H^H H | H^H Y] for subcarrier l in registers.  The rows go to LDS (over the staging area, after the last
+// antenna), A is factored in place column by column (each row by its own
+// thread), and one thread per (subcarrier, data symbol) solves and writes
+// its K symbols.
 #include <algorithm>
 
 #include "internal.h"
@@ -84,29 +84,30 @@ __global__ __launch_bounds__(256) void mmse_detect_kernel(const float2* h, const
     }
     __syncthreads();
     float2* G = Gs + l * K * KT;   // this subcarrier's [A | B]
-    if (i == 0) {
-        // A = L L^H in place (lower triangle), L_jj real
-        for (int j = 0; j < K; ++j) {
+    // A = L L^H in place, column by column: the diagonal entry by its row's
+    // thread, then every row below it by its own thread (L_jj real)
+    for (int j = 0; j < K; ++j) {
+        if (i == j) {
             float d = G[j * KT + j].x;
             for (int q = 0; q < j; ++q) {
                 const float2 v = G[j * KT + q];
                 d -= v.x * v.x + v.y * v.y;
             }
-            d = d > 0.f ? sqrtf(d) : __builtin_nanf("");
-            G[j * KT + j] = make_float2(d, 0.f);
-            const float inv = 1.0f / d;
-            for (int r = j + 1; r < K; ++r) {
-                float2 v = G[r * KT + j];
-                for (int q = 0; q < j; ++q) {   // v -= L_rq conj(L_jq)
-                    const float2 a = G[r * KT + q], b = G[j * KT + q];
-                    v.x -= a.x * b.x + a.y * b.y;
-                    v.y -= a.y * b.x - a.x * b.y;
-                }
-                G[r * KT + j] = make_float2(v.x * inv, v.y * inv);
-            }
+            G[j * KT + j] = make_float2(d > 0.f ? sqrtf(d) : __builtin_nanf(""), 0.f);
         }
+        __syncthreads();
+        if (i > j && i < K) {
+            float2 v = G[i * KT + j];
+            for (int q = 0; q < j; ++q) {   // v -= L_iq conj(L_jq)
+                const float2 a = G[i * KT + q], b = G[j * KT + q];
+                v.x -= a.x * b.x + a.y * b.y;
+                v.y -= a.y * b.x - a.x * b.y;
+            }
+            const float inv = 1.0f / G[j * KT + j].x;
+            G[i * KT + j] = make_float2(v.x * inv, v.y * inv);
+        }
+        __syncthreads();
     }
-    __syncthreads();
     const int t = i;
     if (t < T && n0 + l < N) {
         float2 z[dMaxK];
