@@ -37,6 +37,7 @@ from .comb import (  # noqa: F401
     comb_groups,
     comb_ls,
     comb_ls_hold,
+    comb_ls_linear,
     zero_order_hold,
 )
 from .detect import mmse_detect, qpsk_decide  # noqa: F401

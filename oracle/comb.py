@@ -95,3 +95,45 @@ def comb_ls_hold(y, pilots, S: int, ues) -> np.ndarray:
         est = np.where(have[None, None, :], ls, 0)
         out[:, :, ui, :] = zero_order_hold(est, have)
     return out
+
+
+def comb_ls_linear(y, pilots, S: int, ues, fold: int | None = None) -> np.ndarray:
+    """Interpolated-LS baselines (Sec. II and IV-C comparison lines).
+
+    fold=None: each subcarrier linearly interpolates the LS values of the two
+    UE tones around it (the nearest tone's value outside the first..last
+    tone).  fold=3 ("3-fold interpolated LS"): the same linear interpolation
+    evaluated only at the 3W output positions tone + j S/3, then the
+    zero-order hold of the 3W estimator fills the rest."""
+    ls = comb_ls(y, pilots)
+    nsl, M, N = ls.shape
+    out = np.zeros((nsl, M, len(ues), N), dtype=C128)
+    for ui, ue in enumerate(ues):
+        tones = np.arange(ue, N, S)
+        vals = ls[:, :, tones]
+        def lin(p):
+            p = np.asarray(p, dtype=np.float64)
+            res = np.empty((nsl, M) + p.shape, dtype=C128)
+            for idx, q in np.ndenumerate(p):
+                if q <= tones[0]:
+                    res[(slice(None), slice(None)) + idx] = vals[:, :, 0]
+                elif q >= tones[-1]:
+                    res[(slice(None), slice(None)) + idx] = vals[:, :, -1]
+                else:
+                    i = int((q - ue) // S)
+                    f = (q - tones[i]) / S
+                    res[(slice(None), slice(None)) + idx] = (1 - f) * vals[:, :, i] + f * vals[:, :, i + 1]
+            return res
+        if fold is None:
+            out[:, :, ui, :] = lin(np.arange(N))
+        else:
+            have = np.zeros(N, dtype=bool)
+            est = np.zeros((nsl, M, N), dtype=C128)
+            for t in tones:
+                for j in range(fold):
+                    q = t + j * (S // fold)
+                    if q < N:
+                        est[:, :, q] = lin(np.array([q]))[:, :, 0]
+                        have[q] = True
+            out[:, :, ui, :] = zero_order_hold(est, have)
+    return out

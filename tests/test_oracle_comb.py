@@ -100,3 +100,29 @@ def test_relative_accuracy_matches_fig7a_text():
     assert 5.5 < ls - w12 < 8.5
     assert 2.5 < ls - w3 < 5.0
     assert w12 < w3 < ls
+
+
+def test_linear_interpolation_is_exact_on_a_linear_channel():
+    """LS values that are linear in the subcarrier index are reproduced
+    exactly between the first and last tone (and held outside)."""
+    S, N = 12, 120
+    n = np.arange(N)
+    Hlin = (0.3 + 0.01j) + (0.002 - 0.003j) * n
+    pil = np.exp(1j * np.linspace(0, 5, N))
+    y = (Hlin * pil)[None, None, :]
+    for ue in (0, 5):
+        out = O.comb_ls_linear(y, pil, S, [ue])[0, 0, 0]
+        first, last = ue, ue + S * (N // S - 1)
+        assert np.allclose(out[first:last + 1], Hlin[first:last + 1], atol=1e-12)
+        assert np.allclose(out[:first], Hlin[first]) and np.allclose(out[last:], Hlin[last])
+
+
+def test_three_fold_interpolation_uses_the_3w_positions():
+    cb = make_comb_batch(M=2, K=3, N=240, N_fft=256, powers_db=[0, -3, -6], snr_db=10.0, slots=1)
+    lin = O.comb_ls_linear(cb.y, cb.pilots, 12, range(3))
+    three = O.comb_ls_linear(cb.y, cb.pilots, 12, range(3), fold=3)
+    for k in range(3):
+        pos = [t + 4 * j for t in range(k, 240, 12) for j in range(3) if t + 4 * j < 240]
+        assert np.allclose(three[:, :, k, pos], lin[:, :, k, pos])
+        # between outputs the value is held
+        assert np.allclose(three[:, :, k, k + 1], three[:, :, k, k])
