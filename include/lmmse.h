@@ -275,10 +275,18 @@ int lmmse_sync_status(lmmse_plan_t plan, void *stream, int *info);
  *   LMMSE_COMB_12W: the S subcarriers S b .. S b + S - 1.
  * W_b depends only on b - wst_b (and, for 12W, on k): each UE has `win`
  * filter classes, designed in FP64 on the device when the plan is made and
- * applied in FP32. */
+ * applied in FP32.  The LS baselines (LS_HOLD, LS_LINEAR, LS_LINEAR3) use
+ * the same LS values and no filters (get_filters returns zeros). */
 typedef enum lmmse_comb_kind {
     LMMSE_COMB_3W = 0,
-    LMMSE_COMB_12W = 1
+    LMMSE_COMB_12W = 1,
+    /* interpolated-LS baselines (no filters): */
+    LMMSE_COMB_LS_HOLD = 2,     /* each subcarrier takes the LS of the latest
+                                   tone at or below it (the first below it) */
+    LMMSE_COMB_LS_LINEAR = 3,   /* linear between the two tones around it; the
+                                   nearest tone outside the first..last tone */
+    LMMSE_COMB_LS_LINEAR3 = 4   /* "3-fold": linear at the 3W output positions
+                                   tone + j S/3, held as in 3W */
 } lmmse_comb_kind;
 
 typedef struct lmmse_comb_desc {
@@ -289,7 +297,8 @@ typedef struct lmmse_comb_desc {
     int N;           /* used subcarriers; N / S >= win and <= 4096          */
     int N_fft;       /* FFT size (>= N)                                      */
     int kind;        /* lmmse_comb_kind                                      */
-    int rsource;     /* LMMSE_R_UNIFORM or LMMSE_R_EXPONENTIAL               */
+    int rsource;     /* LMMSE_R_UNIFORM or LMMSE_R_EXPONENTIAL (the filter
+                        kinds; checked for every kind)                       */
     int taps;        /* EXPONENTIAL: integer taps (1..N_fft)                 */
     double tau_rms;  /* EXPONENTIAL: profile decay (> 0)                     */
     double L;        /* UNIFORM: assumed channel length in samples (> 0)     */

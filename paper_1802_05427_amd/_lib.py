@@ -35,7 +35,7 @@ class PlanDesc(ctypes.Structure):
 P_desc = ctypes.POINTER(PlanDesc)
 
 # lmmse_comb_kind
-COMB_3W, COMB_12W = range(2)
+COMB_3W, COMB_12W, COMB_LS_HOLD, COMB_LS_LINEAR, COMB_LS_LINEAR3 = range(5)
 
 
 class CombDesc(ctypes.Structure):

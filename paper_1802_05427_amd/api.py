@@ -227,7 +227,8 @@ class Plan:
         return st, info.value
 
 
-_COMB_KIND = {"3w": _lib.COMB_3W, "12w": _lib.COMB_12W}
+_COMB_KIND = {"3w": _lib.COMB_3W, "12w": _lib.COMB_12W, "ls_hold": _lib.COMB_LS_HOLD,
+              "ls_linear": _lib.COMB_LS_LINEAR, "ls_linear3": _lib.COMB_LS_LINEAR3}
 
 
 def make_comb_desc(M, K, N, N_fft, comb=12, kind="12w", rsource="uniform", L=8.0, tau_rms=1.0,
@@ -257,8 +258,8 @@ class CombPlan:
         self._h = h
         self.device = torch.device("cuda", torch.cuda.current_device())
         d = self.desc
-        self.win = 3 if d.kind == _lib.COMB_3W else 12
-        self.nout = 3 if d.kind == _lib.COMB_3W else d.comb
+        self.win = {_lib.COMB_3W: 3, _lib.COMB_12W: 12}.get(d.kind, 1)
+        self.nout = {_lib.COMB_3W: 3, _lib.COMB_12W: d.comb}.get(d.kind, 1)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

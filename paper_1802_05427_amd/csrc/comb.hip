@@ -14,6 +14,9 @@
 // window, cls = b - wst_b (and, for 12W, on k), so each UE has `win`
 // filter classes.  3W fills every subcarrier without an estimate from the
 // latest estimate below it (the first estimate below the first one).
+// The interpolated-LS baselines use the same LS staging: the held LS, the
+// linear interpolation between a UE's tones, and the 3-fold form (linear at
+// the 3W output positions, then held).
 #include <algorithm>
 #include <cmath>
 #include <new>
@@ -158,6 +161,9 @@ __global__ __launch_bounds__(256) void comb_apply_kernel(lmmse_comb_desc d, int 
             if (d.kind == LMMSE_COMB_12W) {
                 b = p / S;
                 j = p - b * S;
+            } else if (d.kind == LMMSE_COMB_LS_HOLD || d.kind == LMMSE_COMB_LS_LINEAR) {
+                b = 0;
+                j = 0;
             } else if (p < k) {
                 b = 0;
                 j = 0;
@@ -165,13 +171,31 @@ __global__ __launch_bounds__(256) void comb_apply_kernel(lmmse_comb_desc d, int 
                 b = min((p - k) / S, ntones - 1);
                 j = min((p - k - S * b) / (S / 3), 2);
             }
-            const int wst = min(max(b - (win - 1) / 2, 0), ntones - win);
-            const float2* W = wc + ((b - wst) * nout + j) * win;
             float2 acc = make_float2(0.f, 0.f);
-            for (int i = 0; i < win; ++i) {
-                const float2 w = W[i], x = ls[wst + i];
-                acc.x += w.x * x.x - w.y * x.y;
-                acc.y += w.x * x.y + w.y * x.x;
+            if (d.kind == LMMSE_COMB_3W || d.kind == LMMSE_COMB_12W) {
+                const int wst = min(max(b - (win - 1) / 2, 0), ntones - win);
+                const float2* W = wc + ((b - wst) * nout + j) * win;
+                for (int i = 0; i < win; ++i) {
+                    const float2 w = W[i], x = ls[wst + i];
+                    acc.x += w.x * x.x - w.y * x.y;
+                    acc.y += w.x * x.y + w.y * x.x;
+                }
+            } else if (d.kind == LMMSE_COMB_LS_HOLD) {
+                acc = ls[p < k ? 0 : min((p - k) / S, ntones - 1)];
+            } else {
+                // linear interpolation between the UE's tones, at p itself
+                // or (3-fold) at the 3W output position that p holds
+                const int q = d.kind == LMMSE_COMB_LS_LINEAR ? p : k + S * b + j * (S / 3);
+                if (q <= k) {
+                    acc = ls[0];
+                } else if (q >= k + S * (ntones - 1)) {
+                    acc = ls[ntones - 1];
+                } else {
+                    const int i0 = (q - k) / S;
+                    const float f = (float)(q - k - S * i0) / (float)S;
+                    acc = make_float2((1.f - f) * ls[i0].x + f * ls[i0 + 1].x,
+                                      (1.f - f) * ls[i0].y + f * ls[i0 + 1].y);
+                }
             }
             oc[p] = acc;
         }
@@ -192,7 +216,7 @@ int comb_validate(const lmmse_comb_desc* d) {
     if (!d) return LMMSE_ERR_INVALID_ARG;
     if (d->M < 1 || d->K < 1 || d->comb < 1 || d->N < 1 || d->N_fft < 1 || d->max_slots < 1)
         return LMMSE_ERR_INVALID_ARG;
-    if (d->kind != LMMSE_COMB_3W && d->kind != LMMSE_COMB_12W) return LMMSE_ERR_INVALID_ARG;
+    if (d->kind < LMMSE_COMB_3W || d->kind > LMMSE_COMB_LS_LINEAR3) return LMMSE_ERR_INVALID_ARG;
     if (d->rsource != LMMSE_R_UNIFORM && d->rsource != LMMSE_R_EXPONENTIAL) return LMMSE_ERR_INVALID_ARG;
     if (!(d->sigma2 > 0.0) || !std::isfinite(d->sigma2)) return LMMSE_ERR_INVALID_ARG;
     if (d->rsource == LMMSE_R_UNIFORM && (!(d->L > 0.0) || !std::isfinite(d->L))) return LMMSE_ERR_INVALID_ARG;
@@ -200,9 +224,10 @@ int comb_validate(const lmmse_comb_desc* d) {
         (!(d->tau_rms > 0.0) || !std::isfinite(d->tau_rms) || d->taps < 1 || d->taps > d->N_fft))
         return LMMSE_ERR_INVALID_ARG;
     if (d->N > d->N_fft || d->K > d->comb || d->N % d->comb != 0) return LMMSE_ERR_UNSUPPORTED;
-    if (d->kind == LMMSE_COMB_3W && d->comb % 3 != 0) return LMMSE_ERR_UNSUPPORTED;
+    const bool three = d->kind == LMMSE_COMB_3W || d->kind == LMMSE_COMB_LS_LINEAR3;
+    if (three && d->comb % 3 != 0) return LMMSE_ERR_UNSUPPORTED;
     if (d->kind == LMMSE_COMB_12W && d->comb > lmmse::kCombOutMax) return LMMSE_ERR_UNSUPPORTED;
-    const int win = d->kind == LMMSE_COMB_3W ? 3 : 12;
+    const int win = d->kind == LMMSE_COMB_12W ? 12 : (d->kind == LMMSE_COMB_3W ? 3 : 2);
     if (d->N / d->comb < win) return LMMSE_ERR_UNSUPPORTED;
     if (d->N / d->comb > 4096) return LMMSE_ERR_UNSUPPORTED;   // LS staging fits in LDS
     return LMMSE_OK;
@@ -224,8 +249,9 @@ int lmmse_comb_create(const lmmse_comb_desc* desc, lmmse_comb_t* out) {
     CombPlan& p = c->p;
     p.d = *desc;
     p.ntones = desc->N / desc->comb;
-    p.win = desc->kind == LMMSE_COMB_3W ? 3 : 12;
-    p.nout = desc->kind == LMMSE_COMB_3W ? 3 : desc->comb;
+    const bool filt = desc->kind == LMMSE_COMB_3W || desc->kind == LMMSE_COMB_12W;
+    p.win = desc->kind == LMMSE_COMB_12W ? 12 : (desc->kind == LMMSE_COMB_3W ? 3 : 1);
+    p.nout = desc->kind == LMMSE_COMB_12W ? desc->comb : (desc->kind == LMMSE_COMB_3W ? 3 : 1);
     const size_t nw = (size_t)desc->K * p.win * p.nout * p.win;
     if (hipMalloc(&p.w64, nw * sizeof(double2)) != hipSuccess ||
         hipMalloc(&p.w32, nw * sizeof(float2)) != hipSuccess ||
@@ -233,8 +259,14 @@ int lmmse_comb_create(const lmmse_comb_desc* desc, lmmse_comb_t* out) {
         lmmse_comb_destroy(c);
         return LMMSE_ERR_HIP;
     }
-    hipLaunchKernelGGL(lmmse::comb_design_kernel, dim3(p.win, desc->K), dim3(256), 0, 0, p.d, p.win,
-                       p.nout, p.w64, p.w32, p.status);
+    if (filt)
+        hipLaunchKernelGGL(lmmse::comb_design_kernel, dim3(p.win, desc->K), dim3(256), 0, 0, p.d,
+                           p.win, p.nout, p.w64, p.w32, p.status);
+    else if (hipMemset(p.w64, 0, nw * sizeof(double2)) != hipSuccess ||
+             hipMemset(p.w32, 0, nw * sizeof(float2)) != hipSuccess) {
+        lmmse_comb_destroy(c);
+        return LMMSE_ERR_HIP;
+    }
     int st[2] = {0, 0};
     if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
         hipMemcpy(st, p.status, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess) {

@@ -80,3 +80,21 @@ def test_comb_filters_and_estimate_match_oracle(dev, c, kind):
     print(f"  discrepancy {disc:.1f} dB, NMSE gap {gap:.2e} dB", flush=True)
     assert disc < -120.0
     assert gap < 1e-4
+
+
+@pytest.mark.parametrize("kind", ["ls_hold", "ls_linear", "ls_linear3"])
+@pytest.mark.parametrize("c", [CASES[0], CASES[1], CASES[2], CASES[5]])
+def test_interpolated_ls_baselines_match_oracle(dev, c, kind):
+    print(f"comb {kind} {c}", flush=True)
+    S = c.get("comb", 12)
+    cb = make_comb_batch(M=c["M"], K=c["K"], N=c["N"], N_fft=c["N_fft"], powers_db=PROFILE,
+                         snr_db=c["snr"], slots=c["slots"], comb=S)
+    with _plan(c, kind, cb.sigma2) as pl:
+        out = pl.estimate(_t(cb.y, dev), _t(cb.pilots, dev)).cpu().numpy()
+    if kind == "ls_hold":
+        ref = O.comb_ls_hold(cb.y, cb.pilots, S, range(c["K"]))
+    else:
+        ref = O.comb_ls_linear(cb.y, cb.pilots, S, range(c["K"]), fold=3 if kind == "ls_linear3" else None)
+    disc = O.discrepancy_db(out, ref)
+    print(f"  discrepancy {disc:.1f} dB", flush=True)
+    assert disc < -120.0
