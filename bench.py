@@ -251,8 +251,16 @@ def comb_lines(dev, stream, steps=20, warmup=3):
                      "nmse_db": round(O.nmse_db(o1, cb.H[:1]), 3),
                      "nmse_gap_db": abs(O.nmse_db(o1, cb.H[:1]) - O.nmse_db(ref, cb.H[:1])),
                      "discrepancy_db": round(O.discrepancy_db(o1, ref), 1)}
-    ls = O.nmse_db(O.comb_ls_hold(cb.y[:1], cb.pilots, S, range(K)), cb.H[:1])
-    res["ls_hold_nmse_db"] = round(ls, 3)
+    for kind, ref_fn in (("ls_hold", lambda: O.comb_ls_hold(cb.y[:1], cb.pilots, S, range(K))),
+                         ("ls_linear3", lambda: O.comb_ls_linear(cb.y[:1], cb.pilots, S, range(K), fold=3))):
+        with CombPlan(M=M, K=K, N=N, N_fft=Nf, comb=S, kind=kind, rsource="uniform", L=8.0,
+                      sigma2=cb.sigma2, max_slots=slots) as pl:
+            out = torch.empty((slots, M, K, N), dtype=torch.complex64, device=dev)
+            t_ms = time_calls(lambda: pl.estimate(y, pil, out=out), steps, warmup, stream)
+            o1 = out[:1].cpu().numpy()
+        ref = ref_fn()
+        res[kind] = {"ms": round(t_ms, 4), "nmse_db": round(O.nmse_db(o1, cb.H[:1]), 3),
+                     "discrepancy_db": round(O.discrepancy_db(o1, ref), 1)}
     res["workload"] = (f"comb pilots (spacing {S}), M={M}, {K} active UEs, N={N} of {Nf}, {slots} slots, "
                        "6-tap profile, SNR 20 dB, eq. 16 design with L=8")
     return res
