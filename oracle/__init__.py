@@ -38,6 +38,9 @@ from .comb import (  # noqa: F401
     comb_ls,
     comb_ls_hold,
     comb_ls_linear,
+    comb_ls_quadratic,
+    comb_ls_spline,
+    natural_spline_second_derivatives,
     zero_order_hold,
 )
 from .detect import mmse_detect, qpsk_decide  # noqa: F401

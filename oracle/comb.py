@@ -137,3 +137,79 @@ def comb_ls_linear(y, pilots, S: int, ues, fold: int | None = None) -> np.ndarra
                         have[q] = True
             out[:, :, ui, :] = zero_order_hold(est, have)
     return out
+
+
+def comb_ls_quadratic(y, pilots, S: int, ues) -> np.ndarray:
+    """Second-order polynomial interpolated LS (Sec. II, the interpolated LS
+    estimators).  Reading: a subcarrier between a UE's tones i and i+1 takes
+    the quadratic through the LS values of tones i-1, i, i+1 (tones 0, 1, 2
+    in the first interval); outside the first..last tone the nearest tone's
+    value is held, as for the linear form."""
+    ls = comb_ls(y, pilots)
+    nsl, M, N = ls.shape
+    out = np.zeros((nsl, M, len(ues), N), dtype=C128)
+    for ui, ue in enumerate(ues):
+        tones = np.arange(ue, N, S)
+        vals = ls[:, :, tones]
+        nt = len(tones)
+        for p in range(N):
+            if p <= tones[0]:
+                out[:, :, ui, p] = vals[:, :, 0]
+            elif p >= tones[-1]:
+                out[:, :, ui, p] = vals[:, :, -1]
+            else:
+                i = (p - ue) // S
+                m = min(max(i - 1, 0), nt - 3)
+                x = (p - ue) / S                 # position in tone units
+                nodes = [m, m + 1, m + 2]
+                for a in nodes:                  # Lagrange basis through the three tones
+                    wa = 1.0
+                    for b in nodes:
+                        if b != a:
+                            wa *= (x - b) / (a - b)
+                    out[:, :, ui, p] += wa * vals[:, :, a]
+    return out
+
+
+def natural_spline_second_derivatives(v: np.ndarray) -> np.ndarray:
+    """Second derivatives (per unit knot spacing) of the natural cubic spline
+    through equally spaced values v[..., 0..n-1]: zero at both ends, and on
+    the interior knots the continuity of the first derivative,
+    M[i-1] + 4 M[i] + M[i+1] = 6 (v[i-1] - 2 v[i] + v[i+1])."""
+    n = v.shape[-1]
+    Mdd = np.zeros(v.shape, dtype=C128)
+    if n <= 2:
+        return Mdd
+    T = 4.0 * np.eye(n - 2) + np.eye(n - 2, k=1) + np.eye(n - 2, k=-1)
+    rhs = 6.0 * (v[..., :-2] - 2.0 * v[..., 1:-1] + v[..., 2:])
+    Mdd[..., 1:-1] = np.linalg.solve(T, rhs.reshape(-1, n - 2).T).T.reshape(rhs.shape)
+    return Mdd
+
+
+def comb_ls_spline(y, pilots, S: int, ues) -> np.ndarray:
+    """Cubic-spline interpolated LS (Sec. II, the interpolated LS estimators).
+    Reading: the natural cubic spline (zero second derivative at the first
+    and last tone) through the LS values of a UE's tones, real and imaginary
+    parts alike; outside the first..last tone the nearest tone's value is
+    held.  On the interval between tones i and i+1, with u the fraction of
+    the way, the spline is (1-u) v_i + u v_{i+1} + ((1-u)^3 - (1-u)) M_i / 6
+    + (u^3 - u) M_{i+1} / 6."""
+    ls = comb_ls(y, pilots)
+    nsl, M, N = ls.shape
+    out = np.zeros((nsl, M, len(ues), N), dtype=C128)
+    for ui, ue in enumerate(ues):
+        tones = np.arange(ue, N, S)
+        vals = ls[:, :, tones]
+        Mdd = natural_spline_second_derivatives(vals)
+        for p in range(N):
+            if p <= tones[0]:
+                out[:, :, ui, p] = vals[:, :, 0]
+            elif p >= tones[-1]:
+                out[:, :, ui, p] = vals[:, :, -1]
+            else:
+                i = (p - ue) // S
+                u = (p - tones[i]) / S
+                out[:, :, ui, p] = ((1 - u) * vals[:, :, i] + u * vals[:, :, i + 1]
+                                    + ((1 - u) ** 3 - (1 - u)) * Mdd[:, :, i] / 6
+                                    + (u ** 3 - u) * Mdd[:, :, i + 1] / 6)
+    return out

@@ -130,3 +130,99 @@ def test_three_fold_interpolation_uses_the_3w_positions():
         assert np.allclose(three[:, :, k, pos], lin[:, :, k, pos])
         # between outputs the value is held
         assert np.allclose(three[:, :, k, k + 1], three[:, :, k, k])
+
+
+def test_robustness_trends_match_fig7bcd_text():
+    """Fig. 7(b-d), 12W on a Table III-like system at 25 dB: with a true
+    7-tap equal-power channel the error is lowest near the assumed length 7,
+    far worse at L = 1 and only mildly worse at L = 15; a design SNR at or
+    above the true one is about as good as the matched one, a 0 dB design is
+    far worse; a 2-sample timing error moves the error only slightly."""
+    rd = lambda L: (lambda d: O.r_uniform(d, float(L), 2048))
+    est = lambda cb, L, s2, y=None: O.comb_estimate(cb.y if y is None else y, cb.pilots, s2, 12,
+                                                    range(4), "12w", rd(L))
+    cb = make_comb_batch(M=16, K=4, N=1200, N_fft=2048, powers_db=[0] * 7, snr_db=25.0, slots=2)
+    e = {L: O.nmse_db(est(cb, L, cb.sigma2), cb.H) for L in (1, 4, 7, 10, 15)}
+    assert min(e, key=e.get) == 7
+    assert e[1] - e[7] > 6.0 and e[15] - e[7] < 2.0
+    cb = make_comb_batch(M=16, K=4, N=1200, N_fft=2048, powers_db=[-2, -8, -10, -12, -15, -18],
+                         snr_db=25.0, slots=2)
+    s = {sf: O.nmse_db(est(cb, 8, 10 ** (-sf / 10)), cb.H) for sf in (0, 25, 40)}
+    assert abs(s[40] - s[25]) < 1.0 and s[0] - s[25] > 6.0
+    ramp = np.exp(-2j * np.pi * 2 * np.arange(1200) / 2048)
+    e2 = O.nmse_db(est(cb, 8, cb.sigma2, y=cb.y * ramp), cb.H * ramp)
+    assert abs(e2 - O.nmse_db(est(cb, 8, cb.sigma2), cb.H)) < 2.0
+
+
+def _single_ue_input(vals_on_all, N):
+    pil = np.exp(1j * np.linspace(0, 7, N))
+    return (vals_on_all * pil)[None, None, :], pil
+
+
+def test_quadratic_interpolation_reproduces_a_quadratic():
+    S, N = 12, 144
+    n = np.arange(N, dtype=np.float64)
+    Hq = (0.2 - 0.1j) + (0.01 + 0.02j) * n - (3e-4 - 1e-4j) * n * n
+    y, pil = _single_ue_input(Hq, N)
+    for ue in (0, 7):
+        out = O.comb_ls_quadratic(y, pil, S, [ue])[0, 0, 0]
+        first, last = ue, ue + S * (N // S - 1)
+        assert np.allclose(out[first:last + 1], Hq[first:last + 1], atol=1e-12)
+        assert np.allclose(out[:first], Hq[first]) and np.allclose(out[last:], Hq[last])
+
+
+def test_quadratic_interpolation_midpoint_weights():
+    """Halfway between tones i and i+1 the quadratic through tones i-1, i,
+    i+1 weighs them -1/8, 3/4, 3/8 (the second-order interpolation of the
+    paper's reference [10] at alpha = 1/2)."""
+    S, N = 12, 120
+    v = np.random.default_rng(3).standard_normal(N) + 1j * np.random.default_rng(4).standard_normal(N)
+    y, pil = _single_ue_input(v, N)
+    out = O.comb_ls_quadratic(y, pil, S, [0])[0, 0, 0]
+    for i in (1, 4, 8):
+        assert abs(out[S * i + S // 2] - (-v[S * (i - 1)] / 8 + 0.75 * v[S * i] + 3 * v[S * (i + 1)] / 8)) < 1e-12
+    # first interval: tones 0, 1, 2 -> weights 3/8, 3/4, -1/8
+    assert abs(out[S // 2] - (3 * v[0] / 8 + 0.75 * v[S] - v[2 * S] / 8)) < 1e-12
+
+
+def test_quadratic_interpolation_is_local():
+    """Changing tone j's LS value moves only the intervals whose three tones
+    include it: those starting at tones j-1, j and j+1."""
+    S, N, ue, j = 12, 240, 3, 9
+    rng = np.random.default_rng(7)
+    v = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    y, pil = _single_ue_input(v, N)
+    a = O.comb_ls_quadratic(y, pil, S, [ue])[0, 0, 0]
+    y2 = y.copy()
+    y2[0, 0, ue + S * j] += 1.0
+    b = O.comb_ls_quadratic(y2, pil, S, [ue])[0, 0, 0]
+    changed = np.nonzero(np.abs(a - b) > 1e-12)[0]
+    assert changed.min() > ue + S * (j - 1) and changed.max() < ue + S * (j + 2)
+    for i in (j - 1, j, j + 1):
+        assert np.any((changed > ue + S * i) & (changed < ue + S * (i + 1)))
+
+
+def test_natural_spline_matches_library_spline():
+    from scipy.interpolate import CubicSpline
+    S, N = 12, 1200
+    rng = np.random.default_rng(11)
+    v = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    y, pil = _single_ue_input(v, N)
+    for ue in (0, 11):
+        out = O.comb_ls_spline(y, pil, S, [ue])[0, 0, 0]
+        tones = np.arange(ue, N, S)
+        cs = CubicSpline(tones, v[tones], bc_type="natural")
+        span = np.arange(tones[0], tones[-1] + 1)
+        assert np.allclose(out[span], cs(span), atol=1e-10, rtol=0)
+        assert np.allclose(out[:tones[0]], v[tones[0]]) and np.allclose(out[tones[-1]:], v[tones[-1]])
+        Mdd = O.natural_spline_second_derivatives(v[tones])
+        assert np.allclose(Mdd, cs(tones, 2) * S * S, atol=1e-9)
+
+
+def test_natural_spline_reproduces_a_line():
+    S, N = 12, 120
+    n = np.arange(N, dtype=np.float64)
+    Hlin = (0.3 + 0.01j) + (0.002 - 0.003j) * n
+    y, pil = _single_ue_input(Hlin, N)
+    out = O.comb_ls_spline(y, pil, S, [5])[0, 0, 0]
+    assert np.allclose(out[5:5 + S * 9 + 1], Hlin[5:5 + S * 9 + 1], atol=1e-12)
