@@ -252,7 +252,9 @@ def comb_lines(dev, stream, steps=20, warmup=3):
                      "nmse_gap_db": abs(O.nmse_db(o1, cb.H[:1]) - O.nmse_db(ref, cb.H[:1])),
                      "discrepancy_db": round(O.discrepancy_db(o1, ref), 1)}
     for kind, ref_fn in (("ls_hold", lambda: O.comb_ls_hold(cb.y[:1], cb.pilots, S, range(K))),
-                         ("ls_linear3", lambda: O.comb_ls_linear(cb.y[:1], cb.pilots, S, range(K), fold=3))):
+                         ("ls_linear3", lambda: O.comb_ls_linear(cb.y[:1], cb.pilots, S, range(K), fold=3)),
+                         ("ls_quadratic", lambda: O.comb_ls_quadratic(cb.y[:1], cb.pilots, S, range(K))),
+                         ("ls_spline", lambda: O.comb_ls_spline(cb.y[:1], cb.pilots, S, range(K)))):
         with CombPlan(M=M, K=K, N=N, N_fft=Nf, comb=S, kind=kind, rsource="uniform", L=8.0,
                       sigma2=cb.sigma2, max_slots=slots) as pl:
             out = torch.empty((slots, M, K, N), dtype=torch.complex64, device=dev)

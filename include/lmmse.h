@@ -275,8 +275,9 @@ int lmmse_sync_status(lmmse_plan_t plan, void *stream, int *info);
  *   LMMSE_COMB_12W: the S subcarriers S b .. S b + S - 1.
  * W_b depends only on b - wst_b (and, for 12W, on k): each UE has `win`
  * filter classes, designed in FP64 on the device when the plan is made and
- * applied in FP32.  The LS baselines (LS_HOLD, LS_LINEAR, LS_LINEAR3) use
- * the same LS values and no filters (get_filters returns zeros). */
+ * applied in FP32.  The interpolated-LS baselines (Sec. II: LS_HOLD,
+ * LS_LINEAR, LS_LINEAR3, LS_QUADRATIC, LS_SPLINE) use the same LS values and
+ * no filters (get_filters returns zeros); all run in FP32. */
 typedef enum lmmse_comb_kind {
     LMMSE_COMB_3W = 0,
     LMMSE_COMB_12W = 1,
@@ -285,8 +286,15 @@ typedef enum lmmse_comb_kind {
                                    tone at or below it (the first below it) */
     LMMSE_COMB_LS_LINEAR = 3,   /* linear between the two tones around it; the
                                    nearest tone outside the first..last tone */
-    LMMSE_COMB_LS_LINEAR3 = 4   /* "3-fold": linear at the 3W output positions
+    LMMSE_COMB_LS_LINEAR3 = 4,  /* "3-fold": linear at the 3W output positions
                                    tone + j S/3, held as in 3W */
+    LMMSE_COMB_LS_QUADRATIC = 5,/* second-order polynomial: between tones i and
+                                   i+1 the quadratic through tones i-1, i, i+1
+                                   (0, 1, 2 in the first interval); the nearest
+                                   tone outside the first..last tone */
+    LMMSE_COMB_LS_SPLINE = 6    /* natural cubic spline through the UE's tones
+                                   (zero second derivative at the first and
+                                   last tone); the nearest tone outside them */
 } lmmse_comb_kind;
 
 typedef struct lmmse_comb_desc {
@@ -294,7 +302,8 @@ typedef struct lmmse_comb_desc {
     int K;           /* active UEs = comb offsets 0..K-1           (1..comb) */
     int comb;        /* comb spacing S: N % S == 0; 3W: S % 3 == 0;
                         12W: S <= 16                                         */
-    int N;           /* used subcarriers; N / S >= win and <= 4096          */
+    int N;           /* used subcarriers; N / S <= 4096 and >= win (3W 3,
+                        12W 12, QUADRATIC and SPLINE 3, other LS kinds 2)   */
     int N_fft;       /* FFT size (>= N)                                      */
     int kind;        /* lmmse_comb_kind                                      */
     int rsource;     /* LMMSE_R_UNIFORM or LMMSE_R_EXPONENTIAL (the filter

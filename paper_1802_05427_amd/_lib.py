@@ -35,7 +35,7 @@ class PlanDesc(ctypes.Structure):
 P_desc = ctypes.POINTER(PlanDesc)
 
 # lmmse_comb_kind
-COMB_3W, COMB_12W, COMB_LS_HOLD, COMB_LS_LINEAR, COMB_LS_LINEAR3 = range(5)
+COMB_3W, COMB_12W, COMB_LS_HOLD, COMB_LS_LINEAR, COMB_LS_LINEAR3, COMB_LS_QUADRATIC, COMB_LS_SPLINE = range(7)
 
 
 class CombDesc(ctypes.Structure):

@@ -228,7 +228,8 @@ class Plan:
 
 
 _COMB_KIND = {"3w": _lib.COMB_3W, "12w": _lib.COMB_12W, "ls_hold": _lib.COMB_LS_HOLD,
-              "ls_linear": _lib.COMB_LS_LINEAR, "ls_linear3": _lib.COMB_LS_LINEAR3}
+              "ls_linear": _lib.COMB_LS_LINEAR, "ls_linear3": _lib.COMB_LS_LINEAR3,
+              "ls_quadratic": _lib.COMB_LS_QUADRATIC, "ls_spline": _lib.COMB_LS_SPLINE}
 
 
 def make_comb_desc(M, K, N, N_fft, comb=12, kind="12w", rsource="uniform", L=8.0, tau_rms=1.0,

@@ -166,11 +166,16 @@ def test_sample_window_limits():
 
 @pytest.mark.parametrize("kw,code", [
     (dict(), _lib.OK), (dict(kind="3w"), _lib.OK), (dict(rsource="exp", tau_rms=2.0, taps=6), _lib.OK),
-    (dict(K=0), _lib.INVALID_ARG), (dict(kind=5), _lib.INVALID_ARG), (dict(sigma2=0.0), _lib.INVALID_ARG),
+    (dict(K=0), _lib.INVALID_ARG), (dict(kind=7), _lib.INVALID_ARG), (dict(sigma2=0.0), _lib.INVALID_ARG),
     (dict(rsource="sample"), _lib.INVALID_ARG), (dict(L=-1.0), _lib.INVALID_ARG),
     (dict(K=13), _lib.UNSUPPORTED), (dict(N=1210), _lib.UNSUPPORTED),
     (dict(comb=8, N=1200, kind="3w"), _lib.UNSUPPORTED), (dict(comb=18, N=1206 * 3, N_fft=4096), _lib.UNSUPPORTED),
     (dict(N=120), _lib.UNSUPPORTED), (dict(N=2400, N_fft=2048), _lib.UNSUPPORTED),
+    (dict(kind="ls_linear", N=24), _lib.OK), (dict(kind="ls_quadratic", N=24), _lib.UNSUPPORTED),
+    (dict(kind="ls_spline", N=36), _lib.OK), (dict(kind="ls_spline", N=24), _lib.UNSUPPORTED),
+    (dict(kind="ls_spline", N=24576, N_fft=32768), _lib.OK),
+    (dict(kind="ls_spline", N=24588, N_fft=32768), _lib.UNSUPPORTED),
+    (dict(kind="ls_quadratic", N=24588, N_fft=32768), _lib.OK),
 ])
 def test_comb_validate(kw, code):
     from paper_1802_05427_amd import comb_validate

@@ -52,8 +52,15 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("kind", ["3w", "12w"])
-@pytest.mark.parametrize("c", CASES)
+ODD_12W = [
+    # odd spacing and odd N: neighbouring subcarriers in different groups, odd row length
+    dict(M=2, K=3, N=255, N_fft=256, L=6.0, comb=5, slots=2, snr=15.0),
+    dict(M=3, K=7, N=637, N_fft=1024, L=8.0, comb=7, slots=1, snr=20.0),
+]
+
+
+@pytest.mark.parametrize("kind,c", [(k, c) for c in CASES for k in ("3w", "12w")]
+                         + [("12w", c) for c in ODD_12W])
 def test_comb_filters_and_estimate_match_oracle(dev, c, kind):
     print(f"comb {kind} {c}", flush=True)
     S = c.get("comb", 12)
@@ -95,6 +102,28 @@ def test_interpolated_ls_baselines_match_oracle(dev, c, kind):
         ref = O.comb_ls_hold(cb.y, cb.pilots, S, range(c["K"]))
     else:
         ref = O.comb_ls_linear(cb.y, cb.pilots, S, range(c["K"]), fold=3 if kind == "ls_linear3" else None)
+    disc = O.discrepancy_db(out, ref)
+    print(f"  discrepancy {disc:.1f} dB", flush=True)
+    assert disc < -120.0
+
+
+EDGE_LS = [
+    dict(M=1, K=2, N=36, N_fft=64, L=4.0, slots=3, snr=10.0),               # 3 tones: the minimum
+    dict(M=1, K=1, N=24576, N_fft=32768, L=8.0, slots=1, snr=20.0),         # 2048 tones: spline maximum
+]
+
+
+@pytest.mark.parametrize("kind", ["ls_quadratic", "ls_spline"])
+@pytest.mark.parametrize("c", [CASES[0], CASES[1], CASES[2], CASES[5]] + EDGE_LS)
+def test_higher_order_interpolated_ls_match_oracle(dev, c, kind):
+    print(f"comb {kind} {c}", flush=True)
+    S = c.get("comb", 12)
+    cb = make_comb_batch(M=c["M"], K=c["K"], N=c["N"], N_fft=c["N_fft"], powers_db=PROFILE,
+                         snr_db=c["snr"], slots=c["slots"], comb=S)
+    with _plan(c, kind, cb.sigma2) as pl:
+        out = pl.estimate(_t(cb.y, dev), _t(cb.pilots, dev)).cpu().numpy()
+    f = O.comb_ls_quadratic if kind == "ls_quadratic" else O.comb_ls_spline
+    ref = f(cb.y, cb.pilots, S, range(c["K"]))
     disc = O.discrepancy_db(out, ref)
     print(f"  discrepancy {disc:.1f} dB", flush=True)
     assert disc < -120.0
