@@ -30,7 +30,7 @@ constexpr int kCombWinMax = 12;
 constexpr int kCombOutMax = 16;
 constexpr int kCombTonesMax = 4096;         // LS staging in LDS
 constexpr int kCombSplineTonesMax = 2048;   // LS + second derivatives + pivots in LDS
-constexpr int kCombStageBytes = 48 * 1024;        // LS values (+ spline M) of the staged columns
+constexpr int kCombLdsBytes = 64 * 1024;          // dynamic LDS of one apply workgroup
 
 struct CombPlan {
     lmmse_comb_desc d{};
@@ -129,7 +129,9 @@ __global__ __launch_bounds__(256) void comb_design_kernel(lmmse_comb_desc d, int
 
 constexpr int kCombCols = 8;   // columns per workgroup (filter classes loaded once)
 constexpr int kXcds = 8;       // XCDs of the chip
-static_assert(kCombTonesMax * 8 <= kCombStageBytes && kCombSplineTonesMax * 2 * 8 <= kCombStageBytes,
+// one staged column always fits beside the largest filter set (12W, S = 16)
+static_assert(kCombTonesMax * 8 + kCombWinMax * kCombOutMax * kCombWinMax * 8 <= kCombLdsBytes &&
+                  kCombSplineTonesMax * (2 * 8 + 4) + 8 <= kCombLdsBytes,
               "one column must fit the staging area");
 
 // One UE k and kCombCols columns (c = slot * M + antenna) per workgroup,
@@ -483,10 +485,12 @@ int lmmse_comb_estimate(lmmse_comb_t c, int slots, const void* y, const void* pi
     const CombPlan& p = c->p;
     const long long ncols = (long long)slots * p.d.M;
     const bool spline = p.d.kind == LMMSE_COMB_LS_SPLINE;
-    // as many columns staged together as fit kCombStageBytes of LS values
-    // (and, for the spline, second derivatives); at least one fits
+    // as many columns staged together as fit, beside the filter classes (and
+    // the spline's pivots), in kCombLdsBytes of LS values (and, for the
+    // spline, second derivatives); one column always fits
     const int per_col = p.ntones * (spline ? 2 : 1) * (int)sizeof(float2);
-    const int cs = std::max(1, std::min(lmmse::kCombCols, lmmse::kCombStageBytes / per_col));
+    const int fixed = p.win * p.nout * p.win * (int)sizeof(float2) + (spline ? p.ntones * (int)sizeof(float) : 0);
+    const int cs = std::max(1, std::min(lmmse::kCombCols, (lmmse::kCombLdsBytes - fixed) / per_col));
     size_t shm = ((size_t)cs * p.ntones + (size_t)p.win * p.nout * p.win) * sizeof(float2);
     if (spline) shm += (size_t)cs * p.ntones * sizeof(float2) + (size_t)p.ntones * sizeof(float);
     const long long ngrp = (ncols + lmmse::kCombCols - 1) / lmmse::kCombCols;

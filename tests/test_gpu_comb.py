@@ -56,6 +56,8 @@ ODD_12W = [
     # odd spacing and odd N: neighbouring subcarriers in different groups, odd row length
     dict(M=2, K=3, N=255, N_fft=256, L=6.0, comb=5, slots=2, snr=15.0),
     dict(M=3, K=7, N=637, N_fft=1024, L=8.0, comb=7, slots=1, snr=20.0),
+    # the largest filter set (S = 16) beside 768 tones: 7 columns staged, then 1
+    dict(M=8, K=2, N=12288, N_fft=16384, L=8.0, comb=16, slots=1, snr=20.0),
 ]
 
 
