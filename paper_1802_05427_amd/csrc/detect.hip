@@ -27,49 +27,70 @@ __device__ __forceinline__ float2 cmul_conj_a(float2 a, float2 b) {   // conj(a)
     return make_float2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
 }
 
+// KTC = K + T rounded up to a multiple of 4 (rows K + T .. KTC - 1 of the
+// staged [H | Y] are zero), so that the staging and the Gram loops have
+// compile-time trip counts: every thread issues all of its loads of a stage
+// before storing any, and the accumulation runs without branches.
+template <int KTC>
 __global__ __launch_bounds__(256) void mmse_detect_kernel(const float2* h, const float2* y, float2* x,
                                                           int M, int K, int T, int N, float sigma2,
                                                           int nblk) {
+    static_assert(KTC % 4 == 0 && KTC <= dMaxK + dMaxT, "row count");
     extern __shared__ float2 sm[];
     const int KT = K + T;
-    float2* Hs = sm;                         // [dMC][K][dNB]
-    float2* Ys = Hs + dMC * K * dNB;         // [dMC][T][dNB]
+    float2* Hs = sm;                         // [dMC][KTC][dNB]: rows q < K of H, then Y, then zeros
     float2* Gs = sm;                         // [dNB][K][KT], after the antenna loop
     const int tid = threadIdx.x, l = tid & (dNB - 1), i = tid / dNB;
     const long long s = blockIdx.x / nblk;
     const int n0 = (int)(blockIdx.x % nblk) * dNB;
     const float2* hs = h + s * (long long)M * K * N;
     const float2* ys = y + s * (long long)M * T * N;
+    const bool nlive = n0 + l < N;
 
-    float2 acc[dMaxK + dMaxT];
+    float2 acc[KTC];
 #pragma unroll
-    for (int c = 0; c < dMaxK + dMaxT; ++c) acc[c] = make_float2(0.f, 0.f);
+    for (int c = 0; c < KTC; ++c) acc[c] = make_float2(0.f, 0.f);
 
+    // thread (l, i) stages rows q = i and i + 16 (those below KTC) of every
+    // antenna of a stage: one base pointer and stride per row
+    const float2* qp[2];
+    long long qs[2];
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+        const int q = i + 16 * w;
+        qp[w] = (q < K ? hs + (long long)q * N : ys + (long long)(q - K) * N) + n0 + l;
+        qs[w] = q < K ? (long long)K * N : (long long)T * N;
+    }
     for (int m0 = 0; m0 < M; m0 += dMC) {
-        for (int e = tid; e < dMC * KT * dNB; e += 256) {
-            const int ll = e % dNB, r = e / dNB, mm = r / KT, q = r - mm * KT;
-            const int m = m0 + mm, n = n0 + ll;
-            float2 v = make_float2(0.f, 0.f);
-            if (m < M && n < N)
-                v = q < K ? hs[((long long)m * K + q) * N + n] : ys[((long long)m * T + (q - K)) * N + n];
-            if (q < K)
-                Hs[(mm * K + q) * dNB + ll] = v;
-            else
-                Ys[(mm * T + (q - K)) * dNB + ll] = v;
+        float2 v[2][dMC];
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+            const int q = i + 16 * w;
+#pragma unroll
+            for (int mm = 0; mm < dMC; ++mm) {
+                v[w][mm] = make_float2(0.f, 0.f);
+                if (q < KTC && nlive && m0 + mm < M && q < KT) v[w][mm] = qp[w][(m0 + mm) * qs[w]];
+            }
+        }
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+            const int q = i + 16 * w;
+            if (q < KTC) {
+#pragma unroll
+                for (int mm = 0; mm < dMC; ++mm) Hs[(mm * KTC + q) * dNB + l] = v[w][mm];
+            }
         }
         __syncthreads();
         if (i < K) {
+#pragma unroll 2
             for (int mm = 0; mm < dMC; ++mm) {
-                const float2 hi = Hs[(mm * K + i) * dNB + l];
+                const float2* hm = Hs + mm * KTC * dNB + l;
+                const float2 hi = hm[i * dNB];
 #pragma unroll
-                for (int c = 0; c < dMaxK + dMaxT; ++c) {
-                    if (c < KT) {
-                        const float2 v =
-                            c < K ? Hs[(mm * K + c) * dNB + l] : Ys[(mm * T + (c - K)) * dNB + l];
-                        const float2 p = cmul_conj_a(hi, v);
-                        acc[c].x += p.x;
-                        acc[c].y += p.y;
-                    }
+                for (int c = 0; c < KTC; ++c) {
+                    const float2 p = cmul_conj_a(hi, hm[c * dNB]);
+                    acc[c].x += p.x;
+                    acc[c].y += p.y;
                 }
             }
         }
@@ -78,7 +99,7 @@ __global__ __launch_bounds__(256) void mmse_detect_kernel(const float2* h, const
     if (i < K) {
         float2* g = Gs + (l * K + i) * KT;
 #pragma unroll
-        for (int c = 0; c < dMaxK + dMaxT; ++c)
+        for (int c = 0; c < KTC; ++c)
             if (c < KT) g[c] = acc[c];
         g[i].x += sigma2;
     }
@@ -161,10 +182,24 @@ extern "C" int lmmse_mmse_detect(int slots, int M, int K, int T, int N, const vo
     if (slots == 0) return LMMSE_OK;
     if (!h_hat || !y_data || !x_out) return LMMSE_ERR_INVALID_ARG;
     const int nblk = (N + lmmse::dNB - 1) / lmmse::dNB;
-    const size_t shm = std::max((size_t)lmmse::dMC * (K + T) * lmmse::dNB,
+    const int ktc = (K + T + 3) & ~3;
+    const size_t shm = std::max((size_t)lmmse::dMC * ktc * lmmse::dNB,
                                 (size_t)lmmse::dNB * K * (K + T)) * sizeof(float2);
-    hipLaunchKernelGGL(lmmse::mmse_detect_kernel, dim3((unsigned)((long long)slots * nblk)), dim3(256),
-                       shm, (hipStream_t)stream, (const float2*)h_hat, (const float2*)y_data,
-                       (float2*)x_out, M, K, T, N, (float)sigma2, nblk);
+    const dim3 grid((unsigned)((long long)slots * nblk)), block(256);
+    const hipStream_t st = (hipStream_t)stream;
+    const float2 *hp = (const float2*)h_hat, *yp = (const float2*)y_data;
+    float2* xp = (float2*)x_out;
+    switch (ktc) {
+#define LMMSE_DK(C)                                                                              \
+    case C:                                                                                      \
+        hipLaunchKernelGGL(lmmse::mmse_detect_kernel<C>, grid, block, shm, st, hp, yp, xp, M, K, \
+                           T, N, (float)sigma2, nblk);                                           \
+        break;
+        LMMSE_DK(4) LMMSE_DK(8) LMMSE_DK(12) LMMSE_DK(16) LMMSE_DK(20) LMMSE_DK(24) LMMSE_DK(28)
+        LMMSE_DK(32)
+#undef LMMSE_DK
+        default:
+            return LMMSE_ERR_UNSUPPORTED;
+    }
     return hipGetLastError() == hipSuccess ? LMMSE_OK : LMMSE_ERR_HIP;
 }
