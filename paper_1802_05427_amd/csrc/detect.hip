@@ -61,8 +61,10 @@ __global__ __launch_bounds__(256) void mmse_detect_kernel(const float2* h, const
         qp[w] = (q < K ? hs + (long long)q * N : ys + (long long)(q - K) * N) + n0 + l;
         qs[w] = q < K ? (long long)K * N : (long long)T * N;
     }
-    for (int m0 = 0; m0 < M; m0 += dMC) {
-        float2 v[2][dMC];
+    // the loads of stage m0 + dMC are issued before the Gram updates of
+    // stage m0 and stored to LDS after them
+    float2 v[2][dMC];
+    auto load_stage = [&](int m0) {
 #pragma unroll
         for (int w = 0; w < 2; ++w) {
             const int q = i + 16 * w;
@@ -72,6 +74,8 @@ __global__ __launch_bounds__(256) void mmse_detect_kernel(const float2* h, const
                 if (q < KTC && nlive && m0 + mm < M && q < KT) v[w][mm] = qp[w][(m0 + mm) * qs[w]];
             }
         }
+    };
+    auto store_stage = [&]() {
 #pragma unroll
         for (int w = 0; w < 2; ++w) {
             const int q = i + 16 * w;
@@ -80,7 +84,13 @@ __global__ __launch_bounds__(256) void mmse_detect_kernel(const float2* h, const
                 for (int mm = 0; mm < dMC; ++mm) Hs[(mm * KTC + q) * dNB + l] = v[w][mm];
             }
         }
-        __syncthreads();
+    };
+    load_stage(0);
+    store_stage();
+    __syncthreads();
+    for (int m0 = 0; m0 < M; m0 += dMC) {
+        const bool more = m0 + dMC < M;
+        if (more) load_stage(m0 + dMC);
         if (i < K) {
 #pragma unroll 2
             for (int mm = 0; mm < dMC; ++mm) {
@@ -94,6 +104,8 @@ __global__ __launch_bounds__(256) void mmse_detect_kernel(const float2* h, const
                 }
             }
         }
+        __syncthreads();
+        if (more) store_stage();
         __syncthreads();
     }
     if (i < K) {
