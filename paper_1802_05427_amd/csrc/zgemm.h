@@ -1,7 +1,7 @@
 // Batched complex GEMM over strided operand views (used by the
 // sample-covariance design for windows too wide for the register-resident
-// sweep, and by its backward): FP64 on the matrix cores, or FP32 on the
-// vector units for products that only need FP32 accuracy.
+// sweep, and by its backward) on the matrix cores: FP64, or FP32 for
+// products that only need FP32 accuracy.
 #pragma once
 
 #include "internal.h"
@@ -60,133 +60,41 @@ __device__ __forceinline__ typename Cx<R>::T zload(const void* p, long long i, i
     return Cx<R>::make((double)v.x, conj ? -(double)v.y : (double)v.y);
 }
 
-// R: the arithmetic precision (double: FP64 products and sums; float: FP32,
-// for products whose result only needs FP32 accuracy).
-template <typename TA, typename TB, typename TC, typename R = double>
-__global__ __launch_bounds__(256) void zgemm_kernel(ZGemmArgs g) {
+// The product on the matrix cores: a workgroup computes one 64 x 64 output
+// tile, staging 16-term chunks of A and B through LDS (the next chunk's loads
+// in flight during the current chunk's MFMAs); each wave owns a 32 x 32
+// quarter as 2 x 2 MFMA tiles, real and imaginary parts in separate
+// accumulators (4 real products per complex one).  Operand lane (i, k) =
+// (lane % 16, lane / 16).  R is the arithmetic precision: double
+// (v_mfma_f64_16x16x4f64, FP64 products and sums) or float
+// (v_mfma_f32_16x16x4f32, for products whose result only needs FP32
+// accuracy).
+typedef double zd4 __attribute__((ext_vector_type(4)));
+typedef float zf4 __attribute__((ext_vector_type(4)));
+
+template <typename R>
+struct ZMma;
+template <>
+struct ZMma<double> {
+    using V = zd4;
+    __device__ static V mma(double a, double b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    // accumulator element v of lane l: row 4 v + l / 16, column l % 16
+    __device__ static int row(int v, int lk) { return 4 * v + lk; }
+};
+template <>
+struct ZMma<float> {
+    using V = zf4;
+    __device__ static V mma(float a, float b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    // accumulator element v of lane l: row 4 (l / 16) + v, column l % 16
+    __device__ static int row(int v, int lk) { return 4 * lk + v; }
+};
+
+template <typename TA, typename TB, typename TC, typename R>
+__global__ __launch_bounds__(256) void zgemm_mfma_kernel(ZGemmArgs g) {
     using CT = typename Cx<R>::T;
+    using ZM = ZMma<R>;
     __shared__ CT As[zKC][zT];
     __shared__ CT Bs[zKC][zT];
-    const int tid = threadIdx.x;
-    long long t = blockIdx.x;
-    int tm, tn;
-    long long bat;
-    if (g.herm) {   // lower tiles (tn <= tm) of a square C, row by row
-        const int per = g.tiles_m * (g.tiles_m + 1) / 2;
-        int q = (int)(t % per);
-        bat = t / per;
-        tm = 0;
-        while (q > tm) {
-            q -= tm + 1;
-            ++tm;
-        }
-        tn = q;
-    } else {
-        tn = (int)(t % g.tiles_n);
-        t /= g.tiles_n;
-        tm = (int)(t % g.tiles_m);
-        bat = t / g.tiles_m;
-    }
-    const int r0 = tm * zT, c0 = tn * zT;
-    const long long abase = zbase(g.A, bat, g.K, g.nb);
-    const long long bbase = zbase(g.B, bat, g.K, g.nb);
-    const long long cbase = zbase(g.C, bat, g.K, g.nb);
-    // loads: consecutive lanes walk the operand's unit-stride index
-    const bool a_rowfast = g.A.rs == 1, b_colfast = g.B.cs == 1;
-    // outputs: consecutive lanes walk C's unit-stride index
-    const bool c_rowfast = g.C.rs == 1;
-    const int tf = tid & 15, ts = tid >> 4;
-    const int ri = c_rowfast ? tf : ts, ci = c_rowfast ? ts : tf;
-
-    CT acc[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = Cx<R>::make(0.0, 0.0);
-
-    CT pa[4], pb[4];
-    auto fetch = [&](int k0) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int e = tid + 256 * u;
-            const int r = a_rowfast ? (e & 63) : (e >> 4), ka = a_rowfast ? (e >> 6) : (e & 15);
-            const int c = b_colfast ? (e & 63) : (e >> 4), kb = b_colfast ? (e >> 6) : (e & 15);
-            pa[u] = (r0 + r < g.m && k0 + ka < g.kd)
-                        ? zload<R, TA>(g.A.p, abase + (r0 + r) * g.A.rs + (k0 + ka) * g.A.cs, g.A.conj)
-                        : Cx<R>::make(0.0, 0.0);
-            pb[u] = (c0 + c < g.n && k0 + kb < g.kd)
-                        ? zload<R, TB>(g.B.p, bbase + (k0 + kb) * g.B.rs + (c0 + c) * g.B.cs, g.B.conj)
-                        : Cx<R>::make(0.0, 0.0);
-        }
-    };
-    fetch(0);
-    for (int k0 = 0; k0 < g.kd; k0 += zKC) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int e = tid + 256 * u;
-            const int r = a_rowfast ? (e & 63) : (e >> 4), ka = a_rowfast ? (e >> 6) : (e & 15);
-            const int c = b_colfast ? (e & 63) : (e >> 4), kb = b_colfast ? (e >> 6) : (e & 15);
-            As[ka][r] = pa[u];
-            Bs[kb][c] = pb[u];
-        }
-        __syncthreads();
-        if (k0 + zKC < g.kd) fetch(k0 + zKC);
-#pragma unroll 4
-        for (int kk = 0; kk < zKC; ++kk) {
-            CT av[4], bv[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) av[i] = As[kk][ri + 16 * i];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) bv[j] = Bs[kk][ci + 16 * j];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    acc[i][j].x = fma(av[i].x, bv[j].x, fma(-av[i].y, bv[j].y, acc[i][j].x));
-                    acc[i][j].y = fma(av[i].x, bv[j].y, fma(av[i].y, bv[j].x, acc[i][j].y));
-                }
-        }
-        __syncthreads();
-    }
-    TC* cp = reinterpret_cast<TC*>(const_cast<void*>(g.C.p));
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int r = r0 + ri + 16 * i, c = c0 + ci + 16 * j;
-            if (r >= g.m || c >= g.n) continue;
-            const long long o = cbase + r * g.C.rs + c * g.C.cs;
-            double x = g.alpha * acc[i][j].x, y = g.alpha * acc[i][j].y;
-            if (g.beta) {
-                x += (double)cp[o].x;
-                y += (double)cp[o].y;
-            }
-            if constexpr (sizeof(TC) == sizeof(double2))
-                cp[o] = make_double2(x, y);
-            else
-                cp[o] = make_float2((float)x, (float)y);
-            if (g.herm && tm != tn) {   // the mirrored entry of an off-diagonal tile
-                const long long om = cbase + c * g.C.rs + r * g.C.cs;
-                if constexpr (sizeof(TC) == sizeof(double2))
-                    cp[om] = make_double2(x, -y);
-                else
-                    cp[om] = make_float2((float)x, (float)-y);
-            }
-        }
-}
-
-// FP64 form on the matrix cores (v_mfma_f64_16x16x4f64): the same tiles,
-// views and LDS staging as zgemm_kernel; each wave owns a 32 x 32 quarter of
-// the 64 x 64 output tile as 2 x 2 MFMA tiles, real and imaginary parts in
-// separate accumulators (4 real products per complex one).  Operand lane
-// (i, k) = (lane % 16, lane / 16); accumulator element v of lane l is row
-// 4 v + l / 16, column l % 16 of its 16 x 16 tile.
-typedef double zd4 __attribute__((ext_vector_type(4)));
-
-template <typename TA, typename TB, typename TC>
-__global__ __launch_bounds__(256) void zgemm_mfma_kernel(ZGemmArgs g) {
-    __shared__ double2 As[zKC][zT];
-    __shared__ double2 Bs[zKC][zT];
     const int tid = threadIdx.x;
     long long t = blockIdx.x;
     int tm, tn;
@@ -215,7 +123,7 @@ __global__ __launch_bounds__(256) void zgemm_mfma_kernel(ZGemmArgs g) {
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32, li = lane & 15, lk = lane >> 4;
 
-    zd4 cre[2][2], cim[2][2];
+    typename ZM::V cre[2][2], cim[2][2];
     // 16 x 16 sub-tiles this wave computes (wave-uniform): those with rows and
     // columns in range and, on a diagonal tile of a Hermitian product, on or
     // below the diagonal (the upper ones are written as mirrors)
@@ -224,13 +132,13 @@ __global__ __launch_bounds__(256) void zgemm_mfma_kernel(ZGemmArgs g) {
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-            cre[i][j] = zd4{0.0, 0.0, 0.0, 0.0};
-            cim[i][j] = zd4{0.0, 0.0, 0.0, 0.0};
+            cre[i][j] = typename ZM::V{0, 0, 0, 0};
+            cim[i][j] = typename ZM::V{0, 0, 0, 0};
             const int ri = wr + 16 * i, cj = wc + 16 * j;
             live[i][j] = r0 + ri < g.m && c0 + cj < g.n && !(g.herm && tm == tn && ri < cj);
         }
 
-    double2 pa[4], pb[4];
+    CT pa[4], pb[4];
     auto fetch = [&](int k0) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -238,11 +146,11 @@ __global__ __launch_bounds__(256) void zgemm_mfma_kernel(ZGemmArgs g) {
             const int r = a_rowfast ? (e & 63) : (e >> 4), ka = a_rowfast ? (e >> 6) : (e & 15);
             const int c = b_colfast ? (e & 63) : (e >> 4), kb = b_colfast ? (e >> 6) : (e & 15);
             pa[u] = (r0 + r < g.m && k0 + ka < g.kd)
-                        ? zload<double, TA>(g.A.p, abase + (r0 + r) * g.A.rs + (k0 + ka) * g.A.cs, g.A.conj)
-                        : make_double2(0.0, 0.0);
+                        ? zload<R, TA>(g.A.p, abase + (r0 + r) * g.A.rs + (k0 + ka) * g.A.cs, g.A.conj)
+                        : Cx<R>::make(0.0, 0.0);
             pb[u] = (c0 + c < g.n && k0 + kb < g.kd)
-                        ? zload<double, TB>(g.B.p, bbase + (k0 + kb) * g.B.rs + (c0 + c) * g.B.cs, g.B.conj)
-                        : make_double2(0.0, 0.0);
+                        ? zload<R, TB>(g.B.p, bbase + (k0 + kb) * g.B.rs + (c0 + c) * g.B.cs, g.B.conj)
+                        : Cx<R>::make(0.0, 0.0);
         }
     };
     fetch(0);
@@ -260,7 +168,7 @@ __global__ __launch_bounds__(256) void zgemm_mfma_kernel(ZGemmArgs g) {
 #pragma unroll
         for (int ks = 0; ks < zKC / 4; ++ks) {
             const int kk = 4 * ks + lk;
-            double2 a[2], b[2];
+            CT a[2], b[2];
 #pragma unroll
             for (int i = 0; i < 2; ++i) a[i] = As[kk][wr + 16 * i + li];
 #pragma unroll
@@ -270,10 +178,10 @@ __global__ __launch_bounds__(256) void zgemm_mfma_kernel(ZGemmArgs g) {
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
                     if (!live[i][j]) continue;
-                    cre[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].x, cre[i][j], 0, 0, 0);
-                    cre[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[i].y, b[j].y, cre[i][j], 0, 0, 0);
-                    cim[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].y, cim[i][j], 0, 0, 0);
-                    cim[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].y, b[j].x, cim[i][j], 0, 0, 0);
+                    cre[i][j] = ZM::mma(a[i].x, b[j].x, cre[i][j]);
+                    cre[i][j] = ZM::mma(-a[i].y, b[j].y, cre[i][j]);
+                    cim[i][j] = ZM::mma(a[i].x, b[j].y, cim[i][j]);
+                    cim[i][j] = ZM::mma(a[i].y, b[j].x, cim[i][j]);
                 }
         }
         __syncthreads();
@@ -286,7 +194,7 @@ __global__ __launch_bounds__(256) void zgemm_mfma_kernel(ZGemmArgs g) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 if (!live[i][j]) continue;
-                const int r = r0 + wr + 16 * i + 4 * v + lk, c = c0 + wc + 16 * j + li;
+                const int r = r0 + wr + 16 * i + ZM::row(v, lk), c = c0 + wc + 16 * j + li;
                 if (r >= g.m || c >= g.n) continue;
                 // mirrors: every sub-tile off the diagonal of a Hermitian product
                 const bool mirror = g.herm && (tm != tn || wr + 16 * i > wc + 16 * j);
@@ -318,10 +226,7 @@ inline hipError_t zgemm(ZGemmArgs g, long long nbat, hipStream_t st) {
     const long long blocks =
         nbat * (g.herm ? (long long)g.tiles_m * (g.tiles_m + 1) / 2 : (long long)g.tiles_m * g.tiles_n);
     if (blocks == 0) return hipSuccess;
-    if constexpr (sizeof(R) == sizeof(double))
-        hipLaunchKernelGGL((zgemm_mfma_kernel<TA, TB, TC>), dim3((unsigned)blocks), dim3(256), 0, st, g);
-    else
-        hipLaunchKernelGGL((zgemm_kernel<TA, TB, TC, R>), dim3((unsigned)blocks), dim3(256), 0, st, g);
+    hipLaunchKernelGGL((zgemm_mfma_kernel<TA, TB, TC, R>), dim3((unsigned)blocks), dim3(256), 0, st, g);
     return hipGetLastError();
 }
 
