@@ -39,6 +39,8 @@ LARGE = [
     dict(M=20, K=2, N=400, N_fft=512, taps=16, tau=4.0, B=100, Wn=200, slots=2),   # M < Wn
     dict(M=16, K=2, N=3300, N_fft=4096, taps=144, tau=32.0, B=132, Wn=198, slots=1),
     dict(M=260, K=1, N=480, N_fft=512, taps=16, tau=4.0, B=120, Wn=240, slots=1),  # ragged M
+    dict(M=24, K=1, N=512, N_fft=512, taps=16, tau=4.0, B=128, Wn=256, slots=1),   # widest: 4 panels of 64
+    dict(M=24, K=1, N=600, N_fft=1024, taps=16, tau=4.0, B=150, Wn=162, slots=1),  # narrowest: 3 panels of 54
 ]
 
 
