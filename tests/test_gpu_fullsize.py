@@ -1,0 +1,110 @@
+"""GPU parity at the benchmarked sizes, in the launch configurations the
+bench times, on sampled outputs the FP64 oracle computes column by column:
+
+  * the fused despread + block filter on 64 paper-sized slots (M=128, K=12,
+    N=1200 of 2048, overlapping 150/100, exponential design), FP32 and
+    BF16x3, every user and block of sampled (slot, antenna) columns;
+  * the comb-pilot 3W / 12W estimators on 64 slots of 128 antennas and 4
+    UEs, sampled (slot, antenna) columns;
+  * MMSE detection on 64 slots of 128 antennas, 12 users and 12 data
+    symbols, sampled (slot, subcarrier) problems.
+
+The slots are distinct (drawn on the GPU from one seeded generator)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1802_05427_amd import CombPlan, Plan, mmse_detect
+from synth import make_comb_batch, make_pilots
+from synth.torch_slots import draw_batch
+
+pytestmark = pytest.mark.gpu
+
+M, K, N, NF, B, WN, TAPS, TAU, S = 128, 12, 1200, 2048, 100, 150, 72, 4.0, 64
+SAMPLES = [(0, 0), (0, 127), (17, 55), (38, 3), (63, 0), (63, 127)]   # (slot, antenna)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def batch(dev):
+    pil = torch.from_numpy(make_pilots(K, N)).to(dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(180205427 + 64)
+    sigma2 = 0.1   # SNR 10 dB
+    ys = [draw_batch(g, 16, M, K, N, NF, TAPS, TAU, TAU, sigma2, pil)[0] for _ in range(S // 16)]
+    return torch.cat(ys).contiguous(), pil, sigma2
+
+
+@pytest.mark.parametrize("precision,limit_db", [("fp32", -120.0), ("bf16x3", -110.0)])
+def test_headline_batch_sampled_columns(dev, batch, precision, limit_db):
+    y, pil, sigma2 = batch
+    print(f"full-size estimate {precision}: {S} slots", flush=True)
+    with Plan(M=M, K=K, N=N, N_fft=NF, B=B, Wn=WN, rsource="exp", taps=TAPS, tau_rms=TAU,
+              sigma2=sigma2, max_slots=S, precision=precision) as plan:
+        out = torch.empty_like(y)
+        plan.estimate(y, pil, sigma2, out=out)
+        torch.cuda.synchronize()
+    pil_h = pil.cpu().numpy()
+    for s, m in SAMPLES:
+        ys = y[s:s + 1, m:m + 1].cpu().numpy().astype(np.complex128)
+        ref = O.estimate(ys, pil_h, sigma2, B, WN, "exp", N_fft=NF, tau=TAU, taps=TAPS)
+        got = out[s:s + 1, m:m + 1].cpu().numpy()
+        disc = O.discrepancy_db(got, ref)
+        print(f"  slot {s} antenna {m}: discrepancy {disc:.1f} dB", flush=True)
+        assert disc < limit_db, (s, m, disc)
+
+
+@pytest.mark.parametrize("kind", ["3w", "12w"])
+def test_comb_batch_sampled_columns(dev, kind):
+    Kc, Sc = 4, 12
+    cb = make_comb_batch(M=M, K=Kc, N=N, N_fft=NF, powers_db=[-2, -8, -10, -12, -15, -18],
+                         snr_db=20.0, slots=S, comb=Sc)
+    y = torch.from_numpy(cb.y).to(dev)
+    pil = torch.from_numpy(cb.pilots).to(dev)
+    print(f"full-size comb {kind}: {S} slots", flush=True)
+    with CombPlan(M=M, K=Kc, N=N, N_fft=NF, comb=Sc, kind=kind, rsource="uniform", L=8.0,
+                  sigma2=cb.sigma2, max_slots=S) as pl:
+        out = pl.estimate(y, pil)
+        torch.cuda.synchronize()
+    rd = lambda d: O.r_uniform(d, 8.0, NF)
+    for s, m in SAMPLES:
+        ref = O.comb_estimate(cb.y[s:s + 1, m:m + 1], cb.pilots, cb.sigma2, Sc, range(Kc), kind, rd)
+        disc = O.discrepancy_db(out[s:s + 1, m:m + 1].cpu().numpy(), ref)
+        print(f"  slot {s} antenna {m}: discrepancy {disc:.1f} dB", flush=True)
+        assert disc < -120.0, (s, m, disc)
+
+
+def test_detection_batch_sampled_subcarriers(dev):
+    T, sigma2 = 12, 0.1
+    pil = torch.from_numpy(make_pilots(K, N)).to(dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(180205427 + 65)
+    H = torch.cat([draw_batch(g, 16, M, K, N, NF, TAPS, TAU, TAU, 0.0, pil)[1]
+                   for _ in range(S // 16)]).contiguous()
+    bits = torch.randint(0, 2, (S, T, K, N, 2), generator=g, device=dev).float()
+    X = torch.complex(1 - 2 * bits[..., 0], 1 - 2 * bits[..., 1]) / np.sqrt(2.0)
+    Y = torch.zeros((S, M, T, N), dtype=torch.complex64, device=dev)
+    for k in range(K):
+        Y += H[:, :, k, None, :] * X[:, None, :, k, :]
+    Y += torch.complex(torch.randn(Y.shape, generator=g, device=dev),
+                       torch.randn(Y.shape, generator=g, device=dev)) * float(np.sqrt(sigma2 / 2))
+    print(f"full-size detection: {S} slots", flush=True)
+    out = mmse_detect(H, Y, sigma2)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(7)
+    picks = [(0, 0), (63, N - 1)] + [(int(rng.integers(S)), int(rng.integers(N))) for _ in range(10)]
+    for s, n in picks:
+        h = H[s:s + 1, :, :, n:n + 1].cpu().numpy().astype(np.complex128)
+        yy = Y[s:s + 1, :, :, n:n + 1].cpu().numpy().astype(np.complex128)
+        ref = O.mmse_detect(h, yy, sigma2)[0, :, :, 0]
+        got = out[s, :, :, n].cpu().numpy()
+        rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        assert rel < 1e-5, (s, n, rel)
+    print(f"  {len(picks)} subcarrier problems within 1e-5", flush=True)
