@@ -7,7 +7,8 @@ bench times, on sampled outputs the FP64 oracle computes column by column:
   * the comb-pilot 3W / 12W estimators on 64 slots of 128 antennas and 4
     UEs, sampled (slot, antenna) columns;
   * MMSE detection on 64 slots of 128 antennas, 12 users and 12 data
-    symbols, sampled (slot, subcarrier) problems.
+    symbols, sampled (slot, subcarrier) problems;
+  * the large sample-covariance workload on 32 slots, sampled windows.
 
 The slots are distinct (drawn on the GPU from one seeded generator)."""
 import numpy as np
@@ -108,3 +109,33 @@ def test_detection_batch_sampled_subcarriers(dev):
         rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
         assert rel < 1e-5, (s, n, rel)
     print(f"  {len(picks)} subcarrier problems within 1e-5", flush=True)
+
+
+def test_large_sample_batch_sampled_windows(dev):
+    """The large workload (M=256, K=24, N=3300 of 4096, windows of 198 around
+    blocks of 132, per-window sample covariance, FP16x3 filter) on 32 slots:
+    sampled (slot, user, block) windows, the oracle's covariance, filter and
+    product for all 256 antennas of each."""
+    Ml, Kl, Nl, Nfl, Bl, Wl, Sl = 256, 24, 3300, 4096, 132, 198, 32
+    sigma2 = 10.0 ** -1.5
+    pil = torch.from_numpy(make_pilots(Kl, Nl)).to(dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(180205427 + 66)
+    y = torch.cat([draw_batch(g, 4, Ml, Kl, Nl, Nfl, 144, 32.0, 32.0, sigma2, pil)[0]
+                   for _ in range(Sl // 4)]).contiguous()
+    print(f"full-size large sample-covariance estimate: {Sl} slots", flush=True)
+    with Plan(M=Ml, K=Kl, N=Nl, N_fft=Nfl, B=Bl, Wn=Wl, rsource="sample", sigma2=sigma2,
+              max_slots=Sl, precision="fp16x3") as pl:
+        out = pl.estimate(y, pil, sigma2)
+        torch.cuda.synchronize()
+    starts, offs = O.window_starts(Nl, Bl, Wl)
+    nb, lam = Nl // Bl, sigma2 / Kl
+    pil_h = pil.cpu().numpy()
+    for s, k, b in [(0, 0, 0), (31, 23, nb - 1), (13, 7, 12), (22, 16, 1)]:
+        X = O.despread(y[s:s + 1].cpu().numpy().astype(np.complex128), pil_h)[0, :, k, :]
+        Xw = X[:, starts[b]:starts[b] + Wl]
+        R = O.sample_covariance(Xw)
+        W = O.lmmse._filter(R[offs[b]:offs[b] + Bl], R, lam)
+        disc = O.discrepancy_db(out[s, :, k, b * Bl:(b + 1) * Bl].cpu().numpy(), Xw @ W.T)
+        print(f"  slot {s} user {k} block {b}: discrepancy {disc:.1f} dB", flush=True)
+        assert disc < -110.0, (s, k, b, disc)
