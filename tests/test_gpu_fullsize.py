@@ -8,7 +8,9 @@ bench times, on sampled outputs the FP64 oracle computes column by column:
     UEs, sampled (slot, antenna) columns;
   * MMSE detection on 64 slots of 128 antennas, 12 users and 12 data
     symbols, sampled (slot, subcarrier) problems;
-  * the large sample-covariance workload on 32 slots, sampled windows.
+  * the large sample-covariance workload on 32 slots, sampled windows;
+  * the fixed-design forward and backward of the timed training step on
+    16 slots, whole batch.
 
 The slots are distinct (drawn on the GPU from one seeded generator)."""
 import numpy as np
@@ -139,3 +141,42 @@ def test_large_sample_batch_sampled_windows(dev):
         disc = O.discrepancy_db(out[s, :, k, b * Bl:(b + 1) * Bl].cpu().numpy(), Xw @ W.T)
         print(f"  slot {s} user {k} block {b}: discrepancy {disc:.1f} dB", flush=True)
         assert disc < -110.0, (s, k, b, disc)
+
+
+def test_fixed_fwd_bwd_batch(dev):
+    """The timed training step (fixed exponential design at tau 8 and sigma2
+    1e-4, 16 paper-sized slots with tau ~ U[2, 24] at 10 dB): the forward
+    and the backward to h_ls, tau and sigma2, against the oracle's on the
+    whole batch.  The same complex64 LS values (the oracle's despreading)
+    feed both sides, and the loss gradient is the oracle's."""
+    S2, dtau, dsig = 16, 8.0, 1e-4
+    pil = torch.from_numpy(make_pilots(K, N)).to(dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(180205427)
+    y, H, _ = draw_batch(g, S2, M, K, N, NF, TAPS, 2.0, 24.0, 0.1, pil)
+    X32 = O.despread(y.cpu().numpy().astype(np.complex128), pil.cpu().numpy()).astype(np.complex64)
+    X = X32.astype(np.complex128)
+    n = np.arange(N)
+    R = O.toeplitz_from_r(lambda d: O.r_exponential(d, dtau, TAPS, NF), n, n)
+    Ws, st = O.block_filters(R, B, WN, dsig / K)
+    ref = O.apply_filters(Ws, st, B, X)
+    _, G = O.mse_loss_and_grad(ref, H.cpu().numpy())
+    G32 = G.astype(np.complex64)
+    print(f"full-size fixed fwd+bwd: {S2} slots", flush=True)
+    with Plan(M=M, K=K, N=N, N_fft=NF, B=B, Wn=WN, rsource="exp", taps=TAPS, tau_rms=dtau,
+              sigma2=dsig, max_slots=S2) as pl:
+        h = torch.from_numpy(X32).to(dev)
+        o = pl.apply(h)
+        d_hls, d_tau, d_sig = pl.backward(h, torch.from_numpy(G32).to(dev))
+        torch.cuda.synchronize()
+        o, d_hls = o.cpu().numpy(), d_hls.cpu().numpy()
+    dX_o, gtau_o, gsig_o = O.grad_fixed_design(X, G32.astype(np.complex128), B, WN, dtau, TAPS, NF,
+                                               dsig, K)
+    disc = O.discrepancy_db(o, ref)
+    ex = np.linalg.norm(d_hls - dX_o) / np.linalg.norm(dX_o)
+    print(f"  forward {disc:.1f} dB  dX rel {ex:.2e}  dtau gpu {d_tau:.6e} oracle {gtau_o:.6e}"
+          f"  dsig gpu {d_sig:.6e} oracle {gsig_o:.6e}", flush=True)
+    assert disc < -120.0
+    assert ex < 1e-5
+    assert abs(d_tau - gtau_o) <= 1e-4 * abs(gtau_o)
+    assert abs(d_sig - gsig_o) <= 1e-4 * abs(gsig_o)
