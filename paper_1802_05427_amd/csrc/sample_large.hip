@@ -11,7 +11,7 @@
 //          A_KK -> -A_KK^-1,  A_RK -> A_RK A_KK^-1,  A_KR -> A_KK^-1 A_KR,
 //          A_RR -> A_RR - A_RK A_KK^-1 A_KR,
 //      which equals sweeping its pivots one by one.  The panel kernel sweeps
-//      the 64 x 64 diagonal block in LDS and copies the old panel columns P;
+//      the 64 x 64 diagonal block and copies the old panel columns P;
 //      F = A_RK A_KK^-1 = P A_KK^-1 and the update of A_RR, A += (-1) F P^H,
 //      are batched GEMMs (rows of K zero in F and P, so the K rows and
 //      columns are left alone), and a small kernel writes A_RK = F,
@@ -26,7 +26,6 @@
 namespace lmmse {
 
 constexpr int kPW = kSweepPanel;
-constexpr int kPR = 16;   // window rows per staging step of the panel kernel
 
 // A = R + lam I on the diagonal of every window.
 __global__ __launch_bounds__(256) void add_diag_kernel(double2* a, int Wn, double lam) {
@@ -35,44 +34,80 @@ __global__ __launch_bounds__(256) void add_diag_kernel(double2* a, int Wn, doubl
 }
 
 // Panel step over pivots [k0, k0 + kw) of every window, first part: sweeps
-// A_KK in LDS into dsw = -A_KK^-1 ([mat][kPW][kPW], zero past kw), writes it
-// to A_KK, and copies the old panel columns into P ([mat][Wn][kPW], zero
-// rows in K and zero columns >= kw).  F = P A_KK^-1 = P (-dsw) is then a
-// batched GEMM, and panel_writeback_kernel stores A_RK = F, A_KR = F^H.
+// A_KK into dsw = -A_KK^-1 ([mat][kPW][kPW], zero past kw), writes it to
+// A_KK, and copies the old panel columns into P ([mat][Wn][kPW], zero rows
+// in K and zero columns >= kw).  F = P A_KK^-1 = P (-dsw) is then a batched
+// GEMM, and panel_writeback_kernel stores A_RK = F, A_KR = F^H.
+//
+// Thread (w, j) = (tid / 64, tid % 64) holds entries (w + 16 u, j), u < 4,
+// of the 64 x 64 block in registers.  Sweeping pivot p needs row p and
+// column p as they were before it: their holders publish them to LDS (two
+// buffers by the parity of p, so one barrier per pivot suffices: a buffer
+// is rewritten two pivots later, after every thread has passed the barrier
+// that follows its last read).
 __global__ __launch_bounds__(1024) void sweep_panel_kernel(double2* a, double2* dsw, double2* pold,
                                                            int Wn, int k0, int kw, int* status,
                                                            long long mat0) {
-    __shared__ double2 D[kPW][kPW];
+    static_assert(kPW == 64 && kPW * kPW == 4 * 1024, "thread layout");
+    __shared__ double2 rowb[2][kPW], colb[2][kPW];
     const long long mat = blockIdx.x;
     double2* am = a + mat * Wn * Wn;
-    const int tid = threadIdx.x;
-    constexpr int EPT = kPW * kPW / 1024;   // entries of D per thread
-    // old panel columns (rows in K zero)
+    const int tid = threadIdx.x, w = tid >> 6, j = tid & 63;
+    // old panel columns (rows in K zero), rows q0 + w + 16 v: all four loads
+    // of a step issued before any store (reads outside use element 0)
     double2* pm = pold + mat * Wn * kPW;
-    for (int e = tid; e < Wn * kPW; e += 1024) {
-        const int i = e / kPW, t = e - i * kPW;
-        const bool inK = i >= k0 && i < k0 + kw;
-        pm[e] = (!inK && t < kw) ? am[(long long)i * Wn + k0 + t] : make_double2(0.0, 0.0);
+    for (int q0 = 0; q0 < Wn; q0 += 64) {
+        double2 v4[4];
+        bool ok[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = q0 + w + 16 * v;
+            ok[v] = i < Wn && !(i >= k0 && i < k0 + kw) && j < kw;
+            v4[v] = am[ok[v] ? (long long)i * Wn + k0 + j : 0];
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = q0 + w + 16 * v;
+            if (i < Wn) pm[(long long)i * kPW + j] = ok[v] ? v4[v] : make_double2(0.0, 0.0);
+        }
+    }
+    double2 r[4];
+    bool okd[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int i = w + 16 * u;
+        okd[u] = i < kw && j < kw;
+        r[u] = am[okd[u] ? (long long)(k0 + i) * Wn + k0 + j : 0];
     }
 #pragma unroll
-    for (int u = 0; u < EPT; ++u) {
-        const int e = tid + 1024 * u, i = e / kPW, j = e - i * kPW;
-        D[i][j] = (i < kw && j < kw) ? am[(long long)(k0 + i) * Wn + k0 + j] : make_double2(0.0, 0.0);
-    }
-    __syncthreads();
+    for (int u = 0; u < 4; ++u)
+        if (!okd[u]) r[u] = make_double2(0.0, 0.0);
     for (int p = 0; p < kw; ++p) {
-        const double d = D[p][p].x;
+        const int buf = p & 1, up = p >> 4;
+        if (w == (p & 15)) {   // row p is entry u = p / 16 of wave p % 16 (selected by value)
+            double2 rp = r[3];
+            if (up == 0) rp = r[0];
+            else if (up == 1) rp = r[1];
+            else if (up == 2) rp = r[2];
+            rowb[buf][j] = rp;
+        }
+        if (j == p) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) colb[buf][w + 16 * u] = r[u];
+        }
+        __syncthreads();
+        const double d = rowb[buf][p].x;
         if (!(d > 0.0) || !isfinite(d)) {   // the same d for every thread: uniform exit
             if (tid == 0 && atomicCAS(status, 0, LMMSE_ERR_NOT_PD) == 0)
                 status[1] = (int)(mat + mat0);
             return;
         }
         const double invd = 1.0 / d;
-        double2 r[EPT];
+        const double2 apj = rowb[buf][j];
 #pragma unroll
-        for (int u = 0; u < EPT; ++u) {
-            const int e = tid + 1024 * u, i = e / kPW, j = e - i * kPW;
-            const double2 v = D[i][j], aip = D[i][p], apj = D[p][j];
+        for (int u = 0; u < 4; ++u) {
+            const int i = w + 16 * u;
+            const double2 aip = colb[buf][i];
             if (i == p && j == p) {
                 r[u] = make_double2(-invd, 0.0);
             } else if (i == p) {
@@ -81,42 +116,50 @@ __global__ __launch_bounds__(1024) void sweep_panel_kernel(double2* a, double2* 
                 r[u] = make_double2(aip.x * invd, aip.y * invd);
             } else {
                 const double px = aip.x * apj.x - aip.y * apj.y, py = aip.x * apj.y + aip.y * apj.x;
-                r[u] = make_double2(v.x - px * invd, v.y - py * invd);
+                r[u] = make_double2(r[u].x - px * invd, r[u].y - py * invd);
             }
         }
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < EPT; ++u) {
-            const int e = tid + 1024 * u, i = e / kPW, j = e - i * kPW;
-            if (i < kw && j < kw) D[i][j] = r[u];
-        }
-        __syncthreads();
     }
     double2* dm = dsw + mat * kPW * kPW;
 #pragma unroll
-    for (int u = 0; u < EPT; ++u) {
-        const int e = tid + 1024 * u, i = e / kPW, j = e - i * kPW;
-        dm[e] = D[i][j];
-        if (i < kw && j < kw) am[(long long)(k0 + i) * Wn + k0 + j] = D[i][j];
+    for (int u = 0; u < 4; ++u) {
+        const int i = w + 16 * u;
+        dm[i * kPW + j] = r[u];
+        if (i < kw && j < kw) am[(long long)(k0 + i) * Wn + k0 + j] = r[u];
     }
 }
 
-// A_RK = F and A_KR = F^H for the rows outside the panel.
+// A_RK = F and A_KR = F^H for the rows outside the panel.  Rows of F are
+// taken 16 at a time through LDS and stored as rows of A_RK and,
+// transposed, as 16-element runs of the rows of A_KR.
 __global__ __launch_bounds__(256) void panel_writeback_kernel(double2* a, const double2* f, int Wn,
                                                               int k0, int kw) {
+    __shared__ double2 ft[kPW][17];
     const long long mat = blockIdx.x;
     double2* am = a + mat * Wn * Wn;
     const double2* fm = f + mat * Wn * kPW;
-    for (int e = threadIdx.x; e < Wn * kPW; e += 256) {   // row i, column t: rows of A_RK
-        const int i = e / kPW, t = e - i * kPW;
-        if (t < kw && !(i >= k0 && i < k0 + kw)) am[(long long)i * Wn + k0 + t] = fm[e];
-    }
-    for (int e = threadIdx.x; e < Wn * kPW; e += 256) {   // row k0 + t, column i: rows of A_KR
-        const int t = e / Wn, i = e - t * Wn;
-        if (t < kw && !(i >= k0 && i < k0 + kw)) {
-            const double2 v = fm[(long long)i * kPW + t];
-            am[(long long)(k0 + t) * Wn + i] = make_double2(v.x, -v.y);
+    const int tid = threadIdx.x, t = tid & 63, rw = tid >> 6;
+    for (int i0 = 0; i0 < Wn; i0 += 16) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {   // rows i0 + rw + 4 v, column t (rows past Wn read row 0)
+            const int i = i0 + rw + 4 * v;
+            ft[t][rw + 4 * v] = fm[(long long)(i < Wn ? i : 0) * kPW + t];
         }
+        __syncthreads();
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {   // row i of A_RK
+            const int i = i0 + rw + 4 * v;
+            if (i < Wn && t < kw && !(i >= k0 && i < k0 + kw)) am[(long long)i * Wn + k0 + t] = ft[t][rw + 4 * v];
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {   // row k0 + tt of A_KR, columns i0 + c
+            const int e = tid + 256 * v, tt = e >> 4, c = e & 15, i = i0 + c;
+            if (tt < kw && i < Wn && !(i >= k0 && i < k0 + kw)) {
+                const double2 x = ft[tt][c];
+                am[(long long)(k0 + tt) * Wn + i] = make_double2(x.x, -x.y);
+            }
+        }
+        __syncthreads();
     }
 }
 

@@ -54,12 +54,6 @@ struct Cx<float> {
     __device__ static T make(double x, double y) { return make_float2((float)x, (float)y); }
 };
 
-template <typename R, typename T>
-__device__ __forceinline__ typename Cx<R>::T zload(const void* p, long long i, int conj) {
-    const T v = reinterpret_cast<const T*>(p)[i];
-    return Cx<R>::make((double)v.x, conj ? -(double)v.y : (double)v.y);
-}
-
 // The product on the matrix cores: a workgroup computes one 64 x 64 output
 // tile, staging 16-term chunks of A and B through LDS (the next chunk's loads
 // in flight during the current chunk's MFMAs); each wave owns a 32 x 32
@@ -89,8 +83,10 @@ struct ZMma<float> {
     __device__ static int row(int v, int lk) { return 4 * lk + v; }
 };
 
+// Bounded to three waves per SIMD (at most 168 registers per lane): two
+// waves per SIMD leave the matrix cores idle while a workgroup stages.
 template <typename TA, typename TB, typename TC, typename R>
-__global__ __launch_bounds__(256) void zgemm_mfma_kernel(ZGemmArgs g) {
+__global__ __launch_bounds__(256, 3) void zgemm_mfma_kernel(ZGemmArgs g) {
     using CT = typename Cx<R>::T;
     using ZM = ZMma<R>;
     __shared__ CT As[zKC][zT];
@@ -138,19 +134,25 @@ __global__ __launch_bounds__(256) void zgemm_mfma_kernel(ZGemmArgs g) {
             live[i][j] = r0 + ri < g.m && c0 + cj < g.n && !(g.herm && tm == tn && ri < cj);
         }
 
-    CT pa[4], pb[4];
+    // Every thread issues all eight loads of a chunk unconditionally (an
+    // element outside the operand reads the batch's element (0, 0) instead
+    // and is zeroed after the load): loads under a branch would each be
+    // waited for before the next is issued.
+    TA ra[4];
+    TB rb[4];
+    bool oka[4], okb[4];
     auto fetch = [&](int k0) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int e = tid + 256 * u;
             const int r = a_rowfast ? (e & 63) : (e >> 4), ka = a_rowfast ? (e >> 6) : (e & 15);
             const int c = b_colfast ? (e & 63) : (e >> 4), kb = b_colfast ? (e >> 6) : (e & 15);
-            pa[u] = (r0 + r < g.m && k0 + ka < g.kd)
-                        ? zload<R, TA>(g.A.p, abase + (r0 + r) * g.A.rs + (k0 + ka) * g.A.cs, g.A.conj)
-                        : Cx<R>::make(0.0, 0.0);
-            pb[u] = (c0 + c < g.n && k0 + kb < g.kd)
-                        ? zload<R, TB>(g.B.p, bbase + (k0 + kb) * g.B.rs + (c0 + c) * g.B.cs, g.B.conj)
-                        : Cx<R>::make(0.0, 0.0);
+            oka[u] = r0 + r < g.m && k0 + ka < g.kd;
+            okb[u] = c0 + c < g.n && k0 + kb < g.kd;
+            ra[u] = reinterpret_cast<const TA*>(g.A.p)[oka[u] ? abase + (r0 + r) * g.A.rs + (k0 + ka) * g.A.cs
+                                                               : abase];
+            rb[u] = reinterpret_cast<const TB*>(g.B.p)[okb[u] ? bbase + (k0 + kb) * g.B.rs + (c0 + c) * g.B.cs
+                                                               : bbase];
         }
     };
     fetch(0);
@@ -160,8 +162,10 @@ __global__ __launch_bounds__(256) void zgemm_mfma_kernel(ZGemmArgs g) {
             const int e = tid + 256 * u;
             const int r = a_rowfast ? (e & 63) : (e >> 4), ka = a_rowfast ? (e >> 6) : (e & 15);
             const int c = b_colfast ? (e & 63) : (e >> 4), kb = b_colfast ? (e >> 6) : (e & 15);
-            As[ka][r] = pa[u];
-            Bs[kb][c] = pb[u];
+            As[ka][r] = oka[u] ? Cx<R>::make((double)ra[u].x, g.A.conj ? -(double)ra[u].y : (double)ra[u].y)
+                               : Cx<R>::make(0.0, 0.0);
+            Bs[kb][c] = okb[u] ? Cx<R>::make((double)rb[u].x, g.B.conj ? -(double)rb[u].y : (double)rb[u].y)
+                               : Cx<R>::make(0.0, 0.0);
         }
         __syncthreads();
         if (k0 + zKC < g.kd) fetch(k0 + zKC);
@@ -187,8 +191,24 @@ __global__ __launch_bounds__(256) void zgemm_mfma_kernel(ZGemmArgs g) {
         __syncthreads();
     }
     TC* cp = reinterpret_cast<TC*>(const_cast<void*>(g.C.p));
+    // When accumulating, the old values of C of a row of sub-tiles are read
+    // before its first store (unconditional reads, element (0, 0) standing in
+    // for those outside), so that the reads are in flight together.  Only
+    // elements this thread writes itself are read: the mirrored ones are
+    // never read.
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 2; ++i) {
+        TC old[2][4];
+        if (g.beta) {
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = r0 + wr + 16 * i + ZM::row(v, lk), c = c0 + wc + 16 * j + li;
+                    const bool ok = live[i][j] && r < g.m && c < g.n;
+                    old[j][v] = cp[ok ? cbase + r * g.C.rs + c * g.C.cs : cbase];
+                }
+        }
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
@@ -201,8 +221,8 @@ __global__ __launch_bounds__(256) void zgemm_mfma_kernel(ZGemmArgs g) {
                 const long long o = cbase + r * g.C.rs + c * g.C.cs;
                 double x = g.alpha * cre[i][j][v], y = g.alpha * cim[i][j][v];
                 if (g.beta) {
-                    x += (double)cp[o].x;
-                    y += (double)cp[o].y;
+                    x += (double)old[j][v].x;
+                    y += (double)old[j][v].y;
                 }
                 if constexpr (sizeof(TC) == sizeof(double2))
                     cp[o] = make_double2(x, y);
@@ -216,6 +236,7 @@ __global__ __launch_bounds__(256) void zgemm_mfma_kernel(ZGemmArgs g) {
                         cp[om] = make_float2((float)x, (float)-y);
                 }
             }
+    }
 }
 
 template <typename TA, typename TB, typename TC, typename R = double>
@@ -223,6 +244,8 @@ inline hipError_t zgemm(ZGemmArgs g, long long nbat, hipStream_t st) {
     g.tiles_m = (g.m + zT - 1) / zT;
     g.tiles_n = (g.n + zT - 1) / zT;
     if (g.herm && g.m != g.n) return hipErrorInvalidValue;
+    // the kernel reads element (0, 0) of every batch's A and B
+    if (g.kd < 1) return hipErrorInvalidValue;
     const long long blocks =
         nbat * (g.herm ? (long long)g.tiles_m * (g.tiles_m + 1) / 2 : (long long)g.tiles_m * g.tiles_n);
     if (blocks == 0) return hipSuccess;
