@@ -23,14 +23,18 @@ __global__ __launch_bounds__(256) void despread_kernel(const float2* __restrict_
     int n = (int)(gid - a * N);
     if (a >= n_ant) return;
     const float2* yp = y + a * (long long)K * N + n;
-    float2 v[K], z[K];
+    // the pilots are loaded with the symbols, so that all 2K loads are in
+    // flight together
+    float2 v[K], z[K], x[K];
 #pragma unroll
     for (int t = 0; t < K; ++t) v[t] = yp[(long long)t * N];
+#pragma unroll
+    for (int k = 0; k < K; ++k) x[k] = pilots[(long long)k * N + n];
     Dft<K>::run(v, z, tw);
     float2* hp = h + a * (long long)K * N + n;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        float2 r = cmulc(z[k], pilots[(long long)k * N + n]);
+        float2 r = cmulc(z[k], x[k]);
         hp[(long long)k * N] = make_float2(r.x * invK, r.y * invK);
     }
 }
