@@ -315,8 +315,8 @@ def detect_line(dev, stream, steps=20, warmup=3):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this estimator shards over slots with no "
-              "communication, so runs on more than one GPU are not part of this build",
+        print("bench.py measures one GPU only: the estimator shards over slots with no "
+              "communication, and the multi-GPU form is not implemented",
               file=sys.stderr)
         sys.exit(2)
 
