@@ -14,8 +14,8 @@
 //      the 64 x 64 diagonal block and copies the old panel columns P;
 //      F = A_RK A_KK^-1 = P A_KK^-1 and the update of A_RR, A += (-1) F P^H,
 //      are batched GEMMs (rows of K zero in F and P, so the K rows and
-//      columns are left alone), and a small kernel writes A_RK = F,
-//      A_KR = F^H.  After all panels A holds -A^-1;
+//      columns are left alone); the first stores A_RK = F and A_KR = F^H in
+//      place.  After all panels A holds -A^-1;
 //   4. W = (I - lam A^-1)[off rows] (FP64 and compact FP32 copies) and,
 //      when asked for, A^-1 itself.
 #include <algorithm>
@@ -26,6 +26,7 @@
 namespace lmmse {
 
 constexpr int kPW = kSweepPanel;
+static_assert(kPW == zT, "a panel is one GEMM tile row");
 
 // A = R + lam I on the diagonal of every window.
 __global__ __launch_bounds__(256) void add_diag_kernel(double2* a, int Wn, double lam) {
@@ -37,7 +38,7 @@ __global__ __launch_bounds__(256) void add_diag_kernel(double2* a, int Wn, doubl
 // A_KK into dsw = -A_KK^-1 ([mat][kPW][kPW], zero past kw), writes it to
 // A_KK, and copies the old panel columns into P ([mat][Wn][kPW], zero rows
 // in K and zero columns >= kw).  F = P A_KK^-1 = P (-dsw) is then a batched
-// GEMM, and panel_writeback_kernel stores A_RK = F, A_KR = F^H.
+// GEMM that stores A_RK = F and A_KR = F^H.
 //
 // Thread (w, j) = (tid / 64, tid % 64) holds entries (w + 16 u, j), u < 4,
 // of the 64 x 64 block in registers.  Sweeping pivot p needs row p and
@@ -129,40 +130,6 @@ __global__ __launch_bounds__(1024) void sweep_panel_kernel(double2* a, double2* 
     }
 }
 
-// A_RK = F and A_KR = F^H for the rows outside the panel.  Rows of F are
-// taken 16 at a time through LDS and stored as rows of A_RK and,
-// transposed, as 16-element runs of the rows of A_KR.
-__global__ __launch_bounds__(256) void panel_writeback_kernel(double2* a, const double2* f, int Wn,
-                                                              int k0, int kw) {
-    __shared__ double2 ft[kPW][17];
-    const long long mat = blockIdx.x;
-    double2* am = a + mat * Wn * Wn;
-    const double2* fm = f + mat * Wn * kPW;
-    const int tid = threadIdx.x, t = tid & 63, rw = tid >> 6;
-    for (int i0 = 0; i0 < Wn; i0 += 16) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {   // rows i0 + rw + 4 v, column t (rows past Wn read row 0)
-            const int i = i0 + rw + 4 * v;
-            ft[t][rw + 4 * v] = fm[(long long)(i < Wn ? i : 0) * kPW + t];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {   // row i of A_RK
-            const int i = i0 + rw + 4 * v;
-            if (i < Wn && t < kw && !(i >= k0 && i < k0 + kw)) am[(long long)i * Wn + k0 + t] = ft[t][rw + 4 * v];
-        }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {   // row k0 + tt of A_KR, columns i0 + c
-            const int e = tid + 256 * v, tt = e >> 4, c = e & 15, i = i0 + c;
-            if (tt < kw && i < Wn && !(i >= k0 && i < k0 + kw)) {
-                const double2 x = ft[tt][c];
-                am[(long long)(k0 + tt) * Wn + i] = make_double2(x.x, -x.y);
-            }
-        }
-        __syncthreads();
-    }
-}
-
 // W[o][j] = delta(off + o, j) + lam S[off + o][j] with S = -A^-1 as the sweep
 // leaves it; optionally A^-1 = -S in place.
 __global__ __launch_bounds__(256) void large_filters_kernel(double2* a, const int* offsets, int B,
@@ -195,7 +162,7 @@ __global__ __launch_bounds__(256) void large_filters_kernel(double2* a, const in
 }
 
 size_t sweep_scratch_bytes(int Wn, long long nmat) {
-    return (size_t)nmat * (2 * (size_t)Wn * kPW + (size_t)kPW * kPW) * sizeof(double2);
+    return (size_t)nmat * ((size_t)Wn * kPW + (size_t)kPW * kPW) * sizeof(double2);
 }
 
 size_t large_design_bytes(const lmmse_plan_desc& d, long long nmat) {
@@ -230,9 +197,8 @@ hipError_t launch_sample_large(const Plan& p, long long nmat, long long mat0, co
     ga.herm = 0;
     hipLaunchKernelGGL(add_diag_kernel, dim3((unsigned)nmat), dim3(256), 0, st, amat, Wn, lam);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    // scratch: F and P [nmat][Wn][kPW], then -A_KK^-1 [nmat][kPW][kPW]
-    double2* f = scratch;
-    double2* pold = f + nmat * Wn * kPW;
+    // scratch: P [nmat][Wn][kPW], then -A_KK^-1 [nmat][kPW][kPW]
+    double2* pold = scratch;
     double2* dsw = pold + nmat * Wn * kPW;
     const long long pp = (long long)Wn * kPW, dd = (long long)kPW * kPW;
     for (int k0 = 0; k0 < Wn; k0 += kPW) {
@@ -240,22 +206,27 @@ hipError_t launch_sample_large(const Plan& p, long long nmat, long long mat0, co
         hipLaunchKernelGGL(sweep_panel_kernel, dim3((unsigned)nmat), dim3(1024), 0, st, amat, dsw,
                            pold, Wn, k0, kw, p.status, mat0);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        // F = P A_KK^-1 = -P dsw (rows of K vanish with P's)
+        // F = P A_KK^-1 = -P dsw, stored in place as A_RK = F (the panel's
+        // columns) and A_KR = F^H (its rows).  Rows of K vanish with P's: the
+        // panel's tile row is left out, which keeps A_KK as the sweep wrote it.
+        ga.skip_tile = k0 / kPW;
         ga.A = ZView{pold, kPW, 1, pp * p.nb * d.K, pp * p.nb, pp, nullptr, 0};
         ga.B = ZView{dsw, kPW, 1, dd * p.nb * d.K, dd * p.nb, dd, nullptr, 0};
-        ga.C = ZView{f, kPW, 1, pp * p.nb * d.K, pp * p.nb, pp, nullptr, 0};
+        ga.C = ZView{amat + k0, Wn, 1, per * p.nb * d.K, per * p.nb, per, nullptr, 0};
+        ga.T = ZView{amat + (long long)k0 * Wn, Wn, 1, per * p.nb * d.K, per * p.nb, per, nullptr, 0};
+        ga.tcopy = 1;
         ga.m = Wn;
-        ga.n = kPW;
+        ga.n = kw;
         ga.kd = kw;
         ga.alpha = -1.0;
         ga.beta = 0;
         ga.herm = 0;
         if ((e = zgemm<double2, double2, double2>(ga, nmat, st)) != hipSuccess) return e;
-        hipLaunchKernelGGL(panel_writeback_kernel, dim3((unsigned)nmat), dim3(256), 0, st, amat, f,
-                           Wn, k0, kw);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        // A += (-1) F P^H over the whole window (F, P vanish on the panel's rows)
-        ga.A = ZView{f, kPW, 1, pp * p.nb * d.K, pp * p.nb, pp, nullptr, 0};
+        ga.tcopy = 0;
+        // A += (-1) F P^H over the window but the panel's tile row and column,
+        // where F P^H vanishes (F and P are zero on the panel's rows); F is
+        // read from the panel's columns, which this product does not write
+        ga.A = ZView{amat + k0, Wn, 1, per * p.nb * d.K, per * p.nb, per, nullptr, 0};
         ga.B = ZView{pold, 1, kPW, pp * p.nb * d.K, pp * p.nb, pp, nullptr, 1};
         ga.C = ZView{amat, Wn, 1, per * p.nb * d.K, per * p.nb, per, nullptr, 0};
         ga.m = Wn;
@@ -265,6 +236,7 @@ hipError_t launch_sample_large(const Plan& p, long long nmat, long long mat0, co
         ga.beta = 1;
         ga.herm = 1;   // F P^H = A_RK A_KK^-1 A_RK^H is Hermitian
         if ((e = zgemm<double2, double2, double2>(ga, nmat, st)) != hipSuccess) return e;
+        ga.skip_tile = -1;
     }
     hipLaunchKernelGGL(large_filters_kernel, dim3((unsigned)nmat), dim3(256), 0, st, amat,
                        p.d_offsets, d.B, Wn, p.nb, lam, w64, w32, whi, wlo,

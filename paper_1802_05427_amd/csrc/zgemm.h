@@ -27,6 +27,11 @@ struct ZGemmArgs {
     int beta;
     int herm;            // C and the update Hermitian (square): compute the lower
                          // tiles, mirror them
+    int skip_tile = -1;  // when >= 0: the 64-row tile row of that index (and, for a
+                         // Hermitian product, the tile column) is left out: the
+                         // caller knows the product vanishes there or is not read
+    ZView T;             // when tcopy is set (not with herm), element (r, c) of the
+    int tcopy;           // result is also written conjugated at T's element (c, r)
 };
 
 constexpr int zT = 64;    // output tile edge
@@ -110,6 +115,10 @@ __global__ __launch_bounds__(256, 3) void zgemm_mfma_kernel(ZGemmArgs g) {
         t /= g.tiles_n;
         tm = (int)(t % g.tiles_m);
         bat = t / g.tiles_m;
+    }
+    if (g.skip_tile >= 0) {   // tiles_m (and, Hermitian, the square) count the others
+        tm += tm >= g.skip_tile ? 1 : 0;
+        if (g.herm) tn += tn >= g.skip_tile ? 1 : 0;
     }
     const int r0 = tm * zT, c0 = tn * zT;
     const long long abase = zbase(g.A, bat, g.K, g.nb);
@@ -228,6 +237,14 @@ __global__ __launch_bounds__(256, 3) void zgemm_mfma_kernel(ZGemmArgs g) {
                     cp[o] = make_double2(x, y);
                 else
                     cp[o] = make_float2((float)x, (float)y);
+                if (g.tcopy) {
+                    const long long ot = zbase(g.T, bat, g.K, g.nb) + c * g.T.rs + r * g.T.cs;
+                    TC* tp = reinterpret_cast<TC*>(const_cast<void*>(g.T.p));
+                    if constexpr (sizeof(TC) == sizeof(double2))
+                        tp[ot] = make_double2(x, -y);
+                    else
+                        tp[ot] = make_float2((float)x, (float)-y);
+                }
                 if (mirror) {
                     const long long om = cbase + c * g.C.rs + r * g.C.cs;
                     if constexpr (sizeof(TC) == sizeof(double2))
@@ -243,7 +260,9 @@ template <typename TA, typename TB, typename TC, typename R = double>
 inline hipError_t zgemm(ZGemmArgs g, long long nbat, hipStream_t st) {
     g.tiles_m = (g.m + zT - 1) / zT;
     g.tiles_n = (g.n + zT - 1) / zT;
-    if (g.herm && g.m != g.n) return hipErrorInvalidValue;
+    if (g.herm && (g.m != g.n || g.tcopy)) return hipErrorInvalidValue;
+    if (g.skip_tile >= g.tiles_m) return hipErrorInvalidValue;
+    if (g.skip_tile >= 0) --g.tiles_m;   // the kernel maps the remaining tile rows past it
     // the kernel reads element (0, 0) of every batch's A and B
     if (g.kd < 1) return hipErrorInvalidValue;
     const long long blocks =
