@@ -53,7 +53,7 @@ __global__ __launch_bounds__(1024) void sweep_panel_kernel(double2* a, double2* 
     __shared__ double2 rowb[2][kPW], colb[2][kPW];
     const long long mat = blockIdx.x;
     double2* am = a + mat * Wn * Wn;
-    const int tid = threadIdx.x, w = tid >> 6, j = tid & 63;
+    const int tid = threadIdx.x, w = __builtin_amdgcn_readfirstlane(tid >> 6), j = tid & 63;
     // old panel columns (rows in K zero), rows q0 + w + 16 v: all four loads
     // of a step issued before any store (reads outside use element 0)
     double2* pm = pold + mat * Wn * kPW;
@@ -105,19 +105,18 @@ __global__ __launch_bounds__(1024) void sweep_panel_kernel(double2* a, double2* 
         }
         const double invd = 1.0 / d;
         const double2 apj = rowb[buf][j];
+        const double2 q = make_double2(apj.x * invd, apj.y * invd);   // row p of the result
+        const bool jp = j == p;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int i = w + 16 * u;
+            const int i = w + 16 * u;   // wave-uniform
             const double2 aip = colb[buf][i];
-            if (i == p && j == p) {
-                r[u] = make_double2(-invd, 0.0);
-            } else if (i == p) {
-                r[u] = make_double2(apj.x * invd, apj.y * invd);
-            } else if (j == p) {
-                r[u] = make_double2(aip.x * invd, aip.y * invd);
-            } else {
-                const double px = aip.x * apj.x - aip.y * apj.y, py = aip.x * apj.y + aip.y * apj.x;
-                r[u] = make_double2(r[u].x - px * invd, r[u].y - py * invd);
+            if (i == p) {
+                r[u] = jp ? make_double2(-invd, 0.0) : q;
+            } else {   // a_ij - a_ip a_pj / d, and a_ip / d in the pivot column
+                const double gx = fma(-aip.x, q.x, fma(aip.y, q.y, r[u].x));
+                const double gy = fma(-aip.x, q.y, fma(-aip.y, q.x, r[u].y));
+                r[u] = jp ? make_double2(aip.x * invd, aip.y * invd) : make_double2(gx, gy);
             }
         }
     }
