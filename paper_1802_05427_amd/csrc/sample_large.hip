@@ -40,61 +40,64 @@ __global__ __launch_bounds__(256) void add_diag_kernel(double2* a, int Wn, doubl
 // in K and zero columns >= kw).  F = P A_KK^-1 = P (-dsw) is then a batched
 // GEMM that stores A_RK = F and A_KR = F^H.
 //
-// Thread (w, j) = (tid / 64, tid % 64) holds entries (w + 16 u, j), u < 4,
-// of the 64 x 64 block in registers.  Sweeping pivot p needs row p and
-// column p as they were before it: their holders publish them to LDS (two
-// buffers by the parity of p, so one barrier per pivot suffices: a buffer
-// is rewritten two pivots later, after every thread has passed the barrier
-// that follows its last read).
-__global__ __launch_bounds__(1024) void sweep_panel_kernel(double2* a, double2* dsw, double2* pold,
+// Thread (w, j) = (tid / 64, tid % 64) of a workgroup of kSwW waves holds
+// entries (w + kSwW u, j), u < kSwE, of the 64 x 64 block in registers.
+// Sweeping pivot p needs row p and column p as they were before it: their
+// holders publish them to LDS (two buffers by the parity of p, so one barrier
+// per pivot suffices: a buffer is rewritten two pivots later, after every
+// thread has passed the barrier that follows its last read).
+constexpr int kSwT = 512;            // threads per window
+constexpr int kSwW = kSwT / 64;      // waves
+constexpr int kSwE = 64 / kSwW;      // block rows (entries) per thread
+__global__ __launch_bounds__(kSwT) void sweep_panel_kernel(double2* a, double2* dsw, double2* pold,
                                                            int Wn, int k0, int kw, int* status,
                                                            long long mat0) {
-    static_assert(kPW == 64 && kPW * kPW == 4 * 1024, "thread layout");
+    static_assert(kPW == 64 && kSwW * kSwE == 64, "thread layout");
     __shared__ double2 rowb[2][kPW], colb[2][kPW];
     const long long mat = blockIdx.x;
     double2* am = a + mat * Wn * Wn;
     const int tid = threadIdx.x, w = __builtin_amdgcn_readfirstlane(tid >> 6), j = tid & 63;
-    // old panel columns (rows in K zero), rows q0 + w + 16 v: all four loads
-    // of a step issued before any store (reads outside use element 0)
+    // old panel columns (rows in K zero), rows q0 + w + kSwW v: all loads of
+    // a step issued before any store (reads outside use element 0)
     double2* pm = pold + mat * Wn * kPW;
     for (int q0 = 0; q0 < Wn; q0 += 64) {
-        double2 v4[4];
-        bool ok[4];
+        double2 v4[kSwE];
+        bool ok[kSwE];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int i = q0 + w + 16 * v;
+        for (int v = 0; v < kSwE; ++v) {
+            const int i = q0 + w + kSwW * v;
             ok[v] = i < Wn && !(i >= k0 && i < k0 + kw) && j < kw;
             v4[v] = am[ok[v] ? (long long)i * Wn + k0 + j : 0];
         }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int i = q0 + w + 16 * v;
+        for (int v = 0; v < kSwE; ++v) {
+            const int i = q0 + w + kSwW * v;
             if (i < Wn) pm[(long long)i * kPW + j] = ok[v] ? v4[v] : make_double2(0.0, 0.0);
         }
     }
-    double2 r[4];
-    bool okd[4];
+    double2 r[kSwE];
+    bool okd[kSwE];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int i = w + 16 * u;
+    for (int u = 0; u < kSwE; ++u) {
+        const int i = w + kSwW * u;
         okd[u] = i < kw && j < kw;
         r[u] = am[okd[u] ? (long long)(k0 + i) * Wn + k0 + j : 0];
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < kSwE; ++u)
         if (!okd[u]) r[u] = make_double2(0.0, 0.0);
     for (int p = 0; p < kw; ++p) {
-        const int buf = p & 1, up = p >> 4;
-        if (w == (p & 15)) {   // row p is entry u = p / 16 of wave p % 16 (selected by value)
-            double2 rp = r[3];
-            if (up == 0) rp = r[0];
-            else if (up == 1) rp = r[1];
-            else if (up == 2) rp = r[2];
+        const int buf = p & 1, up = p / kSwW;
+        if (w == p % kSwW) {   // row p is entry up of wave p % kSwW (selected by value)
+            double2 rp = r[0];
+#pragma unroll
+            for (int u = 1; u < kSwE; ++u)
+                if (up == u) rp = r[u];
             rowb[buf][j] = rp;
         }
         if (j == p) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) colb[buf][w + 16 * u] = r[u];
+            for (int u = 0; u < kSwE; ++u) colb[buf][w + kSwW * u] = r[u];
         }
         __syncthreads();
         const double d = rowb[buf][p].x;
@@ -108,8 +111,8 @@ __global__ __launch_bounds__(1024) void sweep_panel_kernel(double2* a, double2* 
         const double2 q = make_double2(apj.x * invd, apj.y * invd);   // row p of the result
         const bool jp = j == p;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int i = w + 16 * u;   // wave-uniform
+        for (int u = 0; u < kSwE; ++u) {
+            const int i = w + kSwW * u;   // wave-uniform
             const double2 aip = colb[buf][i];
             if (i == p) {
                 r[u] = jp ? make_double2(-invd, 0.0) : q;
@@ -122,8 +125,8 @@ __global__ __launch_bounds__(1024) void sweep_panel_kernel(double2* a, double2* 
     }
     double2* dm = dsw + mat * kPW * kPW;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int i = w + 16 * u;
+    for (int u = 0; u < kSwE; ++u) {
+        const int i = w + kSwW * u;
         dm[i * kPW + j] = r[u];
         if (i < kw && j < kw) am[(long long)(k0 + i) * Wn + k0 + j] = r[u];
     }
@@ -202,7 +205,7 @@ hipError_t launch_sample_large(const Plan& p, long long nmat, long long mat0, co
     const long long pp = (long long)Wn * kPW, dd = (long long)kPW * kPW;
     for (int k0 = 0; k0 < Wn; k0 += kPW) {
         const int kw = std::min(kPW, Wn - k0);
-        hipLaunchKernelGGL(sweep_panel_kernel, dim3((unsigned)nmat), dim3(1024), 0, st, amat, dsw,
+        hipLaunchKernelGGL(sweep_panel_kernel, dim3((unsigned)nmat), dim3(kSwT), 0, st, amat, dsw,
                            pold, Wn, k0, kw, p.status, mat0);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         // F = P A_KK^-1 = -P dsw, stored in place as A_RK = F (the panel's
