@@ -126,7 +126,12 @@ __global__ __launch_bounds__(256, 3) void zgemm_mfma_kernel(ZGemmArgs g) {
     const long long cbase = zbase(g.C, bat, g.K, g.nb);
     const bool a_rowfast = g.A.rs == 1, b_colfast = g.B.cs == 1;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32, li = lane & 15, lk = lane >> 4;
+    // A tile whose rows end within its first 16 has one live row of
+    // sub-tiles: wave w takes sub-tile (0, w) there, not a 2 x 2 block, so
+    // that all four waves share the work.
+    const bool ragged = r0 + 16 >= g.m;
+    const int wr = ragged ? 0 : (wave >> 1) * 32, wc = ragged ? (wave >> 1) * 32 : (wave & 1) * 32;
+    const int li = lane & 15, lk = lane >> 4;
 
     typename ZM::V cre[2][2], cim[2][2];
     // 16 x 16 sub-tiles this wave computes (wave-uniform): those with rows and
@@ -140,7 +145,8 @@ __global__ __launch_bounds__(256, 3) void zgemm_mfma_kernel(ZGemmArgs g) {
             cre[i][j] = typename ZM::V{0, 0, 0, 0};
             cim[i][j] = typename ZM::V{0, 0, 0, 0};
             const int ri = wr + 16 * i, cj = wc + 16 * j;
-            live[i][j] = r0 + ri < g.m && c0 + cj < g.n && !(g.herm && tm == tn && ri < cj);
+            live[i][j] = r0 + ri < g.m && c0 + cj < g.n && !(g.herm && tm == tn && ri < cj) &&
+                         (!ragged || (i == 0 && j == (wave & 1)));
         }
 
     // Every thread issues all eight loads of a chunk unconditionally (an
