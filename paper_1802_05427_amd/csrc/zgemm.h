@@ -128,9 +128,12 @@ __global__ __launch_bounds__(256, 3) void zgemm_mfma_kernel(ZGemmArgs g) {
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     // A tile whose rows end within its first 16 has one live row of
     // sub-tiles: wave w takes sub-tile (0, w) there, not a 2 x 2 block, so
-    // that all four waves share the work.
+    // that all four waves share the work; likewise sub-tile (w, 0) of a tile
+    // whose columns end within its first 16.
     const bool ragged = r0 + 16 >= g.m;
-    const int wr = ragged ? 0 : (wave >> 1) * 32, wc = ragged ? (wave >> 1) * 32 : (wave & 1) * 32;
+    const bool cragged = !ragged && c0 + 16 >= g.n;
+    const int wr = ragged ? 0 : (wave >> 1) * 32;
+    const int wc = ragged ? (wave >> 1) * 32 : cragged ? 0 : (wave & 1) * 32;
     const int li = lane & 15, lk = lane >> 4;
 
     typename ZM::V cre[2][2], cim[2][2];
@@ -146,7 +149,8 @@ __global__ __launch_bounds__(256, 3) void zgemm_mfma_kernel(ZGemmArgs g) {
             cim[i][j] = typename ZM::V{0, 0, 0, 0};
             const int ri = wr + 16 * i, cj = wc + 16 * j;
             live[i][j] = r0 + ri < g.m && c0 + cj < g.n && !(g.herm && tm == tn && ri < cj) &&
-                         (!ragged || (i == 0 && j == (wave & 1)));
+                         (!ragged || (i == 0 && j == (wave & 1))) &&
+                         (!cragged || (j == 0 && i == (wave & 1)));
         }
 
     // Every thread issues all eight loads of a chunk unconditionally (an
