@@ -345,7 +345,7 @@ void transposed_row_tiles(int out_len, int& RT, int& rgroups) {
 
 hipError_t launch_apply_f32_transposed(const Plan& p, int slots, const float4* bank, int RT,
                                        int rgroups, int pass, int P, const float2* g, float2* dx,
-                                       hipStream_t st) {
+                                       int accumulate, hipStream_t st) {
     ApplyArgs a;
     a.wbank = bank;
     a.starts = p.d_bstarts;
@@ -364,7 +364,7 @@ hipError_t launch_apply_f32_transposed(const Plan& p, int slots, const float4* b
     a.pass = pass;
     a.P = P;
     a.rgroups = rgroups;
-    a.accumulate = 1;
+    a.accumulate = accumulate;
     a.invK = 1.0f;
     a.vec_store = 0;
     const long long ctiles = (a.ncols + kCols - 1) / kCols;

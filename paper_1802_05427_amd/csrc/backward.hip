@@ -13,8 +13,9 @@
 // dX: the FP32 filtering kernel of the forward pass with transposed roles
 // (apply_f32.hip): contraction over the B outputs of each block, Wn output
 // rows, the real embedding of W^H as its bank.  Windows of neighbouring
-// blocks overlap, so dX is zeroed and the blocks are processed in passes whose
-// windows are disjoint (block b in pass b mod P), each adding its
+// blocks overlap, so the blocks are processed in passes whose windows are
+// disjoint (block b in pass b mod P): the first pass stores its windows, the
+// subcarriers none of them covers are zeroed, and each later pass adds its
 // contribution with a read-add-write: deterministic, no atomics.
 //
 // dW: split over column chunks.  A workgroup takes one block, one row group of
@@ -123,6 +124,26 @@ __global__ void pack_wh_kernel(const double2* __restrict__ w64, float4* __restri
 __global__ void fill_zero_kernel(float2* p, long long n) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = make_float2(0.f, 0.f);
+}
+
+// Subcarrier runs [lo, lo + len) that no window of the first dX pass covers;
+// off[i] = total length of runs before run i.
+constexpr int kMaxGapRuns = 64;
+struct GapRuns {
+    int lo[kMaxGapRuns], off[kMaxGapRuns + 1];
+    int n;
+};
+
+// dX = 0 on the runs of every column (one thread per zeroed element).
+__global__ void fill_gaps_kernel(float2* dx, long long ncols, int N, GapRuns gr) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int tot = gr.off[gr.n];
+    if (e >= ncols * tot) return;
+    const long long col = e / tot;
+    const int k = (int)(e - col * tot);
+    int i = 0;
+    while (i + 1 < gr.n && gr.off[i + 1] <= k) ++i;
+    dx[col * N + gr.lo[i] + (k - gr.off[i])] = make_float2(0.f, 0.f);
 }
 
 // ---------------------------------------------------------------- dW partials
@@ -442,14 +463,39 @@ hipError_t launch_backward_fixed(Plan& p, int slots, const float2* hls, const fl
         hipLaunchKernelGGL(pack_wh_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
                            p.w64, bank, p.n_classes, B, Wn, 2 * geo.G16b, geo.RT, geo.rgroups);
     }
-    // dX = 0, then one pass per window colour
+    // One pass per window colour.  The first pass stores its windows; the
+    // subcarriers none of them covers are zeroed before the later passes add
+    // theirs (the whole of dX when there are too many such runs, and then
+    // every pass adds).
+    GapRuns gr{};
     {
+        std::vector<char> cov(N, 0);
+        for (int b = 0; b < p.nb; b += geo.P)
+            for (int j = 0; j < Wn; ++j) cov[p.h_starts[b] + j] = 1;
+        for (int n0 = 0; n0 < N && gr.n <= kMaxGapRuns; ++n0) {
+            if (cov[n0] || (n0 > 0 && !cov[n0 - 1])) continue;
+            int n1 = n0;
+            while (n1 < N && !cov[n1]) ++n1;
+            if (gr.n < kMaxGapRuns) {
+                gr.lo[gr.n] = n0;
+                gr.off[gr.n + 1] = gr.off[gr.n] + (n1 - n0);
+            }
+            ++gr.n;
+        }
+    }
+    const bool store_first = gr.n <= kMaxGapRuns;
+    if (!store_first) {
         const long long n = ncols * N;
         hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, dhls, n);
+    } else if (gr.n > 0) {
+        const long long n = ncols * gr.off[gr.n];
+        hipLaunchKernelGGL(fill_gaps_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, dhls,
+                           ncols, N, gr);
     }
     for (int pass = 0; pass < geo.P; ++pass) {
         const hipError_t e = launch_apply_f32_transposed(p, slots, bank, geo.RT, geo.rgroups, pass,
-                                                         geo.P, g, dhls, st);
+                                                         geo.P, g, dhls,
+                                                         (pass == 0 && store_first) ? 0 : 1, st);
         if (e != hipSuccess) return e;
     }
     hipError_t e = hipGetLastError();

@@ -75,7 +75,7 @@ bool apply_fusable(const Plan& p);
 void transposed_row_tiles(int out_len, int& RT, int& rgroups);
 hipError_t launch_apply_f32_transposed(const Plan& p, int slots, const float4* bank, int RT,
                                        int rgroups, int pass, int P, const float2* g, float2* dx,
-                                       hipStream_t st);
+                                       int accumulate, hipStream_t st);
 
 // Fixed design: r_d (and d r_d / d tau) on the device, A^-1 of the Toeplitz
 // A = R_II + lam I, then class filters W_c = (I - lam A^-1)[off_c rows].
