@@ -62,7 +62,8 @@ struct Cx<float> {
 // The product on the matrix cores: a workgroup computes one 64 x 64 output
 // tile, staging 16-term chunks of A and B through LDS (the next chunk's loads
 // in flight during the current chunk's MFMAs); each wave owns a 32 x 32
-// quarter as 2 x 2 MFMA tiles, real and imaginary parts in separate
+// quarter as 2 x 2 MFMA tiles (one sub-tile each in a tile with a single
+// live row or column of them), real and imaginary parts in separate
 // accumulators (4 real products per complex one).  Operand lane (i, k) =
 // (lane % 16, lane / 16).  R is the arithmetic precision: double
 // (v_mfma_f64_16x16x4f64, FP64 products and sums) or float
