@@ -41,6 +41,9 @@ CASES = [
     dict(M=16, K=12, N=1200, N_fft=2048, taps=72, tau=4.0, B=100, Wn=150, slots=1, design_tau=8.0),
     # large system: 2B = 264 real rows (three dW row groups), 13 window tiles
     dict(M=2, K=24, N=3300, N_fft=4096, taps=144, tau=32.0, B=132, Wn=198, slots=1, design_tau=24.0),
+    # four passes whose first leaves 75 runs of subcarriers uncovered: dX is
+    # zeroed whole and every pass adds
+    dict(M=2, K=2, N=1200, N_fft=2048, taps=8, tau=3.0, B=4, Wn=10, slots=1, design_tau=4.0),
 ]
 
 
