@@ -24,3 +24,34 @@ def test_world_size_above_one_exits_with_a_message():
     r = _bench("--gpus", "1", env=env)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def _bench_module():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_stored_traffic_is_tied_to_the_kernel_sources(monkeypatch):
+    """The roofline's measured HBM bytes are reported only for the kernel
+    sources and workload they were counted on, and equal the record's
+    FETCH_SIZE and WRITE_SIZE scaled by the plain-copy factors."""
+    import json
+    b = _bench_module()
+    rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
+    k = "apply_f32_kernel<13, 12>"
+    e, cp = rec[k], rec["copy_probe"]
+    coeffs = e["coeffs"]
+    assert coeffs == 64 * 128 * 12 * 1200
+    v = b.stored_traffic(k, "fp32", coeffs)
+    if e["src_digest"] == b.src_digest("fp32"):
+        assert v == e["hbm_bytes_per_launch"]
+    else:   # the kernel sources changed since the counters were taken
+        assert v is None
+    scaled = e["FETCH_SIZE_kib"] * 1024 * cp["fetch_scale"] + e["WRITE_SIZE_kib"] * 1024 * cp["write_scale"]
+    assert abs(scaled - e["hbm_bytes_per_launch"]) <= 1e-6 * scaled
+    assert b.stored_traffic(k, "fp32", coeffs + 1) is None
+    monkeypatch.setattr(b, "src_digest", lambda family: "0" * 16)
+    assert b.stored_traffic(k, "fp32", coeffs) is None
