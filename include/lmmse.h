@@ -190,7 +190,8 @@ int lmmse_apply(lmmse_plan_t plan, int slots, const void *h_ls, void *h_hat,
                 void *stream);
 
 /* Sample covariance per (slot, user, window), R = (1/M) sum_m h_m h_m^H over
- * the antennas (Sec. III-B, eq. 13's R estimated from the data), products of
+ * the antennas (not a step of the paper: the data-driven R that eq. 13 takes
+ * as given, estimated from the LS values of the M antennas), products of
  * the complex64 LS values accumulated in FP64, stored as complex128
  * [S][K][N/B][Wn][Wn] (full matrix, both triangles).  Any plan with
  * Wn <= 256 (else UNSUPPORTED). */
@@ -275,7 +276,7 @@ int lmmse_sync_status(lmmse_plan_t plan, void *stream, int *info);
  *   LMMSE_COMB_12W: the S subcarriers S b .. S b + S - 1.
  * W_b depends only on b - wst_b (and, for 12W, on k): each UE has `win`
  * filter classes, designed in FP64 on the device when the plan is made and
- * applied in FP32.  The interpolated-LS baselines (Sec. II: LS_HOLD,
+ * applied in FP32.  The interpolated-LS baselines (Sec. IV-A-1: LS_HOLD,
  * LS_LINEAR, LS_LINEAR3, LS_QUADRATIC, LS_SPLINE) use the same LS values and
  * no filters (get_filters returns zeros); all run in FP32. */
 typedef enum lmmse_comb_kind {
@@ -339,7 +340,7 @@ int lmmse_comb_get_filters(lmmse_comb_t comb, void *w_out, void *stream);
 int lmmse_comb_estimate(lmmse_comb_t comb, int slots, const void *y,
                         const void *pilots, void *h_hat, void *stream);
 
-/* ---- MMSE MIMO detection (Sec. III-C, eq. 20-22) ------------------------- */
+/* ---- MMSE MIMO detection (Sec. IV-A, eq. 20-22; Sec. IV-C) -------------- */
 
 /* Per (slot s, data subcarrier n), with H = h_hat[s][:][:][n] (M x K) and
  * Y = y_data[s][:][:][n] (M x T), writes X = x_out[s][:][:][n] (T x K as

@@ -98,7 +98,7 @@ def comb_ls_hold(y, pilots, S: int, ues) -> np.ndarray:
 
 
 def comb_ls_linear(y, pilots, S: int, ues, fold: int | None = None) -> np.ndarray:
-    """Interpolated-LS baselines (Sec. II and IV-C comparison lines).
+    """Interpolated-LS baselines (Sec. IV-A-1, interpolated LS; comparison lines of Sec. V).
 
     fold=None: each subcarrier linearly interpolates the LS values of the two
     UE tones around it (the nearest tone's value outside the first..last
@@ -140,7 +140,7 @@ def comb_ls_linear(y, pilots, S: int, ues, fold: int | None = None) -> np.ndarra
 
 
 def comb_ls_quadratic(y, pilots, S: int, ues) -> np.ndarray:
-    """Second-order polynomial interpolated LS (Sec. II, the interpolated LS
+    """Second-order polynomial interpolated LS (Sec. IV-A-1, the interpolated LS
     estimators).  Reading: a subcarrier between a UE's tones i and i+1 takes
     the quadratic through the LS values of tones i-1, i, i+1 (tones 0, 1, 2
     in the first interval); outside the first..last tone the nearest tone's
@@ -187,7 +187,7 @@ def natural_spline_second_derivatives(v: np.ndarray) -> np.ndarray:
 
 
 def comb_ls_spline(y, pilots, S: int, ues) -> np.ndarray:
-    """Cubic-spline interpolated LS (Sec. II, the interpolated LS estimators).
+    """Cubic-spline interpolated LS (Sec. IV-A-1, the interpolated LS estimators).
     Reading: the natural cubic spline (zero second derivative at the first
     and last tone) through the LS values of a UE's tones, real and imaginary
     parts alike; outside the first..last tone the nearest tone's value is

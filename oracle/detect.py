@@ -1,4 +1,4 @@
-"""FP64 oracle of MMSE MIMO detection (Sec. III-C, eq. 20-22).  Test
+"""FP64 oracle of MMSE MIMO detection (Sec. IV-A, MMSE MIMO detector, eq. 20-22).  Test
 infrastructure only, like the rest of this package.
 
 Per (slot, data subcarrier n) with H the M x K channel estimate and Y the

@@ -1,4 +1,4 @@
-// MMSE MIMO detection (Sec. III-C, eq. 20-22): per (slot s, data
+// MMSE MIMO detection (Sec. IV-A, MMSE MIMO detector, eq. 20-22): per (slot s, data
 // subcarrier n), with H = h_hat[s, :, :, n] (M x K) and Y = y[s, :, :, n]
 // (M x T), the detected symbols solve
 //     (H^H H + sigma2 I) X = H^H Y                                  (eq. 22)
