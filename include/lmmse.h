@@ -247,6 +247,29 @@ int lmmse_backward(lmmse_plan_t plan, int slots, const void *h_ls,
                    const void *g, void *d_hls, double *d_tau, double *d_sigma2,
                    void *ws, size_t ws_bytes, void *stream);
 
+/* ---- estimate without a workspace argument ------------------------------- */
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * estimate of lmmse_estimate with the library's own static device workspace
+ * of LMMSE_NOALLOC_SCRATCH_BYTES instead of a caller buffer.  The caller
+ * still passes the inputs and the output.  Nothing is allocated or freed:
+ * the workspace is a file-scope device array, which every GPU the library
+ * runs on holds until the process ends, and whose address is looked up once
+ * per device (the first call on a device).  Every call on a GPU shares that
+ * GPU's array, so calls that overlap on one GPU (on other streams or other
+ * threads) race; the array keeps the last call's contents, and nothing is
+ * read from it before being written.  The plan's device must be current
+ * (else INVALID_ARG).  Returns LMMSE_ERR_WORKSPACE, launching nothing, when
+ * the estimate needs more than LMMSE_NOALLOC_SCRATCH_BYTES (lmmse_workspace_size
+ * of the forward path: 0 for the fused fixed designs, H_LS staging for
+ * unfused user counts, H_LS and the per-window filters for the sample
+ * covariance).  Otherwise as lmmse_estimate. */
+#define LMMSE_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int lmmse_estimate_noalloc(lmmse_plan_t plan, int slots, const void *y_pilot,
+                           const void *pilots, double sigma2, void *h_hat,
+                           void *stream);
+
 /* ---- status ------------------------------------------------------------- */
 
 /* Synchronises `stream`, returns LMMSE_OK or the first device-detected error

@@ -21,6 +21,8 @@ OK, INVALID_ARG, UNSUPPORTED, WORKSPACE, HIP, NOT_PD, NOT_READY, NO_DEVICE = ran
 R_UNIFORM, R_EXPONENTIAL, R_SAMPLE, R_USER = range(4)
 # lmmse_precision
 FP32, BF16X3, FP16X3 = range(3)
+# size of the static workspace of lmmse_estimate_noalloc (LMMSE_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class PlanDesc(ctypes.Structure):
@@ -69,6 +71,8 @@ PROTOTYPES = {
                                   c_size_t, c_void_p]),
     "lmmse_estimate": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_double, c_void_p,
                                c_void_p, c_size_t, c_void_p]),
+    "lmmse_estimate_noalloc": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_double, c_void_p,
+                                       c_void_p]),
     "lmmse_backward": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, P_double,
                                P_double, c_void_p, c_size_t, c_void_p]),
     "lmmse_sync_status": (c_int, [c_void_p, c_void_p, P_int]),

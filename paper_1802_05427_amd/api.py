@@ -194,6 +194,19 @@ class Plan:
                                        ws, wsb, _stream_ptr(stream)), "lmmse_estimate")
         return out
 
+    def estimate_noalloc(self, y, pilots, sigma2: float, out=None, stream=None) -> torch.Tensor:
+        """estimate() on the library's static device workspace (lmmse_estimate_noalloc):
+        nothing is allocated by the library; `out` may be passed so that
+        nothing is allocated here either."""
+        S = self._check_cols(y, "y")
+        self._check_pilots(pilots)
+        out = torch.empty_like(y) if out is None else out
+        self._check_cols(out, "out")
+        check(self._lib.lmmse_estimate_noalloc(self._h, S, _ptr(y), _ptr(pilots), float(sigma2),
+                                               _ptr(out), _stream_ptr(stream)),
+              "lmmse_estimate_noalloc")
+        return out
+
     def estimate_ls(self, h_ls, sigma2: float, out=None, stream=None) -> torch.Tensor:
         """The estimator from LS estimates, h_ls -> h_hat (records sigma2 as the design noise)."""
         S = self._check_cols(h_ls, "h_ls")

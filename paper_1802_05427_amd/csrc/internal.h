@@ -59,6 +59,10 @@ struct Plan {
 size_t fixed_bank_f32_elems(const Plan& p);    // float4 elements
 size_t hls_bytes(const lmmse_plan_desc& d, int slots);   // H_LS staging, 256-byte multiple
 size_t split_bank_elems(const Plan& p);        // uint16 elements per part
+// Workspace lmmse_estimate needs for `slots` slots (0 on the fused fixed path).
+size_t forward_workspace_bytes(const lmmse_plan_desc& d, int slots);
+// Device a plan was created on.
+int plan_device(lmmse_plan_t plan);
 
 // ---- launchers (return hipError_t of the launch) ----
 hipError_t launch_despread(const Plan& p, int slots, const float2* y, const float2* pilots,

@@ -136,6 +136,16 @@ size_t hls_bytes(const lmmse_plan_desc& d, int slots) {
     return ((size_t)slots * d.M * d.K * d.N * sizeof(float2) + 255) & ~(size_t)255;
 }
 
+size_t forward_workspace_bytes(const lmmse_plan_desc& d, int slots) {
+    if (slots <= 0) return 0;
+    if (d.rsource == LMMSE_R_SAMPLE) return sample_workspace_bytes(d, slots);
+    Plan tmp;
+    tmp.d = d;
+    return apply_fusable(tmp) ? 0 : hls_bytes(d, slots);
+}
+
+int plan_device(lmmse_plan_t plan) { return plan->device; }
+
 size_t fixed_bank_f32_elems(const Plan& p) { return (size_t)p.n_classes * 2 * p.G16 * p.Rpad * 4; }
 size_t split_bank_elems(const Plan& p) { return (size_t)p.n_classes * p.G16 * p.Rpad * 32; }
 
@@ -178,15 +188,8 @@ int lmmse_workspace_size(const lmmse_plan_desc* desc, int slots, size_t* bytes) 
     const int v = validate(desc);
     if (v != LMMSE_OK) return v;
     if (!bytes || slots < 0 || slots > desc->max_slots) return LMMSE_ERR_INVALID_ARG;
-    size_t need = 0;
-    Plan tmp;
-    tmp.d = *desc;
-    if (desc->rsource == LMMSE_R_SAMPLE) {
-        need = sample_workspace_bytes(*desc, slots);
-    } else if (!apply_fusable(tmp)) {
-        need = hls_bytes(*desc, slots);
-    }
-    need = std::max(need, backward_workspace_bytes(*desc, slots));
+    const size_t need =
+        std::max(forward_workspace_bytes(*desc, slots), backward_workspace_bytes(*desc, slots));
     *bytes = need;
     return LMMSE_OK;
 }
@@ -387,12 +390,9 @@ int lmmse_estimate(lmmse_plan_t plan, int slots, const void* y, const void* pilo
     if (!(sigma2 > 0.0) || !std::isfinite(sigma2)) return LMMSE_ERR_INVALID_ARG;
     if (slots == 0) return LMMSE_OK;
     if (!y || !pilots || !h_hat) return LMMSE_ERR_INVALID_ARG;
-    size_t need = 0;
-    lmmse_workspace_size(&plan->d, slots, &need);
     const hipStream_t st = (hipStream_t)stream;
     if (plan->d.rsource == LMMSE_R_SAMPLE) {
-        if (need && (!ws || ws_bytes < sample_workspace_bytes(plan->d, slots)))
-            return LMMSE_ERR_WORKSPACE;
+        if (!ws || ws_bytes < sample_workspace_bytes(plan->d, slots)) return LMMSE_ERR_WORKSPACE;
         plan->design_sigma2 = sigma2;   // the backward of this estimate uses it
         float2* hls = (float2*)ws;
         LMMSE_HIP_TRY(launch_despread(*plan, slots, (const float2*)y, (const float2*)pilots, hls, st));
