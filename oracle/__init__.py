@@ -44,6 +44,7 @@ from .comb import (  # noqa: F401
     zero_order_hold,
 )
 from .detect import mmse_detect, qpsk_decide  # noqa: F401
+from .fit_optimum import design_mse, fit_optimum, mixture_r  # noqa: F401
 from .grad import (  # noqa: F401
     dr_exponential_dtau,
     grad_fixed_design,
