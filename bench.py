@@ -15,6 +15,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -48,6 +49,8 @@ def parse():
                     help="only run the large sample-covariance workload (M=256, K=24, N=3300)")
     ap.add_argument("--detect-only", action="store_true",
                     help="only run the MMSE detection line")
+    ap.add_argument("--fit-only", action="store_true",
+                    help="only run the 200-step design fit of the differentiation workload")
     ap.add_argument("--comb-only", action="store_true",
                     help="only run the comb-pilot 3W / 12W lines")
     ap.add_argument("--copy-probe", action="store_true",
@@ -137,6 +140,52 @@ def fwd_bwd(M, K, N, N_fft, B, Wn, taps, sigma2, pil, dev, stream, steps, warmup
             "coeffs": S2 * M * K * N,
             "workload": "16 slots, overlapping 150/100, exponential design (tau, sigma2), "
                         "tau_rms ~ U[2, 24] per (slot, user), SNR 10 dB"}
+
+
+def fit_line(M, K, N, N_fft, B, Wn, taps, sigma2, pil, dev, steps=200):
+    """The design fit of the differentiation workload: 200 Adam steps (lr 0.05)
+    on (log tau_rms, log sigma2) from tau 8, sigma2 1e-4, each on a fresh
+    16-slot batch with tau_rms ~ U[2, 24] per (slot, user) drawn on the GPU
+    (generation, despreading, estimate, loss, backward, Adam update); the
+    endpoint beside the stored FP64 optimum of the expected error."""
+    import torch
+
+    from paper_1802_05427_amd import Plan
+    from paper_1802_05427_amd.fit import fit_design
+    from synth.torch_slots import draw_batch
+    S2 = 16
+    with Plan(M=M, K=K, N=N, N_fft=N_fft, B=B, Wn=Wn, rsource="exp", taps=taps, tau_rms=8.0,
+              sigma2=1e-4, max_slots=S2) as pl:
+        def fn(step):
+            g = torch.Generator(device=dev)
+            g.manual_seed(180205427 + 7919 * step)
+            y, H, _ = draw_batch(g, S2, M, K, N, N_fft, taps, 2.0, 24.0, sigma2, pil)
+            return pl.despread(y, pil), H
+
+        fit_design(pl, fn, steps=3, lr=0.05)   # warm-up (kernels, allocator)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = fit_design(pl, fn, steps=steps, lr=0.05, tau0=8.0, sigma2_0=1e-4)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    tail = st.history[-20:]
+    tau_f = math.exp(sum(math.log(h[1]) for h in tail) / len(tail))
+    sig_f = math.exp(sum(math.log(h[2]) for h in tail) / len(tail))
+    res = {"workload": "design fit: 16 slots per step, overlapping 150/100, exponential design, "
+                       "tau_rms ~ U[2, 24] per (slot, user), SNR 10 dB, Adam lr 0.05 from tau 8, "
+                       "sigma2 1e-4", "steps": steps, "seconds": round(wall, 3),
+           "steps_per_s": round(steps / wall, 1), "tau_final": round(tau_f, 4),
+           "sigma2_final": round(sig_f, 5),
+           "loss_last10": sum(h[0] for h in st.history[-10:]) / 10,
+           "loss_first10": sum(h[0] for h in st.history[:10]) / 10}
+    try:
+        with open(os.path.join(ROOT, "tests", "golden", "fit_optimum_diff_workload.json")) as f:
+            opt = json.load(f)
+        res["fp64_optimum"] = {"tau": round(opt["tau"], 4), "sigma2": round(opt["sigma2"], 5),
+                               "expected_mse": opt["mse"]}
+    except OSError:
+        pass
+    return res
 
 
 def large_sample(dev, stream, precision="fp16x3", slots=32, steps=3, warmup=1):
@@ -362,6 +411,12 @@ def main():
         return
     M, K, N, N_fft, taps, tau, snr = 128, 12, 1200, 2048, 72, 4.0, 10.0
     B, Wn, S = args.b, args.wn, args.slots
+    if args.fit_only:
+        from synth import make_pilots
+        pil = torch.from_numpy(make_pilots(K, N)).to(dev)
+        r = fit_line(M, K, N, N_fft, B, Wn, taps, 0.1, pil, dev)
+        print(json.dumps({"metric": "design fit", "detail": r}), flush=True)
+        return
     if args.fwdbwd_only:
         from synth import make_pilots
         pil = torch.from_numpy(make_pilots(K, N)).to(dev)
@@ -484,6 +539,7 @@ def main():
             "nmse_gap_db": abs(O.nmse_db(o3u, sb.H[:1]) - O.nmse_db(ref_s, sb.H[:1])),
             "discrepancy_db": round(O.discrepancy_db(o3u, ref_s), 1)}
         extras["fwd_bwd"] = fwd_bwd(M, K, N, N_fft, B, Wn, taps, sigma2, pil, dev, stream, 5, 2)
+        extras["fit"] = fit_line(M, K, N, N_fft, B, Wn, taps, sigma2, pil, dev)
         del y, out
         torch.cuda.empty_cache()
         extras["large_sample"] = large_sample(dev, stream)

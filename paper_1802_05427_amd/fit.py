@@ -62,12 +62,12 @@ def fit_design(plan, batch_fn, steps: int = 200, lr: float = 0.05, tau0: float =
         loss.backward()
         opt.step()
         state.step = step + 1
-        state.history.append([float(loss.detach()), math.exp(float(lt)), math.exp(float(ls))])
+        state.history.append([float(loss.detach()), math.exp(lt.item()), math.exp(ls.item())])
         if log_every and (step % log_every == 0 or step + 1 == steps):
             print(f"fit step {step}: loss {state.history[-1][0]:.4e} tau {state.history[-1][1]:.3f} "
                   f"sigma2 {state.history[-1][2]:.3e}", flush=True)
-    state.log_tau = float(lt)
-    state.log_sigma2 = float(ls)
+    state.log_tau = lt.item()
+    state.log_sigma2 = ls.item()
     sd = opt.state_dict()
     state.adam = {"state": {str(k): {kk: (vv.item() if torch.is_tensor(vv) else vv)
                                      for kk, vv in v.items()}
