@@ -4,7 +4,9 @@ Workload (default): the paper-sized uplink, M=128 antennas, K=12 users,
 N=1200 used subcarriers of a 2048-point FFT, 12 code-spread pilot symbols per
 slot, a batch of 64 slots (98,304 LS columns, 117,964,800 channel
 coefficients per step), overlapping windows of 150 keeping the central 100,
-exponential-profile design (tau_rms = 4 samples, 72 taps), SNR 10 dB.
+the fixed design of eq. 16 with a uniform profile over the 144-sample cyclic
+prefix (L = 144), channels drawn with an exponential profile (tau_rms = 4
+samples, 72 taps), SNR 10 dB.
 A step is one call of lmmse_estimate: LS despreading of the pilot symbols and
 block filtering of every column (one fused launch), with the plan's FP64
 filters.  Inputs are resident in HBM before timing.
@@ -37,7 +39,7 @@ def parse():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3", "fp16x3"])
     ap.add_argument("--wn", type=int, default=150)
     ap.add_argument("--b", type=int, default=100)
-    ap.add_argument("--rsource", default="exp", choices=["exp", "uniform", "sample"])
+    ap.add_argument("--rsource", default="uniform", choices=["exp", "uniform", "sample"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--quiet", action="store_true")
@@ -107,6 +109,18 @@ def time_calls(fn, steps, warmup, stream):
     return per[len(per) // 2]
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def log(msg, quiet=False):
     if not quiet:
         print(msg, file=sys.stderr, flush=True)
@@ -140,6 +154,60 @@ def fwd_bwd(M, K, N, N_fft, B, Wn, taps, sigma2, pil, dev, stream, steps, warmup
             "coeffs": S2 * M * K * N,
             "workload": "16 slots, overlapping 150/100, exponential design (tau, sigma2), "
                         "tau_rms ~ U[2, 24] per (slot, user), SNR 10 dB"}
+
+
+def timed_estimate(y, pil, sigma2, dev, stream, B, Wn, rsource, precision="fp32", flops=None,
+                   ceiling=None, steps=10, warmup=2):
+    """lmmse_estimate on the headline batch with another block plan or source:
+    median event time, coefficients/s and, for FP32 products, the achieved
+    FP32 matrix-core rate at `flops` per coefficient."""
+    import torch
+
+    from paper_1802_05427_amd import Plan
+    S, M, K, N = (int(v) for v in y.shape)
+    coeffs = S * M * K * N
+    with Plan(M=M, K=K, N=N, N_fft=2048, B=B, Wn=Wn, rsource=rsource, taps=72, tau_rms=4.0, L=144.0,
+              sigma2=sigma2, max_slots=S, precision=precision) as pl:
+        out = torch.empty_like(y)
+        t_ms = time_calls(lambda: pl.estimate(y, pil, sigma2, out=out), steps, warmup, stream)
+    r = {"B": B, "Wn": Wn, "rsource": rsource, "precision": precision, "ms": round(t_ms, 4),
+         "value": round(coeffs / (t_ms * 1e-3), 1)}
+    if flops:
+        r["tflops"] = round(flops * coeffs / (t_ms * 1e-3) / 1e12, 2)
+        r["mfma_fp32_frac"] = round(r["tflops"] / PEAK["fp32_mfma_TFs"], 4)
+        r["flop_per_coef"] = flops
+    if ceiling:
+        r["ceiling_coeff_per_s"] = round(ceiling, 1)
+    if precision != "fp32":
+        r["hbm_frac"] = round(16.0 * coeffs / (t_ms * 1e-3) / 1e9 / PEAK["hbm_GBs"], 4)
+    return r
+
+
+def gap_per_snr(M, K, N, N_fft, B, Wn, taps, tau, rsource, dev):
+    """NMSE gap and discrepancy against the FP64 oracle per SNR point (0, 10,
+    20 dB) for FP32, BF16x3 and FP16x3, one seeded slot each."""
+    import torch
+
+    import oracle as O
+    from paper_1802_05427_amd import Plan
+    from synth import make_slot_batch
+    okw = dict(N_fft=N_fft, tau=tau, taps=taps, L=144.0)
+    res = {}
+    for snr in (0.0, 10.0, 20.0):
+        sb = make_slot_batch(M=M, K=K, N=N, N_fft=N_fft, taps=taps, tau=tau, snr_db=snr, slots=1,
+                             config_id=2, first_slot=100 + int(snr))
+        ref = O.estimate(sb.y, sb.pilots, sb.sigma2, B, Wn, rsource, **okw)
+        y1 = torch.from_numpy(sb.y).to(dev)
+        p1 = torch.from_numpy(sb.pilots).to(dev)
+        for prec in ("fp32", "bf16x3", "fp16x3"):
+            with Plan(M=M, K=K, N=N, N_fft=N_fft, B=B, Wn=Wn, rsource=rsource, taps=taps, tau_rms=tau,
+                      L=144.0, sigma2=sb.sigma2, max_slots=1, precision=prec) as pl:
+                o = pl.estimate(y1, p1, sb.sigma2).cpu().numpy()
+            res.setdefault(prec, {})[f"{snr:g}dB"] = {
+                "nmse_gap_db": abs(O.nmse_db(o, sb.H) - O.nmse_db(ref, sb.H)),
+                "discrepancy_db": round(O.discrepancy_db(o, ref), 1),
+                "nmse_db": round(O.nmse_db(ref, sb.H), 3)}
+    return res
 
 
 def fit_line(M, K, N, N_fft, B, Wn, taps, sigma2, pil, dev, steps=200):
@@ -489,8 +557,11 @@ def main():
     disc = O.discrepancy_db(out_u[:1], ref)
     nmse_gpu = O.nmse_db(out_u, sb.H)
 
-    # roofline of the one kernel a step launches, from the mean event time
-    flops_per_coef = 8.0 * Wn   # complex B x Wn filter per block: 8*B*Wn flops per column per block
+    # roofline of the one kernel a step launches, from the mean event time:
+    # the complex B x Wn filter per block is 8*B*Wn flops per column per block
+    # (8*Wn per coefficient), the fused despreading a K-point DFT (8K) and the
+    # conj-pilot multiply (6) per coefficient
+    flops_per_coef = 8.0 * Wn + 8.0 * K + 6.0
     kernel_flops = flops_per_coef * coeffs
     achieved = kernel_flops / (ms * 1e-3) / 1e12
     peak = {"fp32": PEAK["fp32_mfma_TFs"], "bf16x3": PEAK["bf16_mfma_TFs"] / 3,
@@ -501,7 +572,7 @@ def main():
     kname = ("apply_f32_kernel<13, 12>" if args.precision == "fp32"
              else f"apply_split_kernel<13, 12, {args.precision}>")
     traffic = (stored_traffic(kname, family, coeffs)
-               if (args.rsource == "exp" and B == 100 and Wn == 150) else None)
+               if (args.rsource in ("exp", "uniform") and B == 100 and Wn == 150) else None)
     if args.precision == "fp32":
         roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": traffic}
@@ -510,11 +581,11 @@ def main():
                 "frac": round(gbs / PEAK["hbm_GBs"], 4), "traffic": traffic}
 
     extras = {}
-    if not args.no_extras and args.rsource == "exp" and args.precision == "fp32":
+    if not args.no_extras and args.rsource in ("exp", "uniform") and args.precision == "fp32":
         # split precision on the same workload
         for prec in ("bf16x3", "fp16x3"):
-            with Plan(M=M, K=K, N=N, N_fft=N_fft, B=B, Wn=Wn, rsource="exp", taps=taps, tau_rms=tau,
-                      sigma2=sigma2, max_slots=S, precision=prec) as pl:
+            with Plan(M=M, K=K, N=N, N_fft=N_fft, B=B, Wn=Wn, rsource=args.rsource, taps=taps,
+                      tau_rms=tau, L=144.0, sigma2=sigma2, max_slots=S, precision=prec) as pl:
                 o2 = torch.empty_like(y)
                 t_ms = time_calls(lambda: pl.estimate(y, pil, sigma2, out=o2), max(5, args.steps // 2), 2, stream)
                 o2u = o2[:1].cpu().numpy()
@@ -538,6 +609,18 @@ def main():
             "value": round(S2 * M * K * N / (t_ms * 1e-3), 1), "ms": round(t_ms, 4), "slots": S2,
             "nmse_gap_db": abs(O.nmse_db(o3u, sb.H[:1]) - O.nmse_db(ref_s, sb.H[:1])),
             "discrepancy_db": round(O.discrepancy_db(o3u, ref_s), 1)}
+        extras["gap_per_snr"] = gap_per_snr(M, K, N, N_fft, B, Wn, taps, tau, args.rsource, dev)
+        extras["non_overlap"] = timed_estimate(y, pil, sigma2, dev, stream, B=100, Wn=100,
+                                               rsource=args.rsource, flops=8.0 * 100 + 8.0 * K + 6.0,
+                                               ceiling=PEAK["fp32_mfma_TFs"] * 1e12 / (8.0 * 100 + 8.0 * K + 6.0))
+        extras["full_band"] = {
+            "fixed_fp32": timed_estimate(y, pil, sigma2, dev, stream, B=N, Wn=N, rsource=args.rsource,
+                                         flops=8.0 * N + 8.0 * K + 6.0,
+                                         ceiling=PEAK["fp32_mfma_TFs"] * 1e12 / (8.0 * N + 8.0 * K + 6.0)),
+            "fixed_bf16x3": timed_estimate(y, pil, sigma2, dev, stream, B=N, Wn=N, rsource=args.rsource,
+                                           precision="bf16x3"),
+            "sample_fp32": timed_estimate(y, pil, sigma2, dev, stream, B=N, Wn=N, rsource="sample"),
+        }
         extras["fwd_bwd"] = fwd_bwd(M, K, N, N_fft, B, Wn, taps, sigma2, pil, dev, stream, 5, 2)
         extras["fit"] = fit_line(M, K, N, N_fft, B, Wn, taps, sigma2, pil, dev)
         del y, out
@@ -560,10 +643,23 @@ def main():
             O.estimate(sb.y[i:i + 1], sb.pilots, sigma2, B, Wn, args.rsource, **okw)
             t_cpu += time.perf_counter() - t1
             n_done += 1
+        # the same on one thread (BLAS limited to one thread)
+        from threadpoolctl import threadpool_limits
+        n1, t1c = 0, 0.0
+        with threadpool_limits(limits=1):
+            while t1c < args.cpu_seconds:
+                i = n1 % uniq
+                t1 = time.perf_counter()
+                O.estimate(sb.y[i:i + 1], sb.pilots, sigma2, B, Wn, args.rsource, **okw)
+                t1c += time.perf_counter() - t1
+                n1 += 1
         cpu = {"value": round(n_done * M * K * N / t_cpu, 1), "unit": "coeff/s", "cores": cpu_threads,
                "kind": "oracle",
                "sample": f"{n_done} slot(s) of the same workload, FP64 NumPy oracle "
-                         f"(despread, design, filter), {t_cpu:.1f}s"}
+                         f"(despread, design, filter), {t_cpu:.1f}s",
+               "value_1thread": round(n1 * M * K * N / t1c, 1),
+               "sample_1thread": f"{n1} slot(s), BLAS limited to one thread, {t1c:.1f}s",
+               "cpu_model": cpu_model()}
 
     rec = {
         "metric": "channel coeffs estimated/s (M*K*N) at stated NMSE gap vs FP64",
@@ -580,7 +676,11 @@ def main():
         "data": f"synthetic: {uniq} seeded slots (exponential PDP tau 4, 72 taps, SNR 10 dB) tiled to {S}",
         "config": {"workload": f"paper-sized uplink M={M} K={K} N={N} N_fft={N_fft}, {S} slots, "
                                f"{'overlapping' if Wn > B else 'non-overlapping'} B={B} Wn={Wn}, "
-                               f"{args.rsource} correlation, {args.precision}",
+                               + {"uniform": "fixed design with a uniform profile over the "
+                                             "144-sample cyclic prefix (L=144)",
+                                  "exp": "fixed design with the matched exponential profile (tau 4)",
+                                  "sample": "sample covariance per (slot, user, window)"}[args.rsource]
+                               + f", {args.precision}",
                    "slots": S, "coeffs_per_step": coeffs, "B": B, "Wn": Wn,
                    "precision": args.precision, "rsource": args.rsource},
         "nmse_gap_db": gap,

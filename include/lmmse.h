@@ -38,9 +38,19 @@
  *                        r_d = sum_l p_l exp(-j2 pi l d/N_fft), p_l ~ e^{-l/tau}
  *   LMMSE_R_SAMPLE       raw sample covariance over the M antennas, per
  *                        (slot, user, window): R = (1/M) sum_m h h^H;
- *                        windows up to 256 (up to 160 held in registers,
- *                        wider ones in the workspace)
- *   LMMSE_R_USER         filters supplied by the caller (lmmse_set_filters)
+ *                        windows up to 256 are designed directly (up to 160
+ *                        held in registers, wider ones in the workspace);
+ *                        wider windows, e.g. the full band B = Wn = N, use
+ *                        the equal push-through form W X = X_O G (G + lam I)^-1
+ *                        with the M x M Gram matrix G = X^H X / M of the
+ *                        window (M <= 256, FP32 precision only)
+ *   LMMSE_R_USER         filters supplied by the caller (lmmse_set_filters);
+ *                        also named LMMSE_R_USER_W
+ *   LMMSE_R_USER_R       an N x N subcarrier correlation R_HH supplied by the
+ *                        caller (lmmse_set_correlation), from which the plan
+ *                        designs every block's filter on the device in FP64;
+ *                        R need not be Toeplitz, so every block is its own
+ *                        class (N/B filters)
  * For a fixed design every block whose window sits at the same offset
  * start_b - b*B shares one filter ("class"); there are at most 3 classes
  * when the halo (Wn-B)/2 is at most B (first, interior, last block).
@@ -55,8 +65,8 @@
  * hi*hi + hi*lo + lo*hi with FP32 accumulation in BF16 (LMMSE_BF16X3) or
  * FP16 (LMMSE_FP16X3); the sample-covariance path writes each window's
  * filter as hi / lo parts and filters with the same split products.
- * The backward products are FP32 on the matrix cores (fixed designs) or
- * FP64 on the vector units (sample covariance).
+ * The backward products are FP32 on the matrix cores (fixed designs), or
+ * FP64 and FP32 batched products on the matrix cores (sample covariance).
  *
  * Calls with slots == 0 launch nothing and accept NULL data pointers.
  *
@@ -91,8 +101,10 @@ typedef enum lmmse_rsource {
     LMMSE_R_UNIFORM = 0,
     LMMSE_R_EXPONENTIAL = 1,
     LMMSE_R_SAMPLE = 2,
-    LMMSE_R_USER = 3
+    LMMSE_R_USER = 3,
+    LMMSE_R_USER_R = 4
 } lmmse_rsource;
+#define LMMSE_R_USER_W LMMSE_R_USER
 
 typedef enum lmmse_precision {
     LMMSE_FP32 = 0,
@@ -167,15 +179,29 @@ int lmmse_plan_get_desc(lmmse_plan_t plan, lmmse_plan_desc *out);
  * error (A not positive definite) is reported by lmmse_sync_status. */
 int lmmse_set_design(lmmse_plan_t plan, double tau_rms, double sigma2, void *stream);
 /* On a SAMPLE plan it only records sigma2 (tau_rms ignored, nothing is
- * launched): the noise variance lmmse_backward differentiates at. */
+ * launched): the noise variance lmmse_backward differentiates at.  On a
+ * USER_R plan it records sigma2 and, once a correlation has been set,
+ * redesigns the filters from it (tau_rms ignored). */
 
 /* Installs caller filters (LMMSE_R_USER plans): w is device complex128
  * [n_classes][B][Wn], row-major per filter, class order as lmmse_block_plan
  * numbers them.  Asynchronous (reads w on `stream`). */
 int lmmse_set_filters(lmmse_plan_t plan, const void *w, void *stream);
 
+/* Caller correlation (LMMSE_R_USER_R plans; eq. 13 with R_HH given, per
+ * block of Sec. IV-B): r is device complex128 [N][N], row-major, Hermitian
+ * (both triangles are read as given) and positive semi-definite.  The plan
+ * copies the windows R[I_b, I_b] out of it (r may be freed after the stream
+ * reaches this call) and designs W_b = R[O_b, I_b] (R[I_b, I_b] + lam I)^-1,
+ * lam = sigma2 / K at the plan's design sigma2, for every block b (class b)
+ * on `stream`: the register-resident Hermitian sweep up to Wn = 160, the
+ * panel sweep above.  Asynchronous; a non-positive pivot is reported by
+ * lmmse_sync_status (info = block).  Errors: INVALID_ARG, UNSUPPORTED (not a
+ * USER_R plan), HIP. */
+int lmmse_set_correlation(lmmse_plan_t plan, const void *r, void *stream);
+
 /* Copies the current FP64 filters of a fixed-design or user plan to device
- * complex128 [n_classes][B][Wn].  Asynchronous. */
+ * complex128 [n_classes][B][Wn] (n_classes = N/B for USER_R).  Asynchronous. */
 int lmmse_get_filters(lmmse_plan_t plan, void *w_out, void *stream);
 
 /* ---- forward path ------------------------------------------------------- */
@@ -193,18 +219,22 @@ int lmmse_apply(lmmse_plan_t plan, int slots, const void *h_ls, void *h_hat,
  * the antennas (not a step of the paper: the data-driven R that eq. 13 takes
  * as given, estimated from the LS values of the M antennas), products of
  * the complex64 LS values accumulated in FP64, stored as complex128
- * [S][K][N/B][Wn][Wn] (full matrix, both triangles).  Any plan with
- * Wn <= 256 (else UNSUPPORTED). */
+ * [S][K][N/B][Wn][Wn] (full matrix, both triangles).  Any plan. */
 int lmmse_covariance(lmmse_plan_t plan, int slots, const void *h_ls,
                      void *r_win, void *stream);
 
 /* Batched FP64 block filters from window correlations r_win (complex128
  * [S][K][N/B][Wn][Wn], e.g. from lmmse_covariance): for block b,
  * W = R[off_b : off_b + B, :] (R + (sigma2/K) I)^-1, stored as complex128
- * [S][K][N/B][B][Wn].  Windows with Wn <= 160 (the register-resident
- * design; else UNSUPPORTED). */
+ * [S][K][N/B][B][Wn].  Windows up to 160 use the register-resident sweep
+ * and no workspace; wider windows copy r_win into ws and invert there by the
+ * panel sweep (ws: lmmse_sample_filters_workspace_size bytes, else
+ * LMMSE_ERR_WORKSPACE).  r_win is not modified. */
+int lmmse_sample_filters_workspace_size(const lmmse_plan_desc *desc, int slots,
+                                        size_t *bytes);
 int lmmse_sample_filters(lmmse_plan_t plan, int slots, const void *r_win,
-                         double sigma2, void *w_out, void *stream);
+                         double sigma2, void *w_out, void *ws, size_t ws_bytes,
+                         void *stream);
 
 /* The whole estimator, estimate(y_pilot, pilots, sigma2, block plan) -> h_hat.
  * Fixed/user designs: a fused despread + filter launch with the plan's
@@ -241,7 +271,11 @@ int lmmse_estimate_ls(lmmse_plan_t plan, int slots, const void *h_ls,
  * lmmse_estimate / lmmse_set_design): per (slot, user, window) the filter
  * depends on h_ls through R as well, so d_hls also receives
  * (Gam + Gam^H) X / M with Gam the window's gradient of R (the gradient
- * of the FP64 design, whatever the filtering precision).  ws:
+ * of the FP64 design, whatever the filtering precision).  USER_R: d_hls
+ * and *d_sigma2 (per-block inverses); *d_tau is NaN.  USER (caller
+ * filters): d_hls only.  Windows wider than 256: d_hls only, for fixed,
+ * USER_R and USER plans; requesting d_tau / d_sigma2 there, or any sample
+ * backward, returns LMMSE_ERR_UNSUPPORTED before anything is launched.  ws:
  * lmmse_workspace_size bytes. */
 int lmmse_backward(lmmse_plan_t plan, int slots, const void *h_ls,
                    const void *g, void *d_hls, double *d_tau, double *d_sigma2,

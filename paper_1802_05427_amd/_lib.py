@@ -18,7 +18,7 @@ P_size_t = ctypes.POINTER(ctypes.c_size_t)
 # lmmse_status
 OK, INVALID_ARG, UNSUPPORTED, WORKSPACE, HIP, NOT_PD, NOT_READY, NO_DEVICE = range(8)
 # lmmse_rsource
-R_UNIFORM, R_EXPONENTIAL, R_SAMPLE, R_USER = range(4)
+R_UNIFORM, R_EXPONENTIAL, R_SAMPLE, R_USER, R_USER_R = range(5)
 # lmmse_precision
 FP32, BF16X3, FP16X3 = range(3)
 # size of the static workspace of lmmse_estimate_noalloc (LMMSE_NOALLOC_SCRATCH_BYTES)
@@ -66,7 +66,10 @@ PROTOTYPES = {
     "lmmse_despread": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
     "lmmse_apply": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
     "lmmse_covariance": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
-    "lmmse_sample_filters": (c_int, [c_void_p, c_int, c_void_p, c_double, c_void_p, c_void_p]),
+    "lmmse_sample_filters_workspace_size": (c_int, [P_desc, c_int, P_size_t]),
+    "lmmse_sample_filters": (c_int, [c_void_p, c_int, c_void_p, c_double, c_void_p, c_void_p,
+                                     c_size_t, c_void_p]),
+    "lmmse_set_correlation": (c_int, [c_void_p, c_void_p, c_void_p]),
     "lmmse_estimate_ls": (c_int, [c_void_p, c_int, c_void_p, c_double, c_void_p, c_void_p,
                                   c_size_t, c_void_p]),
     "lmmse_estimate": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_double, c_void_p,

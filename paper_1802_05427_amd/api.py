@@ -16,7 +16,7 @@ from . import _lib
 from ._lib import CombDesc, PlanDesc, check
 
 _RSOURCE = {"uniform": _lib.R_UNIFORM, "exp": _lib.R_EXPONENTIAL,
-            "sample": _lib.R_SAMPLE, "user": _lib.R_USER}
+            "sample": _lib.R_SAMPLE, "user": _lib.R_USER, "user_r": _lib.R_USER_R}
 _PREC = {"fp32": _lib.FP32, "bf16x3": _lib.BF16X3, "fp16x3": _lib.FP16X3}
 
 
@@ -71,6 +71,8 @@ class Plan:
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.starts, self.offsets, self.classes, self.n_classes = block_plan(
             self.desc.N, self.desc.B, self.desc.Wn)
+        if self.desc.rsource == _lib.R_USER_R:   # one filter per block
+            self.classes, self.n_classes = list(range(self.nb)), self.nb
         self._ws = None
 
     # ---- lifetime
@@ -135,6 +137,16 @@ class Plan:
             raise ValueError(f"w must be a contiguous complex128 CUDA [{self.n_classes}, {d.B}, {d.Wn}] tensor")
         check(self._lib.lmmse_set_filters(self._h, _ptr(w), _stream_ptr(stream)), "lmmse_set_filters")
 
+    def set_correlation(self, r: torch.Tensor, stream=None):
+        """Caller correlation (rsource 'user_r'): r is a complex128 CUDA [N, N]
+        Hermitian matrix; the plan designs one filter per block from it."""
+        d = self.desc
+        if (r.dtype != torch.complex128 or r.device.type != "cuda" or not r.is_contiguous()
+                or tuple(r.shape) != (d.N, d.N)):
+            raise ValueError(f"r must be a contiguous complex128 CUDA [{d.N}, {d.N}] tensor")
+        check(self._lib.lmmse_set_correlation(self._h, _ptr(r), _stream_ptr(stream)),
+              "lmmse_set_correlation")
+
     def get_filters(self, stream=None) -> torch.Tensor:
         d = self.desc
         w = torch.empty((self.n_classes, d.B, d.Wn), dtype=torch.complex128, device=self.device)
@@ -179,7 +191,12 @@ class Plan:
         shape = (S, d.K, self.nb, d.B, d.Wn)
         if out is None:
             out = torch.empty(shape, dtype=torch.complex128, device=self.device)
+        b = ctypes.c_size_t(0)
+        check(self._lib.lmmse_sample_filters_workspace_size(ctypes.byref(self.desc), S, ctypes.byref(b)),
+              "lmmse_sample_filters_workspace_size")
+        ws = torch.empty(b.value, dtype=torch.uint8, device=self.device) if b.value else None
         check(self._lib.lmmse_sample_filters(self._h, S, _ptr(r_win), float(sigma2), _ptr(out),
+                                             _ptr(ws) if ws is not None else None, b.value,
                                              _stream_ptr(stream)), "lmmse_sample_filters")
         return out
 

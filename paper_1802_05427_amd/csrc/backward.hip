@@ -52,6 +52,8 @@ struct BwGeom {
 constexpr int kDwMaxRT = 7;           // dW row tiles per workgroup (2B real rows in row groups):
                                       // <= 96 registers, 5 waves per SIMD
 constexpr int kDwMaxWaves = 16;       // one wave per 16 window columns: Wn <= 256
+static_assert(16 * kDwMaxWaves == kMaxSampleWindowLarge,
+              "lmmse_backward refuses design gradients above kMaxSampleWindowLarge");
 constexpr int kDwSlots = 512;         // workgroups resident at once (2 per CU)
 
 static BwGeom bw_geom(const lmmse_plan_desc& d, const std::vector<int>& starts, long long ncols) {
@@ -297,21 +299,27 @@ __global__ __launch_bounds__(256) void dw_reduce_kernel(const float2* __restrict
     }
 }
 
-// Z_c = dW_c A^-1.  A^-1 is stored column-major and is Hermitian, so
-// A^-1[m][j] = conj(ainv[j + m Wn]): consecutive j (threads) read
+// Z_c = dW_c A_c^-1.  A^-1 is Hermitian.  Stored column-major (the fixed
+// design, one matrix for all classes, ainv_stride 0), A^-1[m][j] =
+// conj(ainv[j + m Wn]); stored row-major (a caller correlation, one matrix
+// per class), A^-1[m][j] = ainv[j + m Wn].  Consecutive j (threads) read
 // consecutive entries, and the dW_c row is shared by the workgroup's threads.
 __global__ void z_kernel(const double2* __restrict__ dwc, const double2* __restrict__ ainv,
-                         double2* __restrict__ z, int n_classes, int B, int Wn) {
+                         double2* __restrict__ z, int n_classes, int B, int Wn,
+                         long long ainv_stride, int rowmajor) {
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long per = (long long)B * Wn;
     if (idx >= per * n_classes) return;
     const long long row = idx / Wn;     // (c, o)
     const int j = (int)(idx % Wn);
     const double2* d = dwc + row * Wn;
+    const double2* ai = ainv + (idx / per) * ainv_stride;
+    const double cs = rowmajor ? -1.0 : 1.0;
     double sx = 0.0, sy = 0.0;
 #pragma unroll 4
     for (int m = 0; m < Wn; ++m) {
-        const double2 u = d[m], v = ainv[j + (long long)m * Wn];   // v = conj(A^-1[m][j])
+        const double2 u = d[m], a = ai[j + (long long)m * Wn];
+        const double2 v = make_double2(a.x, cs * a.y);   // conj(A^-1[m][j])
         sx += u.x * v.x + u.y * v.y;
         sy += u.y * v.x - u.x * v.y;
     }
@@ -402,6 +410,7 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 static int count_classes(const lmmse_plan_desc& d) {
     const int nb = d.N / d.B, halo = (d.Wn - d.B) / 2;
+    if (d.rsource == LMMSE_R_USER_R) return nb;   // one filter per block
     std::vector<int> offs;
     for (int b = 0; b < nb; ++b) {
         const int s = std::min(std::max(b * d.B - halo, 0), d.N - d.Wn);
@@ -433,7 +442,8 @@ static BwLayout bw_layout(const lmmse_plan_desc& d, int n_classes, const BwGeom&
 }
 
 size_t backward_workspace_bytes(const lmmse_plan_desc& d, int slots) {
-    if (d.rsource == LMMSE_R_SAMPLE) return sample_backward_workspace_bytes(d, slots);
+    if (d.rsource == LMMSE_R_SAMPLE)   // no sample backward above 256 (refused)
+        return d.Wn > kMaxSampleWindowLarge ? 0 : sample_backward_workspace_bytes(d, slots);
     const long long ncols = (long long)slots * d.M * d.K;
     std::vector<int> starts;
     const int nb = d.N / d.B, halo = (d.Wn - d.B) / 2;
@@ -529,8 +539,9 @@ hipError_t launch_backward_fixed(Plan& p, int slots, const float2* hls, const fl
     const long long tot = (long long)p.n_classes * B * Wn;
     hipLaunchKernelGGL(dw_reduce_kernel, dim3((unsigned)((tot + 63) / 64)), dim3(256), 0, st, part,
                        p.d_classes, dwc, p.n_classes, p.nb, geo.nch, B, Wn);
+    const bool per_block = p.d.rsource == LMMSE_R_USER_R;
     hipLaunchKernelGGL(z_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, dwc, p.ainv,
-                       zc, p.n_classes, B, Wn);
+                       zc, p.n_classes, B, Wn, per_block ? (long long)Wn * Wn : 0LL, per_block ? 1 : 0);
     const long long totg = (long long)p.n_classes * Wn * Wn;
     hipLaunchKernelGGL(gamma_kernel, dim3((unsigned)((totg + 255) / 256)), dim3(256), 0, st, p.w64, zc,
                        gam, p.n_classes, B, Wn);

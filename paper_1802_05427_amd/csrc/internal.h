@@ -42,7 +42,10 @@ struct Plan {
     int* d_bstarts = nullptr;    // [nb] first output subcarrier of each block, b*B
     int* d_class_off = nullptr;  // [n_classes]
     double2* w64 = nullptr;      // [n_classes][B][Wn] FP64 filters
-    double2* ainv = nullptr;     // [Wn][Wn] (R_II + lam I)^-1 of the fixed design
+    double2* ainv = nullptr;     // [Wn][Wn] (R_II + lam I)^-1 of the fixed design (column-major);
+                                 // caller correlation: [nb][Wn][Wn] per block (row-major)
+    double2* rwin = nullptr;     // caller correlation: its windows R[I_b, I_b], [nb][Wn][Wn]
+    double2* dwork = nullptr;    // caller correlation, Wn > 160: sweep scratch of nb windows
     double2* rd = nullptr;       // [3][Wn] r_d, dr_d/dtau (d = 0..Wn-1), x = A^-1 e_0
     float4* wf32 = nullptr;      // FP32 bank
     uint16_t* whi = nullptr;     // split bank, hi part
@@ -51,6 +54,7 @@ struct Plan {
     int* status = nullptr;       // [2] device status word: code, info
     double* dscal = nullptr;     // [4] device scratch for the design backward
     bool ready = false;
+    bool have_corr = false;      // caller correlation set (its windows in rwin)
     double design_sigma2 = 0.0;
     double design_tau = 0.0;
     float lo_scale = 1.0f;       // split-bank lo scale (FP16: 2^11)
@@ -90,9 +94,11 @@ hipError_t launch_pack_banks(Plan& p, hipStream_t st);
 // Sample-covariance path.
 hipError_t launch_covariance(const Plan& p, int slots, const float2* hls, double2* r_win,
                              hipStream_t st);
-hipError_t launch_batched_filters(const Plan& p, int nmat, double2* a_work, double2* rhs_work,
-                                  const double2* r_win, double lam, double2* w_out,
-                                  hipStream_t st);
+// Register-resident design (Wn <= 160) from window correlations r_win
+// [nmat][Wn][Wn] (row-major): W [nmat][B][Wn] with offsets[mat % nb] and,
+// when ainv is not null, A^-1 = (R + lam I)^-1 [nmat][Wn][Wn] (row-major).
+hipError_t launch_batched_filters(const Plan& p, long long nmat, const double2* r_win, double lam,
+                                  double2* w_out, double2* ainv, hipStream_t st);
 hipError_t launch_sample_estimate(const Plan& p, int slots, const float2* hls, double lam,
                                   float2* out, void* ws, hipStream_t st);
 size_t sample_workspace_bytes(const lmmse_plan_desc& d, int slots);
@@ -109,6 +115,31 @@ size_t sample_backward_workspace_bytes(const lmmse_plan_desc& d, int slots);
 constexpr int kMaxSampleWindowReg = 160;
 constexpr int kMaxSampleWindowLarge = 256;
 constexpr int kSweepPanel = 64;   // pivots per panel of the workspace-resident sweep
+// Windows wider than kMaxSampleWindowLarge: the push-through form (M x M
+// systems), for up to this many antennas.
+constexpr int kMaxPushthroughAntennas = 256;
+// -(A + lam I)^-1 in place for nmat Hermitian n x n matrices [mat][n][n]
+// (both triangles), batch index (slot * K + user) * nb + block; scratch:
+// sweep_scratch_bytes(n, nmat).  Non-positive pivot: LMMSE_ERR_NOT_PD with
+// matrix mat0 + mat in status.
+hipError_t launch_sweep_inverse(long long nmat, long long mat0, int n, int K, int nb, double lam,
+                                double2* amat, double2* scratch, int* status, hipStream_t st);
+// From S = -(R + lam I)^-1 as launch_sweep_inverse leaves it, the block
+// filters W = (I + lam S)[off_b rows] (w64 [mat][B][Wn]; offsets indexed by
+// mat % nb) and, with negate, A^-1 = -S in place.
+hipError_t launch_large_filters(long long nmat, double2* amat, const int* offsets, int B, int Wn,
+                                int nb, double lam, double2* w64, bool negate, hipStream_t st);
+// Push-through estimate of windows wider than kMaxSampleWindowLarge: work
+// area pushthrough_bytes(d, nmat) = amat [nmat][M][M] then sweep scratch.
+size_t pushthrough_bytes(const lmmse_plan_desc& d, long long nmat);
+hipError_t launch_sample_pushthrough(const Plan& p, long long nmat, long long mat0, const float2* hls,
+                                     double lam, double2* amat, double2* scratch, float2* out,
+                                     hipStream_t st);
+// Caller correlation (LMMSE_R_USER_R): windows of the N x N matrix into
+// p.rwin, then the block filters from p.rwin at lam = sigma2 / K.
+hipError_t launch_user_corr_gather(Plan& p, const double2* r, hipStream_t st);
+hipError_t launch_user_corr_design(Plan& p, double sigma2, hipStream_t st);
+size_t user_corr_scratch_bytes(const lmmse_plan_desc& d);
 // Workspace-resident sample design of nmat windows: amat [nmat][Wn][Wn] and
 // scratch (sweep_scratch_bytes) are device work areas; w64 / w32 / whi, wlo
 // may be null; with want_ainv amat ends as A^-1.

@@ -55,14 +55,15 @@ int validate(const lmmse_plan_desc* d) {
     if (d->M < 1 || d->K < 1 || d->N < 1 || d->N_fft < d->N || d->B < 1 || d->Wn < 1 ||
         d->max_slots < 1)
         return LMMSE_ERR_INVALID_ARG;
-    if (d->rsource < LMMSE_R_UNIFORM || d->rsource > LMMSE_R_USER) return LMMSE_ERR_INVALID_ARG;
+    if (d->rsource < LMMSE_R_UNIFORM || d->rsource > LMMSE_R_USER_R) return LMMSE_ERR_INVALID_ARG;
     if (d->precision < LMMSE_FP32 || d->precision > LMMSE_FP16X3) return LMMSE_ERR_INVALID_ARG;
     if (d->rsource == LMMSE_R_EXPONENTIAL &&
         (d->taps < 1 || d->taps > d->N_fft || !(d->tau_rms > 0.0) || !std::isfinite(d->tau_rms)))
         return LMMSE_ERR_INVALID_ARG;
     if (d->rsource == LMMSE_R_UNIFORM && (!(d->L > 0.0) || !std::isfinite(d->L)))
         return LMMSE_ERR_INVALID_ARG;
-    if ((d->rsource == LMMSE_R_UNIFORM || d->rsource == LMMSE_R_EXPONENTIAL) &&
+    if ((d->rsource == LMMSE_R_UNIFORM || d->rsource == LMMSE_R_EXPONENTIAL ||
+         d->rsource == LMMSE_R_USER_R) &&
         (!(d->sigma2 > 0.0) || !std::isfinite(d->sigma2)))
         return LMMSE_ERR_INVALID_ARG;
     if (d->K > kMaxK) return LMMSE_ERR_UNSUPPORTED;
@@ -71,7 +72,11 @@ int validate(const lmmse_plan_desc* d) {
     if (d->Wn > kMaxWindow) return LMMSE_ERR_UNSUPPORTED;
     const long long cols = (long long)d->max_slots * d->M * d->K;
     if (cols * d->N >= (1LL << 40)) return LMMSE_ERR_UNSUPPORTED;
-    if (d->rsource == LMMSE_R_SAMPLE && d->Wn > kMaxSampleWindowLarge) return LMMSE_ERR_UNSUPPORTED;
+    // windows wider than the workspace-resident design: the push-through form
+    // (M x M systems), FP32 product only
+    if (d->rsource == LMMSE_R_SAMPLE && d->Wn > kMaxSampleWindowLarge &&
+        (d->M > kMaxPushthroughAntennas || d->precision != LMMSE_FP32))
+        return LMMSE_ERR_UNSUPPORTED;
     return LMMSE_OK;
 }
 
@@ -93,6 +98,8 @@ void choose_row_tiles(int B, int max_rt, int& RT, int& rgroups) {
 }
 
 bool fixed_source(int rs) { return rs == LMMSE_R_UNIFORM || rs == LMMSE_R_EXPONENTIAL; }
+// sources whose filters the plan designs from a correlation it holds
+bool designed_source(int rs) { return fixed_source(rs) || rs == LMMSE_R_USER_R; }
 
 template <typename T>
 int dev_alloc(T*& p, size_t count) {
@@ -107,9 +114,9 @@ int dev_alloc(T*& p, size_t count) {
 
 void free_plan(lmmse_plan* p) {
     if (!p) return;
-    void* ptrs[] = {p->d_starts, p->d_classes, p->d_offsets, p->d_bstarts, p->d_class_off, p->w64, p->ainv, p->rd,
-                    p->wf32,     p->whi,       p->wlo,         p->twiddle, p->status,
-                    p->dscal};
+    void* ptrs[] = {p->d_starts, p->d_classes, p->d_offsets, p->d_bstarts, p->d_class_off, p->w64,
+                    p->ainv,     p->rwin,      p->dwork,     p->rd,        p->wf32,      p->whi,
+                    p->wlo,      p->twiddle,   p->status,    p->dscal};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     delete p;
@@ -167,7 +174,7 @@ const char* lmmse_status_string(int s) {
     }
 }
 
-int lmmse_version(void) { return 10000; }
+int lmmse_version(void) { return 10100; }
 
 int lmmse_plan_validate(const lmmse_plan_desc* desc) { return validate(desc); }
 
@@ -210,6 +217,11 @@ int lmmse_plan_create(const lmmse_plan_desc* desc, lmmse_plan_t* out) {
                     p->h_class_off);
     p->nb = desc->N / desc->B;
     p->halo = (desc->Wn - desc->B) / 2;
+    if (desc->rsource == LMMSE_R_USER_R) {
+        // a caller correlation need not be Toeplitz: one filter per block
+        p->h_class_off = p->h_offsets;
+        for (int b = 0; b < p->nb; ++b) p->h_classes[b] = b;
+    }
     p->n_classes = (int)p->h_class_off.size();
     // split-precision kernels double-buffer three filter parts in LDS: RT <= 13
     choose_row_tiles(desc->B, desc->precision == LMMSE_FP32 ? 17 : 13, p->RT, p->rgroups);
@@ -234,8 +246,9 @@ int lmmse_plan_create(const lmmse_plan_desc* desc, lmmse_plan_t* out) {
         (rc = dev_alloc(p->rd, 3 * (size_t)Wn)))
         return fail(rc);
     if (has_bank) {
+        const size_t ainv_mats = desc->rsource == LMMSE_R_USER_R ? (size_t)p->nb : 1;
         if ((rc = dev_alloc(p->w64, (size_t)p->n_classes * desc->B * Wn)) ||
-            (rc = dev_alloc(p->ainv, (size_t)Wn * Wn)) ||
+            (rc = dev_alloc(p->ainv, ainv_mats * Wn * Wn)) ||
             (rc = dev_alloc(p->wf32, fixed_bank_f32_elems(*p))))
             return fail(rc);
         if (desc->precision != LMMSE_FP32 &&
@@ -243,6 +256,10 @@ int lmmse_plan_create(const lmmse_plan_desc* desc, lmmse_plan_t* out) {
              (rc = dev_alloc(p->wlo, split_bank_elems(*p)))))
             return fail(rc);
     }
+    if (desc->rsource == LMMSE_R_USER_R &&
+        ((rc = dev_alloc(p->rwin, (size_t)p->nb * Wn * Wn)) ||
+         (rc = dev_alloc(p->dwork, user_corr_scratch_bytes(*desc) / sizeof(double2)))))
+        return fail(rc);
     std::vector<float2> tw(K);
     for (int r = 0; r < K; ++r) {
         const double a = 2.0 * M_PI * r / K;
@@ -264,6 +281,9 @@ int lmmse_plan_create(const lmmse_plan_desc* desc, lmmse_plan_t* out) {
         const size_t bytes = fixed_bank_f32_elems(*p) * sizeof(float4);
         if (hipMemset(p->wf32, 0, bytes) != hipSuccess) return fail(LMMSE_ERR_HIP);
     }
+    // r_d is not used by a caller correlation: zero, so that the design
+    // backward's r_d terms vanish
+    if (hipMemset(p->rd, 0, 3 * (size_t)Wn * sizeof(double2)) != hipSuccess) return fail(LMMSE_ERR_HIP);
     if (fixed_source(desc->rsource)) {
         if (launch_fixed_design(*p, desc->tau_rms, desc->sigma2, 0) != hipSuccess ||
             hipDeviceSynchronize() != hipSuccess)
@@ -301,6 +321,17 @@ int lmmse_set_design(lmmse_plan_t plan, double tau_rms, double sigma2, void* str
         plan->design_sigma2 = sigma2;
         return LMMSE_OK;
     }
+    if (plan->d.rsource == LMMSE_R_USER_R) {
+        // only the noise variance; redesigned from the caller's correlation
+        // once one has been set
+        if (!(sigma2 > 0.0) || !std::isfinite(sigma2)) return LMMSE_ERR_INVALID_ARG;
+        plan->design_sigma2 = sigma2;
+        if (plan->have_corr) {
+            LMMSE_HIP_TRY(launch_user_corr_design(*plan, sigma2, (hipStream_t)stream));
+            plan->ready = true;
+        }
+        return LMMSE_OK;
+    }
     if (!fixed_source(plan->d.rsource)) return LMMSE_ERR_UNSUPPORTED;
     if (!(sigma2 > 0.0) || !std::isfinite(sigma2)) return LMMSE_ERR_INVALID_ARG;
     if (plan->d.rsource == LMMSE_R_EXPONENTIAL && (!(tau_rms > 0.0) || !std::isfinite(tau_rms)))
@@ -319,6 +350,16 @@ int lmmse_set_filters(lmmse_plan_t plan, const void* w, void* stream) {
     const size_t bytes = (size_t)plan->n_classes * plan->d.B * plan->d.Wn * sizeof(double2);
     LMMSE_HIP_TRY(hipMemcpyAsync(plan->w64, w, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream));
     LMMSE_HIP_TRY(launch_pack_banks(*plan, (hipStream_t)stream));
+    plan->ready = true;
+    return LMMSE_OK;
+}
+
+int lmmse_set_correlation(lmmse_plan_t plan, const void* r, void* stream) {
+    if (!plan || !r) return LMMSE_ERR_INVALID_ARG;
+    if (plan->d.rsource != LMMSE_R_USER_R) return LMMSE_ERR_UNSUPPORTED;
+    LMMSE_HIP_TRY(launch_user_corr_gather(*plan, (const double2*)r, (hipStream_t)stream));
+    LMMSE_HIP_TRY(launch_user_corr_design(*plan, plan->design_sigma2, (hipStream_t)stream));
+    plan->have_corr = true;
     plan->ready = true;
     return LMMSE_OK;
 }
@@ -363,7 +404,6 @@ int lmmse_apply(lmmse_plan_t plan, int slots, const void* h_ls, void* h_hat, voi
 
 int lmmse_covariance(lmmse_plan_t plan, int slots, const void* h_ls, void* r_win, void* stream) {
     if (!plan || slots < 0 || slots > plan->d.max_slots) return LMMSE_ERR_INVALID_ARG;
-    if (plan->d.Wn > kMaxSampleWindowLarge) return LMMSE_ERR_UNSUPPORTED;
     if (slots == 0) return LMMSE_OK;
     if (!h_ls || !r_win) return LMMSE_ERR_INVALID_ARG;
     LMMSE_HIP_TRY(launch_covariance(*plan, slots, (const float2*)h_ls, (double2*)r_win,
@@ -371,16 +411,45 @@ int lmmse_covariance(lmmse_plan_t plan, int slots, const void* h_ls, void* r_win
     return LMMSE_OK;
 }
 
+int lmmse_sample_filters_workspace_size(const lmmse_plan_desc* desc, int slots, size_t* bytes) {
+    const int v = validate(desc);
+    if (v != LMMSE_OK) return v;
+    if (!bytes || slots < 0 || slots > desc->max_slots) return LMMSE_ERR_INVALID_ARG;
+    const long long nmat = (long long)slots * desc->K * (desc->N / desc->B);
+    *bytes = desc->Wn <= kMaxSampleWindowReg
+                 ? 0
+                 : (size_t)nmat * desc->Wn * desc->Wn * sizeof(double2) +
+                       sweep_scratch_bytes(desc->Wn, nmat);
+    return LMMSE_OK;
+}
+
 int lmmse_sample_filters(lmmse_plan_t plan, int slots, const void* r_win, double sigma2,
-                         void* w_out, void* stream) {
+                         void* w_out, void* ws, size_t ws_bytes, void* stream) {
     if (!plan || slots < 0 || slots > plan->d.max_slots) return LMMSE_ERR_INVALID_ARG;
     if (!(sigma2 >= 0.0) || !std::isfinite(sigma2)) return LMMSE_ERR_INVALID_ARG;
-    if (plan->d.Wn > kMaxSampleWindowReg) return LMMSE_ERR_UNSUPPORTED;
     if (slots == 0) return LMMSE_OK;
     if (!r_win || !w_out) return LMMSE_ERR_INVALID_ARG;
-    const int nmat = slots * plan->d.K * plan->nb;
-    LMMSE_HIP_TRY(launch_batched_filters(*plan, nmat, nullptr, nullptr, (const double2*)r_win,
-                                         sigma2 / plan->d.K, (double2*)w_out, (hipStream_t)stream));
+    const hipStream_t st = (hipStream_t)stream;
+    const long long nmat = (long long)slots * plan->d.K * plan->nb;
+    const double lam = sigma2 / plan->d.K;
+    if (plan->d.Wn <= kMaxSampleWindowReg) {
+        LMMSE_HIP_TRY(launch_batched_filters(*plan, nmat, (const double2*)r_win, lam, (double2*)w_out,
+                                             nullptr, st));
+        return LMMSE_OK;
+    }
+    // wider windows: the panel sweep of a copy of the windows in ws
+    size_t need = 0;
+    lmmse_sample_filters_workspace_size(&plan->d, slots, &need);
+    if (!ws || ws_bytes < need) return LMMSE_ERR_WORKSPACE;
+    const int Wn = plan->d.Wn;
+    double2* amat = (double2*)ws;
+    double2* scratch = amat + nmat * Wn * Wn;
+    LMMSE_HIP_TRY(hipMemcpyAsync(amat, r_win, (size_t)nmat * Wn * Wn * sizeof(double2),
+                                 hipMemcpyDeviceToDevice, st));
+    LMMSE_HIP_TRY(launch_sweep_inverse(nmat, 0, Wn, plan->d.K, plan->nb, lam, amat, scratch,
+                                       plan->status, st));
+    LMMSE_HIP_TRY(launch_large_filters(nmat, amat, plan->d_offsets, plan->d.B, Wn, plan->nb, lam,
+                                       (double2*)w_out, false, st));
     return LMMSE_OK;
 }
 
@@ -400,7 +469,7 @@ int lmmse_estimate(lmmse_plan_t plan, int slots, const void* y, const void* pilo
                                              (char*)ws + hls_bytes(plan->d, slots), st));
         return LMMSE_OK;
     }
-    if (fixed_source(plan->d.rsource) && sigma2 != plan->design_sigma2) {
+    if (designed_source(plan->d.rsource) && sigma2 != plan->design_sigma2) {
         const int rc = lmmse_set_design(plan, plan->design_tau, sigma2, stream);
         if (rc != LMMSE_OK) return rc;
     }
@@ -429,7 +498,7 @@ int lmmse_estimate_ls(lmmse_plan_t plan, int slots, const void* h_ls, double sig
                                              st));
         return LMMSE_OK;
     }
-    if (fixed_source(plan->d.rsource) && sigma2 != plan->design_sigma2) {
+    if (designed_source(plan->d.rsource) && sigma2 != plan->design_sigma2) {
         const int rc = lmmse_set_design(plan, plan->design_tau, sigma2, stream);
         if (rc != LMMSE_OK) return rc;
     }
@@ -441,10 +510,16 @@ int lmmse_backward(lmmse_plan_t plan, int slots, const void* h_ls, const void* g
                    double* d_tau, double* d_sigma2, void* ws, size_t ws_bytes, void* stream) {
     if (!plan || slots < 0 || slots > plan->d.max_slots) return LMMSE_ERR_INVALID_ARG;
     if (slots > 0 && (!h_ls || !g || !d_hls)) return LMMSE_ERR_INVALID_ARG;
+    const bool want = d_tau || d_sigma2;
+    // windows wider than 256: no gradient through the sample covariance, and
+    // no design-parameter gradients of the designed filters (dX alone is
+    // supported for fixed, caller-correlation and caller filters)
+    if (plan->d.Wn > kMaxSampleWindowLarge &&
+        (plan->d.rsource == LMMSE_R_SAMPLE || (want && plan->d.rsource != LMMSE_R_USER)))
+        return LMMSE_ERR_UNSUPPORTED;
     const size_t need = backward_workspace_bytes(plan->d, slots);
     if (need && (!ws || ws_bytes < need)) return LMMSE_ERR_WORKSPACE;
     const hipStream_t st = (hipStream_t)stream;
-    const bool want = d_tau || d_sigma2;
     double h[4] = {NAN, NAN, NAN, NAN};
     if (plan->d.rsource == LMMSE_R_SAMPLE) {
         LMMSE_HIP_TRY(launch_backward_sample(*plan, slots, (const float2*)h_ls, (const float2*)g,

@@ -483,11 +483,12 @@ hipError_t launch_covariance(const Plan& p, int slots, const float2* hls, double
     return launch_sample_design(p, (long long)slots * p.d.K * p.nb, sa, st);
 }
 
-hipError_t launch_batched_filters(const Plan& p, int nmat, double2*, double2*, const double2* r_win,
-                                  double lam, double2* w_out, hipStream_t st) {
+hipError_t launch_batched_filters(const Plan& p, long long nmat, const double2* r_win, double lam,
+                                  double2* w_out, double2* ainv, hipStream_t st) {
     SampleArgs sa = base_args(p, lam);
     sa.r_in = r_win;
     sa.w64 = w_out;
+    sa.ainv = ainv;
     sa.want_w = 1;
     return launch_sample_design(p, nmat, sa, st);
 }
@@ -511,7 +512,8 @@ hipError_t launch_sample_inverse(const Plan& p, long long nmat, long long mat0, 
 // up to 2 GiB of window matrices at a time, at least one slot.
 static int large_chunk(const lmmse_plan_desc& d, int slots) {
     if (slots <= 0) return 0;
-    const size_t per = large_design_bytes(d, (long long)d.K * (d.N / d.B));
+    const long long ms = (long long)d.K * (d.N / d.B);
+    const size_t per = d.Wn > kMaxSampleWindowLarge ? pushthrough_bytes(d, ms) : large_design_bytes(d, ms);
     const size_t c = per ? ((size_t)2 << 30) / per : (size_t)slots;
     return (int)std::min<size_t>(std::max<size_t>(c, 1), (size_t)slots);
 }
@@ -528,8 +530,13 @@ static size_t filter_area_bytes(const lmmse_plan_desc& d, long long nmat) {
 
 size_t sample_workspace_bytes(const lmmse_plan_desc& d, int slots) {
     // H_LS, the compact filters of every (slot, user, block), and for wide
-    // windows the design work area of one chunk of slots
+    // windows the design work area of one chunk of slots; windows wider than
+    // the workspace-resident design: H_LS and the push-through work area of
+    // one chunk of slots
     const size_t hls = hls_bytes(d, slots);
+    if (d.Wn > kMaxSampleWindowLarge)
+        return slots > 0 ? hls + pushthrough_bytes(d, (long long)large_chunk(d, slots) * d.K * (d.N / d.B))
+                         : 0;
     const size_t w = filter_area_bytes(d, (long long)slots * d.K * (d.N / d.B));
     size_t big = 0;
     if (d.Wn > kMaxSampleWindowReg && slots > 0)
@@ -547,6 +554,21 @@ hipError_t launch_sample_estimate(const Plan& p, int slots, const float2* hls, d
     uint32_t* whi = split ? reinterpret_cast<uint32_t*>(ws) : nullptr;
     uint32_t* wlo = split ? whi + nmat * p.d.B * wq : nullptr;
     hipError_t e;
+    if (p.d.Wn > kMaxSampleWindowLarge) {   // push-through form, FP32 product
+        const int chunk = large_chunk(p.d, slots);
+        const long long cm = (long long)chunk * p.d.K * p.nb;
+        double2* amat = reinterpret_cast<double2*>(ws);
+        double2* scratch = amat + cm * p.d.M * p.d.M;
+        const long long per_slot = (long long)p.d.M * p.d.K * p.d.N;
+        for (int s0 = 0; s0 < slots; s0 += chunk) {
+            const int ns = std::min(chunk, slots - s0);
+            e = launch_sample_pushthrough(p, (long long)ns * p.d.K * p.nb, (long long)s0 * p.d.K * p.nb,
+                                          hls + s0 * per_slot, lam, amat, scratch, out + s0 * per_slot,
+                                          st);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
     if (p.d.Wn > kMaxSampleWindowReg) {
         const int chunk = large_chunk(p.d, slots);
         const long long cm = (long long)chunk * p.d.K * p.nb;

@@ -1,5 +1,6 @@
 // Sample-covariance design for windows wider than the register-resident sweep
-// of sample.hip holds (160 < Wn <= 256).  The window matrix lives in the
+// of sample.hip holds (160 < Wn <= 256), and the batched inverse it uses
+// (also for the caller-correlation design and the push-through form).  The window matrix lives in the
 // workspace as FP64 [mat][Wn][Wn] (both triangles):
 //
 //   1. R = X X^H / M with X = h_ls[s, :, k, I_b]^T: a batched GEMM with FP64
@@ -54,6 +55,7 @@ __global__ __launch_bounds__(kSwT) void sweep_panel_kernel(double2* a, double2* 
                                                            long long mat0) {
     static_assert(kPW == 64 && kSwW * kSwE == 64, "thread layout");
     __shared__ double2 rowb[2][kPW], colb[2][kPW];
+    __shared__ double2 tsym[kPW][kPW + 1];   // the block, for its Hermitian part
     const long long mat = blockIdx.x;
     double2* am = a + mat * Wn * Wn;
     const int tid = threadIdx.x, w = __builtin_amdgcn_readfirstlane(tid >> 6), j = tid & 63;
@@ -123,6 +125,19 @@ __global__ __launch_bounds__(kSwT) void sweep_panel_kernel(double2* a, double2* 
             }
         }
     }
+    // -A_KK^-1 is Hermitian, but the sweep's rounding is not: the panel
+    // product stores A_KR = F^H = (P dsw)^H, which is A_KK^-1 A_KR only for a
+    // Hermitian dsw, and the skew part of the rounding grows from panel to
+    // panel (a CPU model of a 1200-wide window lost 10 digits over 19
+    // panels).  The block is therefore replaced by its Hermitian part.
+#pragma unroll
+    for (int u = 0; u < kSwE; ++u) tsym[w + kSwW * u][j] = r[u];
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kSwE; ++u) {
+        const double2 t = tsym[j][w + kSwW * u];
+        r[u] = make_double2(0.5 * (r[u].x + t.x), 0.5 * (r[u].y - t.y));
+    }
     double2* dm = dsw + mat * kPW * kPW;
 #pragma unroll
     for (int u = 0; u < kSwE; ++u) {
@@ -163,6 +178,74 @@ __global__ __launch_bounds__(256) void large_filters_kernel(double2* a, const in
     }
 }
 
+// A -> -A^-1 of nmat Hermitian n x n matrices [mat][n][n] (both triangles)
+// after adding lam to their diagonals: the panel sweep described at the top
+// of this file.  The batch index decomposes as (slot * K + user) * nb +
+// block, as in every batched product here (only the strides depend on it).
+// scratch: sweep_scratch_bytes(n, nmat).  A non-positive pivot records
+// LMMSE_ERR_NOT_PD with matrix mat0 + mat in status.
+hipError_t launch_sweep_inverse(long long nmat, long long mat0, int n, int K, int nb, double lam,
+                                double2* amat, double2* scratch, int* status, hipStream_t st) {
+    if (nmat == 0) return hipSuccess;
+    hipError_t e;
+    hipLaunchKernelGGL(add_diag_kernel, dim3((unsigned)nmat), dim3(256), 0, st, amat, n, lam);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    ZGemmArgs ga{};
+    ga.K = K;
+    ga.nb = nb;
+    const long long per = (long long)n * n;
+    // scratch: P [nmat][n][kPW], then -A_KK^-1 [nmat][kPW][kPW]
+    double2* pold = scratch;
+    double2* dsw = pold + nmat * n * kPW;
+    const long long pp = (long long)n * kPW, dd = (long long)kPW * kPW;
+    for (int k0 = 0; k0 < n; k0 += kPW) {
+        const int kw = std::min(kPW, n - k0);
+        hipLaunchKernelGGL(sweep_panel_kernel, dim3((unsigned)nmat), dim3(kSwT), 0, st, amat, dsw,
+                           pold, n, k0, kw, status, mat0);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        // F = P A_KK^-1 = -P dsw, stored in place as A_RK = F (the panel's
+        // columns) and A_KR = F^H (its rows).  Rows of K vanish with P's: the
+        // panel's tile row is left out, which keeps A_KK as the sweep wrote it.
+        ga.skip_tile = k0 / kPW;
+        ga.A = ZView{pold, kPW, 1, pp * nb * K, pp * nb, pp, nullptr, 0};
+        ga.B = ZView{dsw, kPW, 1, dd * nb * K, dd * nb, dd, nullptr, 0};
+        ga.C = ZView{amat + k0, n, 1, per * nb * K, per * nb, per, nullptr, 0};
+        ga.T = ZView{amat + (long long)k0 * n, n, 1, per * nb * K, per * nb, per, nullptr, 0};
+        ga.tcopy = 1;
+        ga.m = n;
+        ga.n = kw;
+        ga.kd = kw;
+        ga.alpha = -1.0;
+        ga.beta = 0;
+        ga.herm = 0;
+        if ((e = zgemm<double2, double2, double2>(ga, nmat, st)) != hipSuccess) return e;
+        ga.tcopy = 0;
+        // A += (-1) F P^H over the matrix but the panel's tile row and column,
+        // where F P^H vanishes (F and P are zero on the panel's rows); F is
+        // read from the panel's columns, which this product does not write
+        ga.A = ZView{amat + k0, n, 1, per * nb * K, per * nb, per, nullptr, 0};
+        ga.B = ZView{pold, 1, kPW, pp * nb * K, pp * nb, pp, nullptr, 1};
+        ga.C = ZView{amat, n, 1, per * nb * K, per * nb, per, nullptr, 0};
+        ga.m = n;
+        ga.n = n;
+        ga.kd = kw;
+        ga.alpha = -1.0;
+        ga.beta = 1;
+        ga.herm = 1;   // F P^H = A_RK A_KK^-1 A_RK^H is Hermitian
+        if ((e = zgemm<double2, double2, double2>(ga, nmat, st)) != hipSuccess) return e;
+        ga.skip_tile = -1;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_large_filters(long long nmat, double2* amat, const int* offsets, int B, int Wn,
+                                int nb, double lam, double2* w64, bool negate, hipStream_t st) {
+    if (nmat == 0) return hipSuccess;
+    hipLaunchKernelGGL(large_filters_kernel, dim3((unsigned)nmat), dim3(256), 0, st, amat, offsets, B,
+                       Wn, nb, lam, w64, nullptr, nullptr, nullptr, 0, negate ? 1 : 0);
+    return hipGetLastError();
+}
+
 size_t sweep_scratch_bytes(int Wn, long long nmat) {
     return (size_t)nmat * ((size_t)Wn * kPW + (size_t)kPW * kPW) * sizeof(double2);
 }
@@ -197,49 +280,9 @@ hipError_t launch_sample_large(const Plan& p, long long nmat, long long mat0, co
     ga.herm = 1;
     if ((e = zgemm<float2, float2, double2>(ga, nmat, st)) != hipSuccess) return e;
     ga.herm = 0;
-    hipLaunchKernelGGL(add_diag_kernel, dim3((unsigned)nmat), dim3(256), 0, st, amat, Wn, lam);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    // scratch: P [nmat][Wn][kPW], then -A_KK^-1 [nmat][kPW][kPW]
-    double2* pold = scratch;
-    double2* dsw = pold + nmat * Wn * kPW;
-    const long long pp = (long long)Wn * kPW, dd = (long long)kPW * kPW;
-    for (int k0 = 0; k0 < Wn; k0 += kPW) {
-        const int kw = std::min(kPW, Wn - k0);
-        hipLaunchKernelGGL(sweep_panel_kernel, dim3((unsigned)nmat), dim3(kSwT), 0, st, amat, dsw,
-                           pold, Wn, k0, kw, p.status, mat0);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        // F = P A_KK^-1 = -P dsw, stored in place as A_RK = F (the panel's
-        // columns) and A_KR = F^H (its rows).  Rows of K vanish with P's: the
-        // panel's tile row is left out, which keeps A_KK as the sweep wrote it.
-        ga.skip_tile = k0 / kPW;
-        ga.A = ZView{pold, kPW, 1, pp * p.nb * d.K, pp * p.nb, pp, nullptr, 0};
-        ga.B = ZView{dsw, kPW, 1, dd * p.nb * d.K, dd * p.nb, dd, nullptr, 0};
-        ga.C = ZView{amat + k0, Wn, 1, per * p.nb * d.K, per * p.nb, per, nullptr, 0};
-        ga.T = ZView{amat + (long long)k0 * Wn, Wn, 1, per * p.nb * d.K, per * p.nb, per, nullptr, 0};
-        ga.tcopy = 1;
-        ga.m = Wn;
-        ga.n = kw;
-        ga.kd = kw;
-        ga.alpha = -1.0;
-        ga.beta = 0;
-        ga.herm = 0;
-        if ((e = zgemm<double2, double2, double2>(ga, nmat, st)) != hipSuccess) return e;
-        ga.tcopy = 0;
-        // A += (-1) F P^H over the window but the panel's tile row and column,
-        // where F P^H vanishes (F and P are zero on the panel's rows); F is
-        // read from the panel's columns, which this product does not write
-        ga.A = ZView{amat + k0, Wn, 1, per * p.nb * d.K, per * p.nb, per, nullptr, 0};
-        ga.B = ZView{pold, 1, kPW, pp * p.nb * d.K, pp * p.nb, pp, nullptr, 1};
-        ga.C = ZView{amat, Wn, 1, per * p.nb * d.K, per * p.nb, per, nullptr, 0};
-        ga.m = Wn;
-        ga.n = Wn;
-        ga.kd = kw;
-        ga.alpha = -1.0;
-        ga.beta = 1;
-        ga.herm = 1;   // F P^H = A_RK A_KK^-1 A_RK^H is Hermitian
-        if ((e = zgemm<double2, double2, double2>(ga, nmat, st)) != hipSuccess) return e;
-        ga.skip_tile = -1;
-    }
+    if ((e = launch_sweep_inverse(nmat, mat0, Wn, d.K, p.nb, lam, amat, scratch, p.status, st)) !=
+        hipSuccess)
+        return e;
     hipLaunchKernelGGL(large_filters_kernel, dim3((unsigned)nmat), dim3(256), 0, st, amat,
                        p.d_offsets, d.B, Wn, p.nb, lam, w64, w32, whi, wlo,
                        d.precision == LMMSE_FP16X3 ? 1 : 0, want_ainv ? 1 : 0);

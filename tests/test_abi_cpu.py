@@ -54,6 +54,11 @@ def _d(**kw):
     dict(precision="fp16x3"),
     dict(M=8, K=2, N=72, N_fft=128, B=12, Wn=12, taps=8, tau_rms=2.0),
     dict(M=256, K=24, N=3300, N_fft=4096, B=132, Wn=198, taps=144, tau_rms=32.0, max_slots=32),
+    # full band of the paper-sized system: fixed, sample (push-through), caller R
+    dict(B=1200, Wn=1200, rsource="uniform", L=144.0), dict(rsource="sample", B=1200, Wn=1200),
+    dict(rsource="sample", B=300, Wn=300), dict(rsource="sample", B=100, Wn=300),
+    dict(rsource="user_r"), dict(rsource="user_r", B=1200, Wn=1200),
+    dict(rsource="user_r", precision="bf16x3"),
 ])
 def test_validate_accepts_workloads(lib, kw):
     d = _d(**kw)
@@ -69,8 +74,11 @@ def test_validate_accepts_workloads(lib, kw):
     (dict(rsource="uniform", L=-1.0), _lib.INVALID_ARG),
     (dict(B=7), _lib.UNSUPPORTED), (dict(Wn=151), _lib.UNSUPPORTED), (dict(Wn=80), _lib.UNSUPPORTED),
     (dict(Wn=1300), _lib.UNSUPPORTED), (dict(K=65), _lib.UNSUPPORTED),
-    (dict(rsource="sample", B=300, Wn=300), _lib.UNSUPPORTED),
-    (dict(rsource="sample", B=100, Wn=300), _lib.UNSUPPORTED),
+    # push-through windows: FP32 only, M <= 256
+    (dict(rsource="sample", B=300, Wn=300, precision="bf16x3"), _lib.UNSUPPORTED),
+    (dict(rsource="sample", B=1200, Wn=1200, precision="fp16x3"), _lib.UNSUPPORTED),
+    (dict(rsource="sample", B=1200, Wn=1200, M=300), _lib.UNSUPPORTED),
+    (dict(rsource=5), _lib.INVALID_ARG), (dict(rsource="user_r", sigma2=0.0), _lib.INVALID_ARG),
 ])
 def test_validate_rejects(lib, kw, code):
     d = _d(**kw)
@@ -151,7 +159,9 @@ def test_plan_create_without_device_fails_cleanly(lib):
 
 def test_sample_window_limits():
     """The sample design holds windows up to 256 (registers up to 160, then the
-    workspace-resident sweep); wider windows are rejected on the host."""
+    workspace-resident sweep); wider windows take the push-through form, whose
+    work area is M x M per window (refused above 256 antennas or in split
+    precision)."""
     d = _d(rsource="sample", N=3300, N_fft=4096, B=132, Wn=198, K=24, M=256, max_slots=32)
     need = workspace_size(d, 32)
     # at least H_LS, the FP32 filters and one slot of FP64 window matrices
@@ -161,7 +171,12 @@ def test_sample_window_limits():
     assert need < 32 * 256 * 24 * 3300 * 8 + 32 * nmat1 * 132 * 198 * 8 + (3 << 30) \
         + 32 * nmat1 * 8 + (1 << 20)
     with pytest.raises(_lib.LmmseError):
-        workspace_size(_d(rsource="sample", N=1040, B=130, Wn=260), 1)
+        workspace_size(_d(rsource="sample", N=1040, B=130, Wn=260, precision="bf16x3"), 1)
+    # full band of 64 paper-sized slots: H_LS plus M x M FP64 matrices and the
+    # sweep scratch of every (slot, user), no Wn x Wn matrix
+    fb = workspace_size(_d(rsource="sample", B=1200, Wn=1200), 64)
+    nmat = 64 * 12
+    assert fb == 64 * 128 * 12 * 1200 * 8 + nmat * 128 * 128 * 16 + nmat * (128 * 64 + 64 * 64) * 16
 
 
 @pytest.mark.parametrize("kw,code", [
