@@ -65,6 +65,15 @@
  * hi*hi + hi*lo + lo*hi with FP32 accumulation in BF16 (LMMSE_BF16X3) or
  * FP16 (LMMSE_FP16X3); the sample-covariance path writes each window's
  * filter as hi / lo parts and filters with the same split products.
+ * FP16X3 range: the filtering kernels split s * h_ls, s the plan's
+ * power-of-two input scale (lmmse_set_input_scale, default 1), and undo s on
+ * the output (both exact); |s h_ls| must stay below 65504 and every filter
+ * entry below 32 (LMMSE filters are below 1; caller filters are checked).
+ * A value past either limit records LMMSE_ERR_RANGE (info -1) for
+ * lmmse_sync_status, and the affected outputs are not finite.  Below about
+ * 1.2e-4 the FP16 lo part turns subnormal and the split loses accuracy
+ * gradually, so s should bring the LS values to order one.  BF16X3 has the
+ * FP32 range; FP32 results do not depend on s.
  * The backward products are FP32 on the matrix cores (fixed designs), or
  * FP64 and FP32 batched products on the matrix cores (sample covariance).
  *
@@ -94,7 +103,8 @@ typedef enum lmmse_status {
     LMMSE_ERR_HIP = 4,           /* a HIP runtime call failed                */
     LMMSE_ERR_NOT_PD = 5,        /* R_II + lam I not positive definite       */
     LMMSE_ERR_NOT_READY = 6,     /* no filters designed or set yet           */
-    LMMSE_ERR_NO_DEVICE = 7      /* no usable gfx950 device                  */
+    LMMSE_ERR_NO_DEVICE = 7,     /* no usable gfx950 device                  */
+    LMMSE_ERR_RANGE = 8          /* a value outside the FP16 split range     */
 } lmmse_status;
 
 typedef enum lmmse_rsource {
@@ -199,6 +209,13 @@ int lmmse_set_filters(lmmse_plan_t plan, const void *w, void *stream);
  * lmmse_sync_status (info = block).  Errors: INVALID_ARG, UNSUPPORTED (not a
  * USER_R plan), HIP. */
 int lmmse_set_correlation(lmmse_plan_t plan, const void *r, void *stream);
+
+/* Power-of-two scale s of the LS values inside the split-precision
+ * filtering (see Precision above): the kernels split s * h_ls and multiply
+ * the output by 1/s, so the estimate is unchanged while its FP16 parts stay
+ * in range.  s = 2^e with -59 <= e <= 61, else INVALID_ARG.  Host only;
+ * applies to the launches that follow. */
+int lmmse_set_input_scale(lmmse_plan_t plan, double scale);
 
 /* Copies the current FP64 filters of a fixed-design or user plan to device
  * complex128 [n_classes][B][Wn] (n_classes = N/B for USER_R).  Asynchronous. */

@@ -16,7 +16,7 @@ P_double = ctypes.POINTER(ctypes.c_double)
 P_size_t = ctypes.POINTER(ctypes.c_size_t)
 
 # lmmse_status
-OK, INVALID_ARG, UNSUPPORTED, WORKSPACE, HIP, NOT_PD, NOT_READY, NO_DEVICE = range(8)
+OK, INVALID_ARG, UNSUPPORTED, WORKSPACE, HIP, NOT_PD, NOT_READY, NO_DEVICE, RANGE = range(9)
 # lmmse_rsource
 R_UNIFORM, R_EXPONENTIAL, R_SAMPLE, R_USER, R_USER_R = range(5)
 # lmmse_precision
@@ -70,6 +70,7 @@ PROTOTYPES = {
     "lmmse_sample_filters": (c_int, [c_void_p, c_int, c_void_p, c_double, c_void_p, c_void_p,
                                      c_size_t, c_void_p]),
     "lmmse_set_correlation": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "lmmse_set_input_scale": (c_int, [c_void_p, c_double]),
     "lmmse_estimate_ls": (c_int, [c_void_p, c_int, c_void_p, c_double, c_void_p, c_void_p,
                                   c_size_t, c_void_p]),
     "lmmse_estimate": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_double, c_void_p,

@@ -137,6 +137,11 @@ class Plan:
             raise ValueError(f"w must be a contiguous complex128 CUDA [{self.n_classes}, {d.B}, {d.Wn}] tensor")
         check(self._lib.lmmse_set_filters(self._h, _ptr(w), _stream_ptr(stream)), "lmmse_set_filters")
 
+    def set_input_scale(self, scale: float):
+        """Power-of-two scale of the LS values inside the split-precision
+        filtering (undone on the output)."""
+        check(self._lib.lmmse_set_input_scale(self._h, float(scale)), "lmmse_set_input_scale")
+
     def set_correlation(self, r: torch.Tensor, stream=None):
         """Caller correlation (rsource 'user_r'): r is a complex128 CUDA [N, N]
         Hermitian matrix; the plan designs one filter per block from it."""

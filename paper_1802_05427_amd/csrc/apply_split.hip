@@ -9,7 +9,11 @@
 // clear of the subnormal range, and the hi_W hi_X product uses 2^11 hi_W
 // (exact: a power-of-two scaling, formed in registers from hi_W), so the
 // accumulator holds 2^11 W X and one scale by 2^-11 at the store undoes it.
-// FP16 assumes |W| < 32 and |h_ls| < 65504.
+// FP16 needs |W| < 32 (checked when the bank is packed) and |s h_ls| < 65504
+// for the plan's power-of-two input scale s (the LS values are multiplied by
+// s before the split and the output by 1/s, both exact); a value past that
+// records LMMSE_ERR_RANGE in the plan's status word.  Below about 1.2e-4 the
+// FP16 lo part turns subnormal and the split loses precision gradually.
 //
 // The structure follows the FP32 kernel (apply_f32.hip): 4 waves x 3 column
 // tiles = 192 columns per workgroup, RT <= 13 16-row tiles of the real
@@ -38,8 +42,10 @@ struct SplitArgs {
     long long n_tiles;
     int N, B, Wn, G16, Rpad, nb, rgroups;
     int vec_store;
-    float invK;
-    float out_scale;
+    float invK;            // 1/K times the input scale (fused path)
+    float in_scale;        // input scale (unfused path)
+    float out_scale;       // 1 / input scale (FP16: times 2^-11)
+    int* status;           // plan status word (FP16 range reports)
 };
 
 // LS chunk parts in LDS, slot-major: 16-byte slot kq (complex rows
@@ -51,7 +57,7 @@ __device__ __forceinline__ int xw_at(int c, int r) { return 4 * ((r >> 2) * kXP 
 template <int KF, bool FP16>
 __device__ __forceinline__ void split_store_ls(const SplitArgs& a, int tid, int cc,
                                                const RawRegs<KF>& R, uint32_t* xh, uint32_t* xl,
-                                               const float2* pl) {
+                                               const float2* pl, bool& bad) {
     using CR = RawRegs<KF>;
 #pragma unroll
     for (int u = 0; u < CR::TX; ++u) {
@@ -60,7 +66,9 @@ __device__ __forceinline__ void split_store_ls(const SplitArgs& a, int tid, int 
         const int cq = i >> 4, r = i & 15;
         if constexpr (KF == 0) {
             uint32_t h, l;
-            split_c<FP16>(R.v[u][0], h, l);
+            const float2 v = make_float2(R.v[u][0].x * a.in_scale, R.v[u][0].y * a.in_scale);
+            if constexpr (FP16) bad |= !f16_in_range(v);
+            split_c<FP16>(v, h, l);
             xh[xw_at(cq, r)] = h;
             xl[xw_at(cq, r)] = l;
         } else {
@@ -71,6 +79,7 @@ __device__ __forceinline__ void split_store_ls(const SplitArgs& a, int tid, int 
             for (int k = 0; k < KF; ++k) {
                 float2 h = cmulc(z[k], pl[k * 16 + r]);
                 h = live ? make_float2(h.x * a.invK, h.y * a.invK) : make_float2(0.f, 0.f);
+                if constexpr (FP16) bad |= !f16_in_range(h);
                 uint32_t hh, ll;
                 split_c<FP16>(h, hh, ll);
                 xh[xw_at(cq * KF + k, r)] = hh;
@@ -101,12 +110,12 @@ template <int RT, int KF, bool FP16>
 __device__ __forceinline__ void split_step(const SplitCtx& x, int cc, float4* xh4, float4* xl4,
                                            float2* pl, float4* wcur, float4* wnext,
                                            floatx4 (&acc)[RT][kCT], RawRegs<KF>& raw,
-                                           PilotRegs<KF>& pr) {
+                                           PilotRegs<KF>& pr, bool& bad) {
     constexpr int NS = PilotRegs<KF>::NS;
     if constexpr (KF > 0)
         if (cc + 1 < x.nchunks) store_pil<KF>(pr, pl + ((cc + 1) & 1) * NS, x.tid);
     split_store_ls<KF, FP16>(x.a, x.tid, x.ch(cc), raw, reinterpret_cast<uint32_t*>(xh4),
-                             reinterpret_cast<uint32_t*>(xl4), pl + (cc & 1) * NS);
+                             reinterpret_cast<uint32_t*>(xl4), pl + (cc & 1) * NS, bad);
     if (cc + 1 < x.nchunks) load_raw<KF>(x.a, x.tid, x.ch(cc + 1), x.s0, x.c0, raw);
     __syncthreads();
     float4 bh[kCT], bl[kCT];
@@ -195,11 +204,13 @@ __global__ __launch_bounds__(kThreads, (split_min_blocks<RT, KF>())) void apply_
     load_raw<KF>(a, tid, x.ch(0), x.s0, x.c0, raw);
     wait_vm();
     __syncthreads();
+    bool bad = false;
     for (int cc = 0; cc < x.nchunks; cc += 2) {
-        split_step<RT, KF, FP16>(x, cc, xh4, xl4, pl, wA, wB, acc, raw, pr);
+        split_step<RT, KF, FP16>(x, cc, xh4, xl4, pl, wA, wB, acc, raw, pr, bad);
         if (cc + 1 < x.nchunks)
-            split_step<RT, KF, FP16>(x, cc + 1, xh4, xl4, pl, wB, wA, acc, raw, pr);
+            split_step<RT, KF, FP16>(x, cc + 1, xh4, xl4, pl, wB, wA, acc, raw, pr, bad);
     }
+    if constexpr (FP16) report_range(bad, a.status);
 
     const int l16 = x.l16, kq = x.kq;
     const bool vec = a.vec_store != 0;
@@ -272,8 +283,10 @@ hipError_t launch_apply_split(const Plan& p, int slots, const float2* x, const f
     a.Rpad = p.Rpad;
     a.nb = p.nb;
     a.rgroups = p.rgroups;
-    a.invK = 1.0f / (float)p.d.K;
-    a.out_scale = fp16 ? 1.0f / 2048.0f : 1.0f;
+    a.invK = p.in_scale / (float)p.d.K;
+    a.in_scale = p.in_scale;
+    a.out_scale = (fp16 ? 1.0f / 2048.0f : 1.0f) / p.in_scale;
+    a.status = p.status;
     a.vec_store = (((a.N | a.B) & 1) == 0 && ((uintptr_t)out & 15) == 0) ? 1 : 0;
     const long long ctiles = (a.ncols + kCols - 1) / kCols;
     a.n_tiles = ctiles * p.nb * p.rgroups;

@@ -227,9 +227,11 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_floa
 
 // Split parts of the real embedding: hi = round(x), lo = round(x - hi) in
 // BF16; FP16 stores lo = round(2^11 (x - hi)).
+// FP16 banks: the filtering kernel forms 2^11 hi, so every filter entry must
+// be below 32 in magnitude; a larger one records LMMSE_ERR_RANGE.
 __global__ void pack_split_kernel(const double2* __restrict__ w64, uint16_t* __restrict__ hi,
                                   uint16_t* __restrict__ lo, int n_classes, int B, int Wn, int G16, int RT, int rgroups,
-                                  int is_fp16) {
+                                  int is_fp16, int* status) {
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const int rows = RT * 16;
     const long long total = (long long)n_classes * G16 * rgroups * 4 * rows * 8;
@@ -247,6 +249,7 @@ __global__ void pack_split_kernel(const double2* __restrict__ w64, uint16_t* __r
     const int r = rg * rows + rr;
     const double x = wreal(w64 + (long long)c * B * Wn, B, Wn, r, 32 * g + 8 * kq + e);
     if (is_fp16) {
+        if (!(fabs(x) < 32.0) && atomicCAS(status, 0, LMMSE_ERR_RANGE) == 0) status[1] = -1;
         const _Float16 h = (_Float16)x;
         const _Float16 l = (_Float16)((x - (double)h) * 2048.0);
         hi[idx] = __builtin_bit_cast(uint16_t, h);
@@ -270,7 +273,7 @@ hipError_t launch_pack_banks(Plan& p, hipStream_t st) {
         const long long total = (long long)split_bank_elems(p);
         hipLaunchKernelGGL(pack_split_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
                            st, p.w64, p.whi, p.wlo, p.n_classes, B, Wn, p.G16, p.RT,
-                           p.rgroups, p.d.precision == LMMSE_FP16X3 ? 1 : 0);
+                           p.rgroups, p.d.precision == LMMSE_FP16X3 ? 1 : 0, p.status);
     }
     return hipGetLastError();
 }

@@ -58,6 +58,7 @@ struct Plan {
     double design_sigma2 = 0.0;
     double design_tau = 0.0;
     float lo_scale = 1.0f;       // split-bank lo scale (FP16: 2^11)
+    float in_scale = 1.0f;       // power-of-two scale of the LS values before a split
 };
 
 size_t fixed_bank_f32_elems(const Plan& p);    // float4 elements

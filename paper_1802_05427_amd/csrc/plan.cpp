@@ -170,6 +170,7 @@ const char* lmmse_status_string(int s) {
         case LMMSE_ERR_NOT_PD: return "matrix not positive definite";
         case LMMSE_ERR_NOT_READY: return "filters not designed or set";
         case LMMSE_ERR_NO_DEVICE: return "no gfx950 device";
+        case LMMSE_ERR_RANGE: return "value outside the FP16 split range";
         default: return "unknown status";
     }
 }
@@ -351,6 +352,15 @@ int lmmse_set_filters(lmmse_plan_t plan, const void* w, void* stream) {
     LMMSE_HIP_TRY(hipMemcpyAsync(plan->w64, w, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream));
     LMMSE_HIP_TRY(launch_pack_banks(*plan, (hipStream_t)stream));
     plan->ready = true;
+    return LMMSE_OK;
+}
+
+int lmmse_set_input_scale(lmmse_plan_t plan, double scale) {
+    if (!plan) return LMMSE_ERR_INVALID_ARG;
+    int e = 0;
+    if (!(scale > 0.0) || !std::isfinite(scale) || std::frexp(scale, &e) != 0.5 || e < -59 || e > 61)
+        return LMMSE_ERR_INVALID_ARG;
+    plan->in_scale = (float)scale;
     return LMMSE_OK;
 }
 

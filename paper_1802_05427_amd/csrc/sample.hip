@@ -101,6 +101,7 @@ __global__ __launch_bounds__(1024) void sample_design_kernel(SampleArgs a) {
     const int k = (int)(sk % a.K);
     const long long s = sk / a.K;
     const int st = a.starts[b];
+    double lam_s = a.lam, ainv_s = 1.0;   // lam and 1/alpha of the scaled sweep (below)
 
     double2 A[NE];
 #pragma unroll
@@ -168,10 +169,40 @@ __global__ __launch_bounds__(1024) void sample_design_kernel(SampleArgs a) {
     }
     if (!a.want_w) return;
 
-    // A = R + lam I; publish pivot column 0
+    // The rank-1 form of the sweep below subtracts the constants 1 (w = c - e_k)
+    // and 2 at the pivot, which is exact only for entries of order one: with
+    // R ~ 1e10 the pivot updates cancel to noise.  The sweep therefore works
+    // on A / alpha, alpha a power of two near the largest diagonal entry of
+    // R + lam I (exact scaling): W = I - lam A^-1 = I - (lam / alpha)
+    // (A / alpha)^-1, and A^-1 = (A / alpha)^-1 / alpha.
+    double* red = reinterpret_cast<double*>(&cb[0][0]);   // 16 wave maxima
+    {
+        double dm = 0.0;
+#pragma unroll
+        for (int P = 0; P < NBK; ++P)
+            if (tr == tc && 32 * P + tr < n) dm = fmax(dm, A[blk(P, P)].x);
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) dm = fmax(dm, __shfl_xor(dm, m));
+        if ((tid & 63) == 0) red[tid >> 6] = dm;
+        __syncthreads();
+        dm = red[0];
+        for (int w = 1; w < 16; ++w) dm = fmax(dm, red[w]);
+        __syncthreads();   // every read of red is done before cb is cleared
+        const double top = dm + a.lam;
+        const double alpha = (top > 0.0 && isfinite(top)) ? exp2(rint(log2(top))) : 1.0;
+        const double inva = 1.0 / alpha;
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            A[e].x *= inva;
+            A[e].y *= inva;
+        }
+        lam_s = a.lam * inva;
+        ainv_s = inva;
+    }
+    // A = R + lam I (scaled); publish pivot column 0
 #pragma unroll
     for (int P = 0; P < NBK; ++P)
-        if (tr == tc && 32 * P + tr < n) A[blk(P, P)].x += a.lam;
+        if (tr == tc && 32 * P + tr < n) A[blk(P, P)].x += lam_s;
     for (int e = tid; e < 2 * NMAX; e += 1024) cb[e / NMAX][e % NMAX] = make_double2(0.0, 0.0);
     __syncthreads();
     publish_col<NBK, 0>(A, 0, tr, tc, n, cb[0]);
@@ -237,8 +268,8 @@ __global__ __launch_bounds__(1024) void sample_design_kernel(SampleArgs a) {
             const double2 v = A[blk(P, Q)];
             if (a.ainv) {
                 double2* ai = a.ainv + mat * n * n;
-                ai[(long long)i * n + j] = make_double2(-v.x, -v.y);
-                if (P > Q) ai[(long long)j * n + i] = make_double2(-v.x, v.y);
+                ai[(long long)i * n + j] = make_double2(-v.x * ainv_s, -v.y * ainv_s);
+                if (P > Q) ai[(long long)j * n + i] = make_double2(-v.x * ainv_s, v.y * ainv_s);
             }
             // entry (i, j) and, off the diagonal blocks, its mirror (j, i)
 #pragma unroll
@@ -247,7 +278,7 @@ __global__ __launch_bounds__(1024) void sample_design_kernel(SampleArgs a) {
                 const int o = row - off;
                 if (o < 0 || o >= a.B) continue;
                 const double vy = side == 0 ? v.y : -v.y;
-                const double2 w = make_double2((row == col ? 1.0 : 0.0) + a.lam * v.x, a.lam * vy);
+                const double2 w = make_double2((row == col ? 1.0 : 0.0) + lam_s * v.x, lam_s * vy);
                 if (a.w64) a.w64[(mat * a.B + o) * n + col] = w;
                 if (a.w32) {
                     float2* wr = a.w32 + (mat * a.B + o) * wp;

@@ -29,7 +29,9 @@ struct SampleSplitArgs {
     float2* out;
     long long n_tiles;
     int M, K, N, B, Wn, Wq, nb, rgroups, G16, cgroups;
-    float out_scale;
+    float in_scale;    // power-of-two input scale applied before the split
+    float out_scale;   // its inverse (FP16: times 2^-11)
+    int* status;       // plan status word (FP16 range reports)
 };
 
 constexpr int sCT = 2;                  // column tiles per wave
@@ -101,12 +103,14 @@ __device__ __forceinline__ void ss_load_x(const SampleSplitArgs& a, const float2
 
 template <bool FP16>
 __device__ __forceinline__ void ss_store_x(const SampleSplitRaw& R, int tid, uint32_t* xh,
-                                           uint32_t* xl) {
+                                           uint32_t* xl, float in_scale, bool& bad) {
     const int r = tid & 15, c0 = tid >> 4;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
         uint32_t h, l;
-        split_c<FP16>(R.v[u], h, l);
+        const float2 v = make_float2(R.v[u].x * in_scale, R.v[u].y * in_scale);
+        if constexpr (FP16) bad |= !f16_in_range(v);
+        split_c<FP16>(v, h, l);
         xh[sx_at(c0 + 16 * u, r)] = h;
         xl[sx_at(c0 + 16 * u, r)] = l;
     }
@@ -127,8 +131,9 @@ struct SampleSplitCtx {
 template <int RT, bool FP16>
 __device__ __forceinline__ void ss_step(const SampleSplitCtx& x, int cc, uint32_t* xh, uint32_t* xl,
                                         const float4* hcur, const float4* lcur, float4* hnext,
-                                        float4* lnext, floatx4 (&acc)[RT][sCT], SampleSplitRaw& raw) {
-    ss_store_x<FP16>(raw, x.tid, xh, xl);
+                                        float4* lnext, floatx4 (&acc)[RT][sCT], SampleSplitRaw& raw,
+                                        bool& bad) {
+    ss_store_x<FP16>(raw, x.tid, xh, xl, x.a.in_scale, bad);
     if (cc + 1 < x.nchunks) ss_load_x(x.a, x.xbase, x.xstride, x.m0, cc + 1, x.tid, raw);
     __syncthreads();
     float4 bh[sCT], bl[sCT];
@@ -203,10 +208,12 @@ __global__ __launch_bounds__(sThreads, 2) void apply_sample_split_kernel(SampleS
     ss_load_x(a, x.xbase, x.xstride, x.m0, 0, tid, raw);
     __builtin_amdgcn_s_waitcnt(0x0F70);
     __syncthreads();
+    bool bad = false;
     for (int cc = 0; cc < x.nchunks; cc += 2) {
-        ss_step<RT, FP16>(x, cc, xh, xl, hA, lA, hB, lB, acc, raw);
-        if (cc + 1 < x.nchunks) ss_step<RT, FP16>(x, cc + 1, xh, xl, hB, lB, hA, lA, acc, raw);
+        ss_step<RT, FP16>(x, cc, xh, xl, hA, lA, hB, lB, acc, raw, bad);
+        if (cc + 1 < x.nchunks) ss_step<RT, FP16>(x, cc + 1, xh, xl, hB, lB, hA, lA, acc, raw, bad);
     }
+    if constexpr (FP16) report_range(bad, a.status);
     // lane (l16, kq) of tile (rt, ct) holds real rows 16 rt + 4 kq .. +3 of its
     // column: complex outputs o, o + 1 of the block
     const int l16 = x.l16, q = x.kq;
@@ -248,7 +255,9 @@ hipError_t launch_apply_sample_split(const Plan& p, long long nmat, const float2
     a.cgroups = (p.d.M + sCols - 1) / sCols;
     a.n_tiles = nmat * a.cgroups * p.rgroups;
     const bool fp16 = p.d.precision == LMMSE_FP16X3;
-    a.out_scale = fp16 ? 1.0f / 2048.0f : 1.0f;
+    a.in_scale = p.in_scale;
+    a.out_scale = (fp16 ? 1.0f / 2048.0f : 1.0f) / p.in_scale;
+    a.status = p.status;
     const dim3 grid((unsigned)a.n_tiles), block(sThreads);
 #define LMMSE_SS(R)                                                                        \
     case R:                                                                                \

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/lmmse.h"
+
 namespace lmmse {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -24,6 +26,20 @@ __device__ __forceinline__ void split2(float v, uint16_t& h, uint16_t& l) {
         h = __builtin_bit_cast(uint16_t, hh);
         l = __builtin_bit_cast(uint16_t, ll);
     }
+}
+
+// FP16 hi parts hold magnitudes below 65504 (a larger value rounds to inf,
+// NaN stays NaN): false when v leaves that range.
+__device__ __forceinline__ bool f16_in_range(float2 v) {
+    return fabsf(v.x) < 65504.0f && fabsf(v.y) < 65504.0f;
+}
+
+// Records LMMSE_ERR_RANGE (info -1) in a status word [code, info] when any
+// lane of the wave saw an out-of-range value; the first error wins.  `bad`
+// may differ between lanes.
+__device__ __forceinline__ void report_range(bool bad, int* status) {
+    if (__any(bad) && (threadIdx.x & 63) == 0 && status)
+        if (atomicCAS(status, 0, LMMSE_ERR_RANGE) == 0) status[1] = -1;
 }
 
 // hi and lo of one complex value, each as a packed (re, im) pair

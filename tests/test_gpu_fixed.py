@@ -8,12 +8,16 @@ import torch
 
 import oracle as O
 from paper_1802_05427_amd import Plan
+from parity_helpers import assert_blocks
 from synth import make_slot_batch
 
 pytestmark = pytest.mark.gpu
 
 FP32_GAP_DB = 1e-4          # NMSE gap bound for the FP32 path
-FP32_DISC_DB = -100.0       # ||Hhat_gpu - Hhat_oracle||^2 / ||Hhat_oracle||^2 bound
+# ||Hhat_gpu - Hhat_oracle||^2 / ||Hhat_oracle||^2 bound, whole batch and per
+# block (measured: -129.2 dB at worst over these cases)
+FP32_DISC_DB = -120.0
+FP32_BLOCK_DB = -115.0
 
 
 @pytest.fixture(scope="module")
@@ -80,10 +84,11 @@ def test_despread(dev, K, M, slots):
     np.testing.assert_allclose(h, ref, rtol=0, atol=2e-6 * np.abs(ref).max())
 
 
-def _check_estimate(out, ref, truth):
+def _check_estimate(out, ref, truth, B=None):
     disc = O.discrepancy_db(out, ref)
     gap = abs(O.nmse_db(out, truth) - O.nmse_db(ref, truth))
-    print(f"  discrepancy {disc:.1f} dB, NMSE gap {gap:.2e} dB", flush=True)
+    worst = assert_blocks(out, ref, B, FP32_BLOCK_DB) if B else float("nan")
+    print(f"  discrepancy {disc:.1f} dB (worst block {worst:.1f} dB), NMSE gap {gap:.2e} dB", flush=True)
     assert disc < FP32_DISC_DB
     assert gap < FP32_GAP_DB
 
@@ -122,8 +127,8 @@ def test_estimate_exp_design_matches_oracle(dev, cfg, snr):
         out2 = plan.apply(h).cpu().numpy()
     ref = O.estimate(sb.y, sb.pilots, sb.sigma2, c["B"], c["Wn"], "exp", N_fft=c["N_fft"],
                      tau=c["tau"], taps=c["taps"])
-    _check_estimate(out, ref, sb.H)
-    _check_estimate(out2, ref, sb.H)
+    _check_estimate(out, ref, sb.H, c["B"])
+    _check_estimate(out2, ref, sb.H, c["B"])
 
 
 def test_estimate_uniform_design_paper_size(dev):

@@ -21,6 +21,7 @@ import torch
 
 import oracle as O
 from paper_1802_05427_amd import Plan
+from parity_helpers import assert_blocks
 from synth import make_pilots, make_slot_batch
 from synth.torch_slots import draw_batch
 
@@ -75,13 +76,15 @@ def test_fullband_fixed_filter_and_estimate(dev, kind, snr):
     gap = abs(O.nmse_db(out, sb.H) - O.nmse_db(ref, sb.H))
     print(f"  filter max rel err {werr:.2e}; discrepancy {disc:.1f} dB, NMSE gap {gap:.2e} dB "
           f"(NMSE {O.nmse_db(ref, sb.H):.2f} dB)", flush=True)
-    # cond(R + lam I) reaches 4.5e5 (exponential tau 4 at 20 dB)
-    assert werr < 1e-7
-    assert disc < -100.0
+    # cond(R + lam I) reaches 4.5e5 (exponential tau 4 at 20 dB); measured
+    # filter errors up to 1.4e-11, discrepancies -121.2 dB
+    assert werr < 1e-9
+    assert disc < -115.0
     assert gap < 1e-4
 
 
-@pytest.mark.parametrize("precision,limit_db", [("bf16x3", -100.0), ("fp16x3", -100.0)])
+# measured -117.4 (BF16x3) and -125.5 dB (FP16x3)
+@pytest.mark.parametrize("precision,limit_db", [("bf16x3", -110.0), ("fp16x3", -118.0)])
 @pytest.mark.parametrize("snr", [0.0, 20.0])
 def test_fullband_fixed_split_precision(dev, precision, limit_db, snr):
     print(f"full-band fixed uniform {precision} {snr} dB", flush=True)
@@ -116,7 +119,7 @@ def test_fullband_fixed_64_slots_sampled_columns(dev):
         ys = y[s:s + 1, m:m + 1].cpu().numpy()
         ref = O.estimate(ys, pil_h, sigma2, N, N, "uniform", N_fft=NF, L=144.0)
         disc = O.discrepancy_db(out[s:s + 1, m:m + 1].cpu().numpy(), ref)
-        assert disc < -100.0, (s, m, disc)
+        assert disc < -115.0, (s, m, disc)
 
 
 @pytest.mark.parametrize("snr", [0.0, 20.0])
@@ -133,7 +136,7 @@ def test_fullband_sample_covariance_pushthrough(dev, snr):
     gap = abs(O.nmse_db(out, sb.H) - O.nmse_db(ref, sb.H))
     print(f"  discrepancy {disc:.1f} dB, NMSE gap {gap:.2e} dB (NMSE {O.nmse_db(ref, sb.H):.2f} dB)",
           flush=True)
-    assert disc < -100.0
+    assert disc < -120.0   # measured -130.8
     assert gap < 1e-4
 
 
@@ -151,8 +154,9 @@ def test_pushthrough_windows(dev, c):
         out = plan.estimate(_t(sb.y, dev), _t(sb.pilots, dev), sb.sigma2).cpu().numpy()
     ref = O.estimate(sb.y, sb.pilots, sb.sigma2, c["B"], c["Wn"], "sample")
     disc = O.discrepancy_db(out, ref)
-    print(f"  discrepancy {disc:.1f} dB", flush=True)
-    assert disc < -100.0
+    worst = assert_blocks(out, ref, c["B"], -115.0)
+    print(f"  discrepancy {disc:.1f} dB (worst block {worst:.1f} dB)", flush=True)
+    assert disc < -120.0   # measured -128.6 at worst
 
 
 @pytest.mark.parametrize("c", [
@@ -231,7 +235,7 @@ def test_user_correlation(dev, c):
     d1, d2 = O.discrepancy_db(out, ref), O.discrepancy_db(out2, ref2)
     print(f"  filters {werr:.2e}; discrepancy {d1:.1f} / {d2:.1f} dB", flush=True)
     assert werr < 1e-9
-    assert d1 < -100.0 and d2 < -100.0
+    assert d1 < -115.0 and d2 < -115.0   # measured -121.0 at worst
 
 
 @pytest.mark.parametrize("c", [

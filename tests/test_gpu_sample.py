@@ -119,7 +119,7 @@ def test_sample_estimate_matches_oracle(dev, c, snr):
     disc = O.discrepancy_db(out, ref)
     gap = abs(O.nmse_db(out, sb.H) - O.nmse_db(ref, sb.H))
     print(f"  discrepancy {disc:.1f} dB, NMSE gap {gap:.2e} dB", flush=True)
-    assert disc < -100.0
+    assert disc < -120.0   # measured -127.9 dB at worst
     assert gap < 1e-4
 
 
@@ -136,3 +136,26 @@ def test_not_positive_definite_is_reported(dev):
         # cleared after reading
         assert plan.sync_status() == (0, -1)
     del c
+
+
+@pytest.mark.parametrize("factor", [1e5, 1e-5])
+@pytest.mark.parametrize("Wn", [60, 200])
+def test_sample_design_is_scale_invariant(dev, factor, Wn):
+    """LS values far from order one (an unnormalised receiver): the FP64
+    window design must not depend on the absolute scale (register-resident
+    sweep for Wn = 60, panel sweep for Wn = 200)."""
+    c = dict(M=24, K=2, N=400, N_fft=512, taps=16, tau=4.0, B=40 if Wn == 60 else 100, slots=1)
+    print(f"sample design scale {factor} Wn={Wn}", flush=True)
+    sb = make_slot_batch(M=c["M"], K=c["K"], N=c["N"], N_fft=c["N_fft"], taps=c["taps"], tau=c["tau"],
+                         snr_db=10.0, slots=1, config_id=8)
+    ys = (sb.y.astype(np.complex128) * factor).astype(np.complex64)
+    sig = sb.sigma2 * factor ** 2
+    with Plan(M=c["M"], K=c["K"], N=c["N"], N_fft=c["N_fft"], B=c["B"], Wn=Wn, rsource="sample",
+              sigma2=sig, max_slots=1) as plan:
+        out = plan.estimate(_t(ys, dev), _t(sb.pilots, dev), sig).cpu().numpy()
+        st, _ = plan.sync_status()
+    ref = O.estimate(ys, sb.pilots, sig, c["B"], Wn, "sample")
+    disc = O.discrepancy_db(out, ref)
+    print(f"  status {st}, discrepancy {disc:.1f} dB", flush=True)
+    assert st == 0
+    assert disc < -120.0   # measured -127.9 dB at worst
