@@ -75,14 +75,18 @@ __device__ __forceinline__ void store_ls(const ApplyArgs& a, int tid, int cc, co
         if constexpr (KF == 0) {
             xs2[xs2_at(cq, r)] = R.v[u][0];
         } else {
-            const bool live = cc * 16 + r < a.Wn;
+            // rows past the window are scaled by 0 rather than branched
+            // around: a branch per user would wait for each pilot read in turn
+            const float s = cc * 16 + r < a.Wn ? a.invK : 0.f;
+            float2 p[KF];
+#pragma unroll
+            for (int k = 0; k < KF; ++k) p[k] = pl[k * 16 + r];
             float2 z[KF];
             Dft<KF>::run(R.v[u], z, nullptr);
 #pragma unroll
             for (int k = 0; k < KF; ++k) {
-                const float2 h = cmulc(z[k], pl[k * 16 + r]);
-                xs2[xs2_at(cq * KF + k, r)] =
-                    live ? make_float2(h.x * a.invK, h.y * a.invK) : make_float2(0.f, 0.f);
+                const float2 h = cmulc(z[k], p[k]);
+                xs2[xs2_at(cq * KF + k, r)] = make_float2(h.x * s, h.y * s);
             }
         }
     }

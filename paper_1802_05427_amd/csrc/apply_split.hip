@@ -72,13 +72,18 @@ __device__ __forceinline__ void split_store_ls(const SplitArgs& a, int tid, int 
             xh[xw_at(cq, r)] = h;
             xl[xw_at(cq, r)] = l;
         } else {
-            const bool live = cc * 16 + r < a.Wn;
+            // rows past the window are scaled by 0 rather than branched
+            // around: a branch per user would wait for each pilot read in turn
+            const float s = cc * 16 + r < a.Wn ? a.invK : 0.f;
+            float2 p[KF];
+#pragma unroll
+            for (int k = 0; k < KF; ++k) p[k] = pl[k * 16 + r];
             float2 z[KF];
             Dft<KF>::run(R.v[u], z, nullptr);
 #pragma unroll
             for (int k = 0; k < KF; ++k) {
-                float2 h = cmulc(z[k], pl[k * 16 + r]);
-                h = live ? make_float2(h.x * a.invK, h.y * a.invK) : make_float2(0.f, 0.f);
+                float2 h = cmulc(z[k], p[k]);
+                h = make_float2(h.x * s, h.y * s);
                 if constexpr (FP16) bad |= !f16_in_range(h);
                 uint32_t hh, ll;
                 split_c<FP16>(h, hh, ll);
