@@ -3,9 +3,9 @@
 // (also for the caller-correlation design and the push-through form).  The window matrix lives in the
 // workspace as FP64 [mat][Wn][Wn] (both triangles):
 //
-//   1. R = X X^H / M with X = h_ls[s, :, k, I_b]^T: a batched GEMM with FP64
-//      accumulation of the exact products of the FP32 LS values, on the
-//      lower tiles only (the upper ones are their mirror);
+//   1. R = X X^H / M with X = h_ls[s, :, k, I_b]^T: a batched GEMM on the
+//      FP32 matrix cores (FP32 products and sums over the M antennas), on the
+//      lower tiles only (the upper ones are their mirror), stored as FP64;
 //   2. A = R + lam I;
 //   3. the Hermitian sweep of all Wn pivots, in panels of 64 pivots K (rest
 //      R): sweeping a panel at once maps
@@ -55,7 +55,7 @@ __global__ __launch_bounds__(kSwT) void sweep_panel_kernel(double2* a, double2* 
                                                            long long mat0) {
     static_assert(kPW == 64 && kSwW * kSwE == 64, "thread layout");
     __shared__ double2 rowb[2][kPW], colb[2][kPW];
-    __shared__ double2 tsym[kPW][kPW + 1];   // the block, for its Hermitian part
+    __shared__ double2 tsym[kPW / 2][kPW + 1];   // half the block, for its Hermitian part
     const long long mat = blockIdx.x;
     double2* am = a + mat * Wn * Wn;
     const int tid = threadIdx.x, w = __builtin_amdgcn_readfirstlane(tid >> 6), j = tid & 63;
@@ -130,14 +130,25 @@ __global__ __launch_bounds__(kSwT) void sweep_panel_kernel(double2* a, double2* 
     // Hermitian dsw, and the skew part of the rounding grows from panel to
     // panel (a CPU model of a 1200-wide window lost 10 digits over 19
     // panels).  The block is therefore replaced by its Hermitian part.
+    // In two halves of 32 block rows (a 64 x 64 buffer would leave room for
+    // only two workgroups per CU): entry (i, j) needs (j, i), which the half
+    // holding row j provides.
+    double2 tr_[kSwE];
 #pragma unroll
-    for (int u = 0; u < kSwE; ++u) tsym[w + kSwW * u][j] = r[u];
-    __syncthreads();
+    for (int h = 0; h < 2; ++h) {
 #pragma unroll
-    for (int u = 0; u < kSwE; ++u) {
-        const double2 t = tsym[j][w + kSwW * u];
-        r[u] = make_double2(0.5 * (r[u].x + t.x), 0.5 * (r[u].y - t.y));
+        for (int u = 0; u < kSwE; ++u)
+            if ((w + kSwW * u) / 32 == h) tsym[(w + kSwW * u) % 32][j] = r[u];
+        __syncthreads();
+        if (j / 32 == h) {
+#pragma unroll
+            for (int u = 0; u < kSwE; ++u) tr_[u] = tsym[j % 32][w + kSwW * u];
+        }
+        __syncthreads();
     }
+#pragma unroll
+    for (int u = 0; u < kSwE; ++u)
+        r[u] = make_double2(0.5 * (r[u].x + tr_[u].x), 0.5 * (r[u].y - tr_[u].y));
     double2* dm = dsw + mat * kPW * kPW;
 #pragma unroll
     for (int u = 0; u < kSwE; ++u) {
@@ -278,7 +289,8 @@ hipError_t launch_sample_large(const Plan& p, long long nmat, long long mat0, co
     ga.alpha = 1.0 / d.M;
     ga.beta = 0;
     ga.herm = 1;
-    if ((e = zgemm<float2, float2, double2>(ga, nmat, st)) != hipSuccess) return e;
+    // FP32 matrix-core products and sums, stored as FP64 for the sweep
+    if ((e = zgemm<float2, float2, double2, float>(ga, nmat, st)) != hipSuccess) return e;
     ga.herm = 0;
     if ((e = launch_sweep_inverse(nmat, mat0, Wn, d.K, p.nb, lam, amat, scratch, p.status, st)) !=
         hipSuccess)

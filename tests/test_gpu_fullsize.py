@@ -140,7 +140,8 @@ def test_large_sample_batch_sampled_windows(dev):
         W = O.lmmse._filter(R[offs[b]:offs[b] + Bl], R, lam)
         disc = O.discrepancy_db(out[s, :, k, b * Bl:(b + 1) * Bl].cpu().numpy(), Xw @ W.T)
         print(f"  slot {s} user {k} block {b}: discrepancy {disc:.1f} dB", flush=True)
-        assert disc < -110.0, (s, k, b, disc)
+        # FP32 covariance on the matrix cores, FP64 design, FP16x3 filter
+        assert disc < -85.0, (s, k, b, disc)
 
 
 def test_fixed_fwd_bwd_batch(dev):

@@ -119,7 +119,9 @@ def test_sample_estimate_matches_oracle(dev, c, snr):
     disc = O.discrepancy_db(out, ref)
     gap = abs(O.nmse_db(out, sb.H) - O.nmse_db(ref, sb.H))
     print(f"  discrepancy {disc:.1f} dB, NMSE gap {gap:.2e} dB", flush=True)
-    assert disc < -120.0   # measured -127.9 dB at worst
+    # windows up to 160 sum the covariance in FP64 (measured -127.9 dB at
+    # worst); wider ones in FP32 on the matrix cores
+    assert disc < (-120.0 if c["Wn"] <= 160 else -85.0)
     assert gap < 1e-4
 
 

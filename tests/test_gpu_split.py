@@ -17,6 +17,11 @@ SPLIT_GAP_DB = 0.05
 # far better (measured at worst: BF16x3 -112.9 dB, FP16x3 -132.8 dB)
 SPLIT_DISC_DB = {"bf16x3": -105.0, "fp16x3": -125.0}
 SPLIT_BLOCK_DB = {"bf16x3": -100.0, "fp16x3": -120.0}
+# sample covariance of windows wider than 160: summed in FP32 on the matrix
+# cores (measured at worst: BF16x3 -111.4 dB, FP16x3 -122.1 dB, per block
+# -111.0 / -114.6 dB)
+WIDE_SAMPLE_DISC_DB = {"bf16x3": -105.0, "fp16x3": -115.0}
+WIDE_SAMPLE_BLOCK_DB = {"bf16x3": -100.0, "fp16x3": -108.0}
 
 
 @pytest.fixture(scope="module")
@@ -88,14 +93,17 @@ def test_split_sample_estimate_matches_oracle(dev, prec, cfg, snr):
         st, info = plan.sync_status()
     assert st == 0
     ref = O.estimate(sb.y, sb.pilots, sb.sigma2, c["B"], c["Wn"], "sample")
+    wide = c["Wn"] > 160
+    lim = (WIDE_SAMPLE_DISC_DB if wide else SPLIT_DISC_DB)[prec]
+    blim = (WIDE_SAMPLE_BLOCK_DB if wide else SPLIT_BLOCK_DB)[prec]
     for o in (out, out2):
         disc = O.discrepancy_db(o, ref)
         gap = abs(O.nmse_db(o, sb.H) - O.nmse_db(ref, sb.H))
-        worst = assert_blocks(o, ref, c["B"], SPLIT_BLOCK_DB[prec])
+        worst = assert_blocks(o, ref, c["B"], blim)
         print(f"  discrepancy {disc:.1f} dB (worst block {worst:.1f} dB), NMSE gap {gap:.2e} dB",
               flush=True)
         assert gap < SPLIT_GAP_DB
-        assert disc < SPLIT_DISC_DB[prec]
+        assert disc < lim
 
 
 # LS values far from order one: the FP16 split needs |s h_ls| < 65504 and
