@@ -39,7 +39,9 @@
  *   LMMSE_R_SAMPLE       raw sample covariance over the M antennas, per
  *                        (slot, user, window): R = (1/M) sum_m h h^H;
  *                        windows up to 256 are designed directly (up to 160
- *                        held in registers, wider ones in the workspace);
+ *                        held in registers, R summed in FP64; wider ones in
+ *                        the workspace, R summed in FP32 on the matrix
+ *                        cores);
  *                        wider windows, e.g. the full band B = Wn = N, use
  *                        the equal push-through form W X = X_O G (G + lam I)^-1
  *                        with the M x M Gram matrix G = X^H X / M of the
@@ -235,7 +237,8 @@ int lmmse_apply(lmmse_plan_t plan, int slots, const void *h_ls, void *h_hat,
 /* Sample covariance per (slot, user, window), R = (1/M) sum_m h_m h_m^H over
  * the antennas (not a step of the paper: the data-driven R that eq. 13 takes
  * as given, estimated from the LS values of the M antennas), products of
- * the complex64 LS values accumulated in FP64, stored as complex128
+ * the complex64 LS values accumulated in FP64 (the estimate itself sums the
+ * covariance of windows wider than 160 in FP32), stored as complex128
  * [S][K][N/B][Wn][Wn] (full matrix, both triangles).  Any plan. */
 int lmmse_covariance(lmmse_plan_t plan, int slots, const void *h_ls,
                      void *r_win, void *stream);
