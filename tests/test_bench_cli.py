@@ -46,10 +46,13 @@ def test_stored_traffic_is_tied_to_the_kernel_sources(monkeypatch):
     coeffs = e["coeffs"]
     assert coeffs == 64 * 128 * 12 * 1200
     v = b.stored_traffic(k, "fp32", coeffs)
-    if e["src_digest"] == b.src_digest("fp32"):
-        assert v == e["hbm_bytes_per_launch"]
-    else:   # the kernel sources changed since the counters were taken
-        assert v is None
+    # the counters were taken on the committed kernel sources: a change to
+    # them must come with new counters
+    assert e["src_digest"] == b.src_digest("fp32")
+    assert v == e["hbm_bytes_per_launch"]
+    ks = "apply_split_kernel<13, 12, bf16x3>"
+    assert rec[ks]["src_digest"] == b.src_digest("split")
+    assert b.stored_traffic(ks, "split", coeffs) == rec[ks]["hbm_bytes_per_launch"]
     scaled = e["FETCH_SIZE_kib"] * 1024 * cp["fetch_scale"] + e["WRITE_SIZE_kib"] * 1024 * cp["write_scale"]
     assert abs(scaled - e["hbm_bytes_per_launch"]) <= 1e-6 * scaled
     assert b.stored_traffic(k, "fp32", coeffs + 1) is None
