@@ -49,12 +49,13 @@ struct BwGeom {
     long long cpw;           // columns per chunk (multiple of 16)
 };
 
-constexpr int kDwMaxRT = 7;           // dW row tiles per workgroup (2B real rows in row groups):
-                                      // <= 96 registers, 5 waves per SIMD
+constexpr int kDwMaxRT = 13;          // dW row tiles per workgroup (2B real rows in row groups):
+                                      // one group for B <= 104, so the window is read once;
+                                      // <= 128 registers, 4 waves per SIMD
 constexpr int kDwMaxWaves = 16;       // one wave per 16 window columns: Wn <= 256
 static_assert(16 * kDwMaxWaves == kMaxSampleWindowLarge,
               "lmmse_backward refuses design gradients above kMaxSampleWindowLarge");
-constexpr int kDwSlots = 512;         // workgroups resident at once (2 per CU)
+constexpr int kDwSlots = 256;         // workgroups resident at once (one 10-wave workgroup per CU at Wn = 150)
 
 static BwGeom bw_geom(const lmmse_plan_desc& d, const std::vector<int>& starts, long long ncols) {
     BwGeom g{};
@@ -161,7 +162,7 @@ struct DwArgs {
 constexpr int kDwS = 18;   // LDS row stride (float2) of the transposed tiles: 16 columns + pad
 
 template <int RT>
-__global__ __launch_bounds__(64 * kDwMaxWaves) __attribute__((amdgpu_waves_per_eu(5)))
+__global__ __launch_bounds__(64 * kDwMaxWaves) __attribute__((amdgpu_waves_per_eu(4)))
 void dw_kernel(DwArgs a) {
     constexpr int NO = RT * 8;                     // complex output rows of the group
     __shared__ float2 gT[NO * kDwS];               // G: [o][col]
@@ -532,6 +533,7 @@ hipError_t launch_backward_fixed(Plan& p, int slots, const float2* hls, const fl
 #define LMMSE_DW(R) \
     case R: hipLaunchKernelGGL((dw_kernel<R>), gridw, blockw, 0, st, dw); break;
         LMMSE_DW(1) LMMSE_DW(2) LMMSE_DW(3) LMMSE_DW(4) LMMSE_DW(5) LMMSE_DW(6) LMMSE_DW(7)
+        LMMSE_DW(8) LMMSE_DW(9) LMMSE_DW(10) LMMSE_DW(11) LMMSE_DW(12) LMMSE_DW(13)
 #undef LMMSE_DW
         default:
             return hipErrorInvalidValue;
