@@ -144,6 +144,7 @@ def test_fullband_sample_covariance_pushthrough(dev, snr):
     dict(M=128, K=2, N=1200, N_fft=2048, taps=72, tau=4.0, B=100, Wn=300, slots=2),   # clamped windows
     dict(M=72, K=3, N=600, N_fft=1024, taps=32, tau=6.0, B=200, Wn=400, slots=1),    # ragged M
     dict(M=256, K=1, N=520, N_fft=1024, taps=32, tau=6.0, B=260, Wn=520, slots=1),   # widest M
+    dict(M=73, K=2, N=600, N_fft=1024, taps=32, tau=6.0, B=200, Wn=400, slots=1),    # odd M: the M x M sweep ends with 9 pivots
 ])
 def test_pushthrough_windows(dev, c):
     print(f"push-through windows {c}", flush=True)

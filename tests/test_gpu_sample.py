@@ -40,7 +40,8 @@ LARGE = [
     dict(M=16, K=2, N=3300, N_fft=4096, taps=144, tau=32.0, B=132, Wn=198, slots=1),
     dict(M=260, K=1, N=480, N_fft=512, taps=16, tau=4.0, B=120, Wn=240, slots=1),  # ragged M
     dict(M=24, K=1, N=512, N_fft=512, taps=16, tau=4.0, B=128, Wn=256, slots=1),   # widest: 4 panels of 64
-    dict(M=24, K=1, N=600, N_fft=1024, taps=16, tau=4.0, B=150, Wn=162, slots=1),  # narrowest: 3 panels of 54
+    dict(M=24, K=1, N=600, N_fft=1024, taps=16, tau=4.0, B=150, Wn=162, slots=1),  # narrowest: panels 64, 64, 34
+    dict(M=24, K=1, N=330, N_fft=512, taps=16, tau=4.0, B=55, Wn=165, slots=1),    # odd last panel (37 pivots)
 ]
 
 
