@@ -139,6 +139,16 @@ __global__ __launch_bounds__(kSwT) void sweep_panel_kernel(double2* a, double2* 
         const double2 t1 = make_double2(bq.x * invd2, bq.y * invd2);
         const double2 t0 = make_double2(q.x - (ba.x * t1.x - ba.y * t1.y), q.y - (ba.x * t1.y + ba.y * t1.x));
         const bool j0 = j == p, j1 = j == p + 1;
+        // Rows outside the pair take one formula in every column, rs a_ij -
+        // x0 ql - x1 tl, with per-lane coefficients set once per step: off the
+        // pair's columns rs = 1, ql = q, tl = t1 (a_ij - x0 q - x1 t1); in
+        // column p, A_iK A_KK^-1's first column x0 / a - x1 conj(b) / (a d2)
+        // (rs = 0, ql = -1/a, tl = conj(b) / (a d2)); in column p+1, x1 / d2
+        // (rs = 0, ql = 0, tl = -1/d2).  Branching per lane instead would run
+        // all three forms in every wave.
+        const double rs = (j0 || j1) ? 0.0 : 1.0;
+        const double2 ql = j0 ? make_double2(-inva, 0.0) : j1 ? make_double2(0.0, 0.0) : q;
+        const double2 tl = j0 ? cb : j1 ? make_double2(-invd2, 0.0) : t1;
 #pragma unroll
         for (int u = 0; u < kSwE; ++u) {
             const int i = w + kSwW * u;   // wave-uniform
@@ -152,18 +162,11 @@ __global__ __launch_bounds__(kSwT) void sweep_panel_kernel(double2* a, double2* 
                 const double2 x0 = colb[buf][0][i], x1o = colb[buf][1][i];
                 const double2 x1 = make_double2(x1o.x - (x0.x * ba.x - x0.y * ba.y),
                                                 x1o.y - (x0.x * ba.y + x0.y * ba.x));
-                if (j0) {         // a_ip / a - x1 conj(b) / (a d2)
-                    r[u] = make_double2(x0.x * inva - (x1.x * cb.x - x1.y * cb.y),
-                                        x0.y * inva - (x1.x * cb.y + x1.y * cb.x));
-                } else if (j1) {  // x1 / d2
-                    r[u] = make_double2(x1.x * invd2, x1.y * invd2);
-                } else {          // a_ij - x0 q - x1 t1
-                    double gx = fma(-x0.x, q.x, fma(x0.y, q.y, r[u].x));
-                    double gy = fma(-x0.x, q.y, fma(-x0.y, q.x, r[u].y));
-                    gx = fma(-x1.x, t1.x, fma(x1.y, t1.y, gx));
-                    gy = fma(-x1.x, t1.y, fma(-x1.y, t1.x, gy));
-                    r[u] = make_double2(gx, gy);
-                }
+                double gx = fma(-x0.x, ql.x, fma(x0.y, ql.y, rs * r[u].x));
+                double gy = fma(-x0.x, ql.y, fma(-x0.y, ql.x, rs * r[u].y));
+                gx = fma(-x1.x, tl.x, fma(x1.y, tl.y, gx));
+                gy = fma(-x1.x, tl.y, fma(-x1.y, tl.x, gy));
+                r[u] = make_double2(gx, gy);
             }
         }
     }
