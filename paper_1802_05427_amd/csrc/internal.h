@@ -32,6 +32,8 @@ struct Plan {
     int n_classes = 0;
     int RT = 0;          // 16-row MFMA tiles per workgroup row group
     int rgroups = 0;     // row groups per block: RT*16*rgroups = Rpad >= 2B
+    int sRT = 0;         // the same for the split-precision filter of the sample path,
+    int srgroups = 0;    // whose per-window filter parts take less LDS (up to 17 tiles)
     int Rpad = 0;        // padded real rows of a filter (RT*16*rgroups)
     int G8 = 0;          // ceil(Wn/8)
     int G16 = 0;         // ceil(Wn/16)

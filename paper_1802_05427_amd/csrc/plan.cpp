@@ -226,6 +226,10 @@ int lmmse_plan_create(const lmmse_plan_desc* desc, lmmse_plan_t* out) {
     p->n_classes = (int)p->h_class_off.size();
     // split-precision kernels double-buffer three filter parts in LDS: RT <= 13
     choose_row_tiles(desc->B, desc->precision == LMMSE_FP32 ? 17 : 13, p->RT, p->rgroups);
+    // the sample path's split kernel holds one window's filter parts compactly
+    // (two buffers of 8 RT rows x 4 slots per part): 17 tiles fit, so a block
+    // of up to 136 outputs reads its window once
+    choose_row_tiles(desc->B, 17, p->sRT, p->srgroups);
     p->Rpad = p->RT * 16 * p->rgroups;
     p->G8 = (desc->Wn + 7) / 8;
     p->G16 = (desc->Wn + 15) / 16;

@@ -250,10 +250,10 @@ hipError_t launch_apply_sample_split(const Plan& p, long long nmat, const float2
     a.Wn = p.d.Wn;
     a.Wq = (p.d.Wn + 3) & ~3;
     a.nb = p.nb;
-    a.rgroups = p.rgroups;
+    a.rgroups = p.srgroups;
     a.G16 = p.G16;
     a.cgroups = (p.d.M + sCols - 1) / sCols;
-    a.n_tiles = nmat * a.cgroups * p.rgroups;
+    a.n_tiles = nmat * a.cgroups * p.srgroups;
     const bool fp16 = p.d.precision == LMMSE_FP16X3;
     a.in_scale = p.in_scale;
     a.out_scale = (fp16 ? 1.0f / 2048.0f : 1.0f) / p.in_scale;
@@ -266,8 +266,9 @@ hipError_t launch_apply_sample_split(const Plan& p, long long nmat, const float2
         else                                                                               \
             hipLaunchKernelGGL((apply_sample_split_kernel<R, false>), grid, block, 0, st, a); \
         break;
-    switch (p.RT) {
-        LMMSE_SS(1) LMMSE_SS(2) LMMSE_SS(4) LMMSE_SS(8) LMMSE_SS(9) LMMSE_SS(13)
+    switch (p.sRT) {
+        LMMSE_SS(1) LMMSE_SS(2) LMMSE_SS(4) LMMSE_SS(8) LMMSE_SS(9) LMMSE_SS(13) LMMSE_SS(15)
+        LMMSE_SS(17)
         default:
             return hipErrorInvalidValue;
     }
