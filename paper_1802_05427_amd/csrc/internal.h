@@ -127,6 +127,11 @@ constexpr int kMaxPushthroughAntennas = 256;
 // matrix mat0 + mat in status.
 hipError_t launch_sweep_inverse(long long nmat, long long mat0, int n, int K, int nb, double lam,
                                 double2* amat, double2* scratch, int* status, hipStream_t st);
+// The same for n <= 208 with one workgroup holding a whole matrix (no
+// scratch); resident_inverse_fits(n) says whether it applies.
+bool resident_inverse_fits(int n);
+hipError_t launch_resident_inverse(long long nmat, long long mat0, int n, double lam, double2* amat,
+                                   int* status, hipStream_t st);
 // From S = -(R + lam I)^-1 as launch_sweep_inverse leaves it, the block
 // filters W = (I + lam S)[off_b rows] (w64 [mat][B][Wn]; offsets indexed by
 // mat % nb) and, with negate, A^-1 = -S in place.

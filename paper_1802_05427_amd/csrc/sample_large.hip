@@ -7,8 +7,9 @@
 //      FP32 matrix cores (FP32 products and sums over the M antennas), on the
 //      lower tiles only (the upper ones are their mirror), stored as FP64;
 //   2. A = R + lam I;
-//   3. the Hermitian sweep of all Wn pivots, in panels of 64 pivots K (rest
-//      R): sweeping a panel at once maps
+//   3. the Hermitian sweep of all Wn pivots: for Wn <= 208 in one launch
+//      with the matrix held on one compute unit (resident_inverse.hip);
+//      wider, in panels of 64 pivots K (rest R): sweeping a panel at once maps
 //          A_KK -> -A_KK^-1,  A_RK -> A_RK A_KK^-1,  A_KR -> A_KK^-1 A_KR,
 //          A_RR -> A_RR - A_RK A_KK^-1 A_KR,
 //      which equals sweeping its pivots one by one.  The panel kernel sweeps
@@ -281,6 +282,8 @@ __global__ __launch_bounds__(256) void large_filters_kernel(double2* a, const in
 hipError_t launch_sweep_inverse(long long nmat, long long mat0, int n, int K, int nb, double lam,
                                 double2* amat, double2* scratch, int* status, hipStream_t st) {
     if (nmat == 0) return hipSuccess;
+    // a matrix that one compute unit holds whole: the register-resident form
+    if (resident_inverse_fits(n)) return launch_resident_inverse(nmat, mat0, n, lam, amat, status, st);
     hipError_t e;
     hipLaunchKernelGGL(add_diag_kernel, dim3((unsigned)nmat), dim3(256), 0, st, amat, n, lam);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -341,6 +344,7 @@ hipError_t launch_large_filters(long long nmat, double2* amat, const int* offset
 }
 
 size_t sweep_scratch_bytes(int Wn, long long nmat) {
+    if (resident_inverse_fits(Wn)) return 0;   // no panel operands
     return (size_t)nmat * ((size_t)Wn * kPW + (size_t)kPW * kPW) * sizeof(double2);
 }
 

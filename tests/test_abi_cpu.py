@@ -172,11 +172,12 @@ def test_sample_window_limits():
         + 32 * nmat1 * 8 + (1 << 20)
     with pytest.raises(_lib.LmmseError):
         workspace_size(_d(rsource="sample", N=1040, B=130, Wn=260, precision="bf16x3"), 1)
-    # full band of 64 paper-sized slots: H_LS plus M x M FP64 matrices and the
-    # sweep scratch of every (slot, user), no Wn x Wn matrix
+    # full band of 64 paper-sized slots: H_LS plus the M x M FP64 matrices of
+    # every (slot, user), no Wn x Wn matrix and no panel scratch (a 128 x 128
+    # system is inverted whole by one workgroup)
     fb = workspace_size(_d(rsource="sample", B=1200, Wn=1200), 64)
     nmat = 64 * 12
-    assert fb == 64 * 128 * 12 * 1200 * 8 + nmat * 128 * 128 * 16 + nmat * (128 * 64 + 64 * 64) * 16
+    assert fb == 64 * 128 * 12 * 1200 * 8 + nmat * 128 * 128 * 16
 
 
 @pytest.mark.parametrize("kw,code", [
