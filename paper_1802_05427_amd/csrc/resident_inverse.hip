@@ -46,6 +46,7 @@ __device__ __forceinline__ void ri_wave_sync() {
 // addresses derived from it are formed where they are used rather than held
 // in registers across the loop for every slot.
 __device__ __forceinline__ int ri_opaque(int c) {
+    c = __builtin_amdgcn_readfirstlane(c);   // uniform; a scalar register for the constraint
     __asm__ volatile("" : "+s"(c));
     return c;
 }
@@ -54,38 +55,75 @@ __device__ __forceinline__ double2 ri_shfl(double2 v, int src) {
     return make_double2(__shfl(v.x, src), __shfl(v.y, src));
 }
 
-// Sweep of the 16 pivots of one 16 x 16 sub-tile held in the result layout
-// (re[v], im[v]: row 4 v + lk, column li), single pivots in order:
+// Lane (li, lk) takes x of lane (P, lk): the DPP broadcast of one lane of
+// every 16-lane row to its row (a register move, no LDS round trip).
+template <int P>
+__device__ __forceinline__ double ri_rowbcast(double x) {
+    const long long b = __builtin_bit_cast(long long, x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x150 + P, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x150 + P, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double ri_readlane(double x, int l) {
+    const long long b = __builtin_bit_cast(long long, x);
+    const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+// 1/d for a positive finite d: the hardware estimate refined by two Newton
+// steps (each squares the relative error), well within an ulp or two of the
+// quotient, with a short dependency chain.
+__device__ __forceinline__ double ri_rcp(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(fma(-d, r, 1.0), r, r);
+    return fma(fma(-d, r, 1.0), r, r);
+}
+
+// Pivot P of the sweep of one 16 x 16 sub-tile held in the result layout
+// (re[v], im[v]: row 4 v + lk, column li):
 //   a_pp -> -1/d, a_pj -> a_pj / d, a_ip -> a_ip / d,
-//   a_ij -> a_ij - a_ip a_pj / d        (d = a_pp),
-// then its Hermitian part.  Returns false when a pivot is not positive and
-// finite.  dt: the wave's 16 x kRiS LDS staging block, which ends holding the
-// result row-major.
-__device__ __forceinline__ bool ri_sweep_diag(zd4& re, zd4& im, double2 (*dt)[kRiS], int li, int lk) {
-    bool ok = true;
-    for (int p = 0; p < 16; ++p) {
-        const int vp = p >> 2, lp = p & 3;   // wave-uniform
-        // row p (as it is before this pivot), entry of this lane's column
-        const double rx = vp == 0 ? re[0] : vp == 1 ? re[1] : vp == 2 ? re[2] : re[3];
-        const double ry = vp == 0 ? im[0] : vp == 1 ? im[1] : vp == 2 ? im[2] : im[3];
-        const double2 apj = ri_shfl(make_double2(rx, ry), 16 * lp + li);
-        const double d = __shfl(rx, 16 * lp + p);
-        ok = ok && d > 0.0 && isfinite(d);
-        const double invd = 1.0 / d;
-        const double2 q = make_double2(apj.x * invd, apj.y * invd);
-        const bool jp = li == p;
+//   a_ij -> a_ij - a_ip a_pj / d        (d = a_pp).
+// Column P reaches every lane of a row by DPP, row P (held by row-group
+// P % 4, entry P / 4) by a lane permute, d by reading one lane.
+template <int P>
+__device__ __forceinline__ bool ri_pivot(zd4& re, zd4& im, int li, int lk) {
+    constexpr int vp = P >> 2, lp = P & 3;
+    const double d = ri_readlane(re[vp], 16 * lp + P);
+    const double2 apj = ri_shfl(make_double2(re[vp], im[vp]), 16 * lp + li);
+    double2 aip[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            // a_ip of this lane's row 4 v + lk, read before element v changes
-            const double2 aip = ri_shfl(make_double2(re[v], im[v]), 16 * lk + p);
-            const bool ip = 4 * v + lk == p;
-            // per-lane selects, not branches
-            const double gx = fma(-aip.x, q.x, fma(aip.y, q.y, re[v]));
-            const double gy = fma(-aip.x, q.y, fma(-aip.y, q.x, im[v]));
-            re[v] = ip ? (jp ? -invd : q.x) : (jp ? aip.x * invd : gx);
-            im[v] = ip ? (jp ? 0.0 : q.y) : (jp ? aip.y * invd : gy);
-        }
+    for (int v = 0; v < 4; ++v) aip[v] = make_double2(ri_rowbcast<P>(re[v]), ri_rowbcast<P>(im[v]));
+    const double invd = ri_rcp(d);
+    const double2 q = make_double2(apj.x * invd, apj.y * invd);
+    const bool jp = li == P;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const bool ip = 4 * v + lk == P;
+        // per-lane selects, not branches
+        const double gx = fma(-aip[v].x, q.x, fma(aip[v].y, q.y, re[v]));
+        const double gy = fma(-aip[v].x, q.y, fma(-aip[v].y, q.x, im[v]));
+        re[v] = ip ? (jp ? -invd : q.x) : (jp ? aip[v].x * invd : gx);
+        im[v] = ip ? (jp ? 0.0 : q.y) : (jp ? aip[v].y * invd : gy);
     }
+    return d > 0.0 && isfinite(d);
+}
+
+template <int P>
+__device__ __forceinline__ bool ri_pivots(zd4& re, zd4& im, int li, int lk) {
+    const bool ok = ri_pivot<P>(re, im, li, lk);
+    if constexpr (P + 1 < 16)
+        return ri_pivots<P + 1>(re, im, li, lk) && ok;
+    else
+        return ok;
+}
+
+// Sweep of the 16 pivots of one 16 x 16 sub-tile in order, then its
+// Hermitian part.  Returns false when a pivot is not positive and finite.
+// dt: the wave's 16 x kRiS LDS staging block, which ends holding the result
+// row-major.
+__device__ __forceinline__ bool ri_sweep_diag(zd4& re, zd4& im, double2 (*dt)[kRiS], int li, int lk) {
+    const bool ok = ri_pivots<0>(re, im, li, lk);
     // Hermitian part: entry (i, j) and conj of (j, i) through LDS
 #pragma unroll
     for (int v = 0; v < 4; ++v) dt[4 * v + lk][li] = make_double2(re[v], im[v]);
@@ -103,15 +141,160 @@ __device__ __forceinline__ bool ri_sweep_diag(zd4& re, zd4& im, double2 (*dt)[kR
     return ok;
 }
 
-template <int NT>
+// The holder of a diagonal sub-tile (one wave), once the block is staged in
+// dt: the block swept (the result, D = -block^-1, ends in dt; the slot takes
+// it from there later).  A pivot that is not positive and finite sets bad.
+__device__ __forceinline__ void ri_sweep_staged(double2 (*dt)[kRiS], int li, int lk, int& bad, int lane) {
+    ri_wave_sync();
+    zd4 tr, ti;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const double2 x = dt[4 * v + lk][li];
+        tr[v] = x.x;
+        ti[v] = x.y;
+    }
+    ri_wave_sync();
+    if (!ri_sweep_diag(tr, ti, dt, li, lk) && lane == 0) bad = 1;
+}
+
+// D = (+-A) (+-B) + C on the FP64 matrix cores; NEG bit 0 negates A, bit 1
+// negates B (the instruction's own modifiers, so no separate negation).
+template <int NEG>
+__device__ __forceinline__ zd4 ri_mma(double a, double b, zd4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, NEG);
+}
+
+// C -= F P^H for one 16 x 16 sub-tile: A = F[li][kk] = ft[kk][li],
+// B = (P^H)[kk][li] = conj(pt[kk][li]), four real products per complex one.
+// f0, q0: the first step's operands, read ahead by the caller.
+__device__ __forceinline__ void ri_update(zd4& cr, zd4& ci, const double2 (*ft)[kRiS],
+                                          const double2 (*pt)[kRiS], double2 f0, double2 q0, int li,
+                                          int lk) {
+    double2 f = f0, q = q0;
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+        double2 fn = f, qn = q;
+        if (ks + 1 < 4) {
+            fn = ft[4 * (ks + 1) + lk][li];
+            qn = pt[4 * (ks + 1) + lk][li];
+        }
+        cr = ri_mma<1>(f.x, q.x, cr);   // re -= fx qx + fy qy
+        ci = ri_mma<1>(f.y, q.x, ci);   // im -= fy qx - fx qy
+        cr = ri_mma<1>(f.y, q.y, cr);
+        ci = ri_mma<0>(f.x, q.y, ci);
+        f = fn;
+        q = qn;
+    }
+}
+
+// The window's LS values for the fused covariance: X[j][m] = h_ls[s, m, k,
+// starts[b] + j] (complex FP32, [S][M][K][N]) for matrix (s K + k) nb + b.
+struct RiCov {
+    const float2* hls;
+    const int* starts;
+    int M, K, N, nb;
+};
+
+typedef float ri_f4 __attribute__((ext_vector_type(4)));
+
+// R = X X^H / M on the FP32 matrix cores for this wave's lower sub-tiles,
+// then A = R + lam I (identity on the padding) in the FP64 layout of the
+// inverse: the same products, in the same order, with FP32 sums over the
+// antennas, as the batched covariance product of the wider windows.  The LS
+// values go through LDS in chunks of 16 antennas (xs: two [16][16 NT]
+// buffers), the next chunk read into registers during the current one's
+// products.  The FP32 result layout (row 4 lk + v) is turned into the FP64
+// one (row 4 v + lk) through the wave's own LDS block tw.
+template <int NT, int SL>
+__device__ __forceinline__ void ri_covariance(zd4 (&cre)[SL], zd4 (&cim)[SL], const int (&code)[SL],
+                                              const RiCov& cv, long long mat, int n, double lam,
+                                              float2* xs, double2 (*tw)[kRiS], int tid, int lane) {
+    constexpr int R = 16 * NT;                        // rows of a chunk
+    constexpr int PT = (16 * R + kRiThreads - 1) / kRiThreads;   // chunk values per thread
+    const int li = lane & 15, lk = lane >> 4;
+    const int b = (int)(mat % cv.nb);
+    const long long sk = mat / cv.nb;
+    const float2* xw = cv.hls + (sk / cv.K) * ((long long)cv.M * cv.K * cv.N) + (sk % cv.K) * cv.N +
+                       cv.starts[b];
+    const long long ms = (long long)cv.K * cv.N;   // antenna stride
+    float2 pre[PT];
+    auto fetch = [&](int m0) {
+#pragma unroll
+        for (int t = 0; t < PT; ++t) {
+            const int e = tid + kRiThreads * t, m = e / R, j = e - m * R;
+            const bool ok = e < 16 * R && j < n && m0 + m < cv.M;
+            pre[t] = xw[ok ? (m0 + m) * ms + j : 0];
+            if (!ok) pre[t] = make_float2(0.f, 0.f);
+        }
+    };
+    ri_f4 fr[SL], fi[SL];
+#pragma unroll
+    for (int u = 0; u < SL; ++u) {
+        fr[u] = ri_f4{0, 0, 0, 0};
+        fi[u] = ri_f4{0, 0, 0, 0};
+    }
+    fetch(0);
+    const int nch = (cv.M + 15) / 16;
+    for (int ch = 0; ch < nch; ++ch) {
+        float2* xb = xs + (ch & 1) * 16 * R;   // [16 antennas][R rows]
+#pragma unroll
+        for (int t = 0; t < PT; ++t) {
+            const int e = tid + kRiThreads * t;
+            if (e < 16 * R) xb[e] = pre[t];
+        }
+        __syncthreads();   // (the other buffer was last read before the previous barrier)
+        if (ch + 1 < nch) fetch(16 * (ch + 1));
+#pragma unroll
+        for (int u = 0; u < SL; ++u) {
+            const int c = ri_opaque(code[u]), I = c & 15, J = (c >> 4) & 15;
+            if (!(c >> 8)) continue;
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                const float2 x1 = xb[(4 * ks + lk) * R + 16 * I + li], x2 = xb[(4 * ks + lk) * R + 16 * J + li];
+                // x1 conj(x2): re = x1.x x2.x + x1.y x2.y, im = x1.y x2.x - x1.x x2.y
+                fr[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(x1.x, x2.x, fr[u], 0, 0, 0);
+                fr[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(x1.y, x2.y, fr[u], 0, 0, 0);
+                fi[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(-x1.x, x2.y, fi[u], 0, 0, 0);
+                fi[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(x1.y, x2.x, fi[u], 0, 0, 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    const double invM = 1.0 / cv.M;
+#pragma unroll
+    for (int u = 0; u < SL; ++u) {
+        const int c = ri_opaque(code[u]), I = c & 15, J = (c >> 4) & 15;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) tw[4 * lk + v][li] = make_double2(invM * fr[u][v], invM * fi[u][v]);
+        ri_wave_sync();
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const double2 x = tw[4 * v + lk][li];
+            const int i = 16 * I + 4 * v + lk, j = 16 * J + li;
+            const bool ok = (c >> 8) && i < n && j < n;
+            const double dg = i == j ? (ok ? lam : 1.0) : 0.0;   // padding: identity
+            cre[u][v] = (ok ? x.x : 0.0) + dg;
+            cim[u][v] = ok ? x.y : 0.0;
+        }
+        ri_wave_sync();
+    }
+}
+
+template <int NT, bool COV>
 __global__ __launch_bounds__(kRiThreads) void resident_inverse_kernel(double2* a, int n, double lam,
-                                                                      int* status, long long mat0) {
+                                                                      int* status, long long mat0,
+                                                                      RiCov cv) {
     constexpr int NS = NT * (NT + 1) / 2;
     constexpr int SL = (NS + kRiWaves - 1) / kRiWaves;
-    __shared__ double2 Pt[NT][16][kRiS];   // Pt[I][kk][r] = P_I[r][kk]
-    __shared__ double2 Ft[NT][16][kRiS];   // Ft[I][kk][r] = F_I[r][kk]
-    __shared__ double2 Dt[16][kRiS];       // D row-major
+    constexpr int kBlk = 16 * kRiS;   // one staged 16 x 16 block (complex values)
+    // Pt[I][kk][r] = P_I[r][kk], Ft[I][kk][r] = F_I[r][kk], Dt = D row-major;
+    // while the covariance is formed, Pt's area holds the LDS chunks of the
+    // LS values and Ft's the per-wave blocks of the layout change
+    __shared__ double2 lds_all[(2 * NT + 1) * kBlk];
     __shared__ int bad;
+    double2(*Pt)[16][kRiS] = reinterpret_cast<double2(*)[16][kRiS]>(lds_all);
+    double2(*Ft)[16][kRiS] = reinterpret_cast<double2(*)[16][kRiS]>(lds_all + NT * kBlk);
+    double2(*Dt)[kRiS] = reinterpret_cast<double2(*)[kRiS]>(lds_all + 2 * NT * kBlk);
 
     const long long mat = blockIdx.x;
     double2* am = a + mat * n * n;
@@ -134,40 +317,46 @@ __global__ __launch_bounds__(kRiThreads) void resident_inverse_kernel(double2* a
         }
         code[u] = I | s << 4 | lv << 8;
     }
-    // Loads straight into the accumulators (real and imaginary parts as
-    // separate 8-byte loads, so no staging registers), all issued before any
-    // is used; then padding and lam on the diagonal.  Elements outside the
-    // matrix read its element 0 and are replaced.
     zd4 cre[SL], cim[SL];
-    const double* ad = reinterpret_cast<const double*>(am);
+    if constexpr (COV) {
+        ri_covariance<NT, SL>(cre, cim, code, cv, mat, n, lam, reinterpret_cast<float2*>(lds_all),
+                              reinterpret_cast<double2(*)[16][kRiS]>(lds_all + NT * kBlk)[w], tid, lane);
+    } else {
+        // Loads straight into the accumulators (real and imaginary parts as
+        // separate 8-byte loads, so no staging registers), all issued before
+        // any is used; then padding and lam on the diagonal.  Elements outside
+        // the matrix read its element 0 and are replaced.
+        const double* ad = reinterpret_cast<const double*>(am);
 #pragma unroll
-    for (int u = 0; u < SL; ++u) {
-        const int c = ri_opaque(code[u]), I = c & 15, J = (c >> 4) & 15;
+        for (int u = 0; u < SL; ++u) {
+            const int c = ri_opaque(code[u]), I = c & 15, J = (c >> 4) & 15;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int i = 16 * I + 4 * v + lk, j = 16 * J + li;
-            const long long e = (c >> 8) && i < n && j < n ? (long long)i * n + j : 0;
-            cre[u][v] = ad[2 * e];
-            cim[u][v] = ad[2 * e + 1];
+            for (int v = 0; v < 4; ++v) {
+                const int i = 16 * I + 4 * v + lk, j = 16 * J + li;
+                const long long e = (c >> 8) && i < n && j < n ? (long long)i * n + j : 0;
+                cre[u][v] = ad[2 * e];
+                cim[u][v] = ad[2 * e + 1];
+            }
         }
-    }
 #pragma unroll
-    for (int u = 0; u < SL; ++u) {
-        const int c = ri_opaque(code[u]), I = c & 15, J = (c >> 4) & 15;
+        for (int u = 0; u < SL; ++u) {
+            const int c = ri_opaque(code[u]), I = c & 15, J = (c >> 4) & 15;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int i = 16 * I + 4 * v + lk, j = 16 * J + li;
-            const bool ok = (c >> 8) && i < n && j < n;
-            const double dg = i == j ? (ok ? lam : 1.0) : 0.0;   // padding: identity
-            cre[u][v] = (ok ? cre[u][v] : 0.0) + dg;
-            cim[u][v] = ok ? cim[u][v] : 0.0;
+            for (int v = 0; v < 4; ++v) {
+                const int i = 16 * I + 4 * v + lk, j = 16 * J + li;
+                const bool ok = (c >> 8) && i < n && j < n;
+                const double dg = i == j ? (ok ? lam : 1.0) : 0.0;   // padding: identity
+                cre[u][v] = (ok ? cre[u][v] : 0.0) + dg;
+                cim[u][v] = ok ? cim[u][v] : 0.0;
+            }
         }
     }
     __syncthreads();
 
 #pragma unroll 1
     for (int k = 0; k < NT; ++k) {
-        // 1. P of the panel's sub-tiles, and the sweep of the diagonal one
+        // 1. P of the panel's sub-tiles and the diagonal block to LDS; the
+        //    holder of the diagonal block sweeps it there (D = -A_KK^-1)
 #pragma unroll
         for (int u = 0; u < SL; ++u) {
             const int c = ri_opaque(code[u]), I = c & 15, J = (c >> 4) & 15;
@@ -178,92 +367,88 @@ __global__ __launch_bounds__(kRiThreads) void resident_inverse_kernel(double2* a
             } else if (J == k && I > k) {   // (I, k): P_I[r][kk] = C[r][kk]
 #pragma unroll
                 for (int v = 0; v < 4; ++v) Pt[I][li][4 * v + lk] = make_double2(cre[u][v], cim[u][v]);
+            } else if (I == k && J == k) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) Dt[4 * v + lk][li] = make_double2(cre[u][v], cim[u][v]);
             }
         }
-        {
-            // the diagonal sub-tile, if this wave holds it (slot ud)
-            int ud = -1;
-#pragma unroll
-            for (int u = 0; u < SL; ++u)
-                if (code[u] == (k | k << 4 | 1 << 8)) ud = u;
-            if (ud >= 0) {
-                zd4 tr = cre[0], ti = cim[0];
-#pragma unroll
-                for (int u = 1; u < SL; ++u)
-                    if (u == ud) {
-                        tr = cre[u];
-                        ti = cim[u];
-                    }
-                if (!ri_sweep_diag(tr, ti, Dt, li, lk) && lane == 0) bad = 1;
-#pragma unroll
-                for (int u = 0; u < SL; ++u)
-                    if (u == ud) {
-                        cre[u] = tr;
-                        cim[u] = ti;
-                    }
-            }
-        }
+        if (w == (k * (k + 3) / 2) % kRiWaves) ri_sweep_staged(Dt, li, lk, bad, lane);
         __syncthreads();
         if (bad) {   // uniform: every wave leaves here
             if (tid == 0 && atomicCAS(status, 0, LMMSE_ERR_NOT_PD) == 0) status[1] = (int)(mat + mat0);
             return;
         }
-        // 2. F of the panel's sub-tiles
+        // 2. the panel's sub-tiles: F_I = -P_I D for (I, k), I > k, and
+        //    F_J^H = -D P_J^H for (k, J), J < k (the choice made once per slot:
+        //    a branch inside the product made the compiler copy the
+        //    accumulators around it); then D itself into sub-tile (k, k)
 #pragma unroll
         for (int u = 0; u < SL; ++u) {
             const int c = ri_opaque(code[u]), cI = c & 15, cJ = (c >> 4) & 15;
             if (!(c >> 8)) continue;
             const bool col = cJ == k && cI > k, row = cI == k && cJ < k;
             if (!col && !row) continue;
-            const int I = col ? cI : cJ;
-            zd4 fr = {0, 0, 0, 0}, fi = {0, 0, 0, 0};
+            cre[u] = zd4{0, 0, 0, 0};
+            cim[u] = zd4{0, 0, 0, 0};
+            if (col) {   // F_I = -P_I D: A = P_I[li][kk], B = D[kk][li]
+                const int I = cI;
 #pragma unroll
-            for (int ks = 0; ks < 4; ++ks) {
-                const int kk = 4 * ks + lk;
-                const double2 pv = Pt[I][kk][li];   // P_I[li][kk]
-                if (col) {   // F_I = -P_I D: A = P_I[li][kk], B = D[kk][li]
-                    const double2 dv = Dt[kk][li];
-                    fr = __builtin_amdgcn_mfma_f64_16x16x4f64(-pv.x, dv.x, fr, 0, 0, 0);
-                    fr = __builtin_amdgcn_mfma_f64_16x16x4f64(pv.y, dv.y, fr, 0, 0, 0);
-                    fi = __builtin_amdgcn_mfma_f64_16x16x4f64(-pv.x, dv.y, fi, 0, 0, 0);
-                    fi = __builtin_amdgcn_mfma_f64_16x16x4f64(-pv.y, dv.x, fi, 0, 0, 0);
-                } else {     // F_J^H = -D P_J^H: A = D[li][kk], B = conj(P_J[li][kk])
-                    const double2 dv = Dt[li][kk];
-                    fr = __builtin_amdgcn_mfma_f64_16x16x4f64(-dv.x, pv.x, fr, 0, 0, 0);
-                    fr = __builtin_amdgcn_mfma_f64_16x16x4f64(-dv.y, pv.y, fr, 0, 0, 0);
-                    fi = __builtin_amdgcn_mfma_f64_16x16x4f64(dv.x, pv.y, fi, 0, 0, 0);
-                    fi = __builtin_amdgcn_mfma_f64_16x16x4f64(-dv.y, pv.x, fi, 0, 0, 0);
+                for (int ks = 0; ks < 4; ++ks) {
+                    const int kk = 4 * ks + lk;
+                    const double2 av = Pt[I][kk][li], bv = Dt[kk][li];
+                    cre[u] = ri_mma<1>(av.x, bv.x, cre[u]);
+                    cim[u] = ri_mma<1>(av.x, bv.y, cim[u]);
+                    cre[u] = ri_mma<0>(av.y, bv.y, cre[u]);
+                    cim[u] = ri_mma<1>(av.y, bv.x, cim[u]);
                 }
-            }
-            cre[u] = fr;
-            cim[u] = fi;
+#pragma unroll   // F_I[4v + lk][li] -> Ft[I][li][4v + lk]
+                for (int v = 0; v < 4; ++v) Ft[I][li][4 * v + lk] = make_double2(cre[u][v], cim[u][v]);
+            } else {     // F_J^H = -D P_J^H: A = D[li][kk], B = conj(P_J[li][kk])
+                const int J = cJ;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                if (col)   // F_I[4v + lk][li]
-                    Ft[I][li][4 * v + lk] = make_double2(fr[v], fi[v]);
-                else       // F_J[li][4v + lk] = conj(F_J^H[4v + lk][li])
-                    Ft[I][4 * v + lk][li] = make_double2(fr[v], -fi[v]);
+                for (int ks = 0; ks < 4; ++ks) {
+                    const int kk = 4 * ks + lk;
+                    const double2 av = Dt[li][kk], bv = Pt[J][kk][li];
+                    cre[u] = ri_mma<1>(av.x, bv.x, cre[u]);
+                    cim[u] = ri_mma<0>(av.x, bv.y, cim[u]);
+                    cre[u] = ri_mma<1>(av.y, bv.y, cre[u]);
+                    cim[u] = ri_mma<1>(av.y, bv.x, cim[u]);
+                }
+#pragma unroll   // F_J[li][4v + lk] = conj(F_J^H[4v + lk][li]) -> Ft[J][4v + lk][li]
+                for (int v = 0; v < 4; ++v) Ft[J][4 * v + lk][li] = make_double2(cre[u][v], -cim[u][v]);
             }
             __builtin_amdgcn_sched_barrier(0);
         }
+#pragma unroll
+        for (int u = 0; u < SL; ++u) {
+            if (ri_opaque(code[u]) != (k | k << 4 | 1 << 8)) continue;
+            __asm__ volatile("");   // a branch, not selects over every slot
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const double2 x = Dt[4 * v + lk][li];
+                cre[u][v] = x.x;
+                cim[u][v] = x.y;
+            }
+        }
         __syncthreads();
-        // 3. C -= F_I P_J^H off the panel's row and column
+        // 3. C -= F_I P_J^H off the panel's row and column.  The first step's
+        //    operands of the next slot are read during this slot's products
+        //    (every slot's indices are valid, active or not), so that a wave,
+        //    which issues an FP64 product only every other turn of its SIMD,
+        //    does not wait on LDS between slots.
+        double2 f0 = Ft[code[0] & 15][lk][li], q0 = Pt[(code[0] >> 4) & 15][lk][li];
 #pragma unroll
         for (int u = 0; u < SL; ++u) {
             const int c = ri_opaque(code[u]), I = c & 15, J = (c >> 4) & 15;
-            if (!(c >> 8) || I == k || J == k) continue;
-#pragma unroll
-            for (int ks = 0; ks < 4; ++ks) {
-                const int kk = 4 * ks + lk;
-                const double2 fv = Ft[I][kk][li];   // F_I[li][kk]
-                const double2 pv = Pt[J][kk][li];   // P_J[li][kk]: B = conj
-                cre[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(-fv.x, pv.x, cre[u], 0, 0, 0);
-                cre[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(-fv.y, pv.y, cre[u], 0, 0, 0);
-                cim[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(-fv.y, pv.x, cim[u], 0, 0, 0);
-                cim[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(fv.x, pv.y, cim[u], 0, 0, 0);
+            double2 fn = f0, qn = q0;
+            if (u + 1 < SL) {
+                const int cn = ri_opaque(code[u + 1]);
+                fn = Ft[cn & 15][lk][li];
+                qn = Pt[(cn >> 4) & 15][lk][li];
             }
-            // one slot's operands at a time: reading ahead for every slot
-            // would hold 32 registers per slot
+            if ((c >> 8) && I != k && J != k) ri_update(cre[u], cim[u], Ft[I], Pt[J], f0, q0, li, lk);
+            f0 = fn;
+            q0 = qn;
             __builtin_amdgcn_sched_barrier(0);
         }
         __syncthreads();   // Pt, Ft and Dt are rewritten by the next panel
@@ -286,12 +471,15 @@ __global__ __launch_bounds__(kRiThreads) void resident_inverse_kernel(double2* a
 }
 
 // Sub-tile rows of the instantiated kernels (n <= 16 NT).
-constexpr int kRiNT[] = {4, 6, 8, 10, 11, 12, 13};
+constexpr int kRiNT[] = {4, 8, 10, 11, 12, 13};
 
 bool resident_inverse_fits(int n) { return n >= 1 && n <= 16 * 13; }
 
-hipError_t launch_resident_inverse(long long nmat, long long mat0, int n, double lam, double2* amat,
-                                   int* status, hipStream_t st) {
+// cov: when not null, A = X X^H / M + lam I is formed from the LS values in
+// the kernel (the window matrices in amat are then output only), for
+// windows wider than 144 subcarriers.
+static hipError_t launch_ri(long long nmat, long long mat0, int n, double lam, double2* amat, int* status,
+                            const RiCov* cov, hipStream_t st) {
     if (nmat == 0) return hipSuccess;
     if (!resident_inverse_fits(n)) return hipErrorInvalidValue;
     int nt = 0;
@@ -301,15 +489,39 @@ hipError_t launch_resident_inverse(long long nmat, long long mat0, int n, double
             break;
         }
     const dim3 grid((unsigned)nmat), block(kRiThreads);
-    switch (nt) {
+    const RiCov cv = cov ? *cov : RiCov{};
+    if (cov) {
+        switch (nt) {
+#define LMMSE_RIC(T) \
+    case T: hipLaunchKernelGGL((resident_inverse_kernel<T, true>), grid, block, 0, st, amat, n, lam, status, mat0, cv); break;
+            LMMSE_RIC(10) LMMSE_RIC(11) LMMSE_RIC(12) LMMSE_RIC(13)
+#undef LMMSE_RIC
+            default:
+                return hipErrorInvalidValue;
+        }
+    } else {
+        switch (nt) {
 #define LMMSE_RI(T) \
-    case T: hipLaunchKernelGGL((resident_inverse_kernel<T>), grid, block, 0, st, amat, n, lam, status, mat0); break;
-        LMMSE_RI(4) LMMSE_RI(6) LMMSE_RI(8) LMMSE_RI(10) LMMSE_RI(11) LMMSE_RI(12) LMMSE_RI(13)
+    case T: hipLaunchKernelGGL((resident_inverse_kernel<T, false>), grid, block, 0, st, amat, n, lam, status, mat0, cv); break;
+            LMMSE_RI(4) LMMSE_RI(8) LMMSE_RI(10) LMMSE_RI(11) LMMSE_RI(12) LMMSE_RI(13)
 #undef LMMSE_RI
-        default:
-            return hipErrorInvalidValue;
+            default:
+                return hipErrorInvalidValue;
+        }
     }
     return hipGetLastError();
+}
+
+hipError_t launch_resident_inverse(long long nmat, long long mat0, int n, double lam, double2* amat,
+                                   int* status, hipStream_t st) {
+    return launch_ri(nmat, mat0, n, lam, amat, status, nullptr, st);
+}
+
+hipError_t launch_resident_design(const Plan& p, long long nmat, long long mat0, const float2* hls, double lam,
+                                  double2* amat, hipStream_t st) {
+    if (p.d.Wn <= 144 || !resident_inverse_fits(p.d.Wn)) return hipErrorInvalidValue;
+    const RiCov cv{hls, p.d_starts, p.d.M, p.d.K, p.d.N, p.nb};
+    return launch_ri(nmat, mat0, p.d.Wn, lam, amat, p.status, &cv, st);
 }
 
 }  // namespace lmmse
