@@ -133,11 +133,14 @@ bool resident_inverse_fits(int n);
 hipError_t launch_resident_inverse(long long nmat, long long mat0, int n, double lam, double2* amat,
                                    int* status, hipStream_t st);
 // The sample design of windows 145..208 wide in the same kernel: R = X X^H / M
-// from the LS values (FP32 products and sums, as the batched product), then
-// -(R + lam I)^-1 into amat [nmat][Wn][Wn]; matrix indices as in
-// launch_sample_large (hls and nmat of one chunk of slots).
+// from the LS values (FP32 products and sums, as the batched product), its
+// inverse, and the block filters W = (I - lam A^-1)[off_b rows] into any of
+// w64 / w32 / whi, wlo (the layouts of launch_sample_large); with want_ainv
+// A^-1 into amat [nmat][Wn][Wn] (otherwise amat is not touched).  Matrix
+// indices as in launch_sample_large (hls and nmat of one chunk of slots).
 hipError_t launch_resident_design(const Plan& p, long long nmat, long long mat0, const float2* hls, double lam,
-                                  double2* amat, hipStream_t st);
+                                  double2* amat, double2* w64, float2* w32, uint32_t* whi, uint32_t* wlo,
+                                  bool want_ainv, hipStream_t st);
 // From S = -(R + lam I)^-1 as launch_sweep_inverse leaves it, the block
 // filters W = (I + lam S)[off_b rows] (w64 [mat][B][Wn]; offsets indexed by
 // mat % nb) and, with negate, A^-1 = -S in place.

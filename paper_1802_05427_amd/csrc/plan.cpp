@@ -451,7 +451,7 @@ int lmmse_sample_filters(lmmse_plan_t plan, int slots, const void* r_win, double
                                              nullptr, st));
         return LMMSE_OK;
     }
-    // wider windows: the panel sweep of a copy of the windows in ws
+    // wider windows: the sweep inverse of a copy of the windows in ws
     size_t need = 0;
     lmmse_sample_filters_workspace_size(&plan->d, slots, &need);
     if (!ws || ws_bytes < need) return LMMSE_ERR_WORKSPACE;

@@ -27,6 +27,7 @@
 //      real products per complex one, FP64 throughout.
 // After the NT panels the sub-tiles hold -A^-1, which is written back in
 // place (both triangles: each off-diagonal sub-tile and its mirror).
+#include "split.h"
 #include "zgemm.h"
 
 namespace lmmse {
@@ -193,7 +194,37 @@ struct RiCov {
     const float2* hls;
     const int* starts;
     int M, K, N, nb;
+    // the block filters straight from the registers: W = (I + lam S)[off
+    // rows] (S = -A^-1, off = offsets[b], B rows) into w64 [mat][B][Wn],
+    // w32 [mat][B][Wn rounded up to 2] or whi / wlo [mat][B][Wn rounded up
+    // to 4] (split, FP16 when fp16), any of them null; with ainv, A^-1 = -S
+    // into the window matrix, which is otherwise not written
+    const int* offsets;
+    int B;
+    double2* w64;
+    float2* w32;
+    uint32_t* whi;
+    uint32_t* wlo;
+    int fp16, ainv;
 };
+
+// Entry (o, col) of this window's block filter, w = delta + lam s.
+__device__ __forceinline__ void ri_store_w(const RiCov& cv, long long mat, int o, int col, int n, double2 w) {
+    const long long row = mat * cv.B + o;
+    if (cv.w64) cv.w64[row * n + col] = w;
+    if (cv.w32) cv.w32[row * ((n + 1) & ~1) + col] = make_float2((float)w.x, (float)w.y);
+    if (cv.whi) {
+        uint32_t h, l;
+        const float2 wf = make_float2((float)w.x, (float)w.y);
+        if (cv.fp16)
+            split_c<true>(wf, h, l);
+        else
+            split_c<false>(wf, h, l);
+        const int wq = (n + 3) & ~3;
+        cv.whi[row * wq + col] = h;
+        cv.wlo[row * wq + col] = l;
+    }
+}
 
 typedef float ri_f4 __attribute__((ext_vector_type(4)));
 
@@ -454,17 +485,54 @@ __global__ __launch_bounds__(kRiThreads) void resident_inverse_kernel(double2* a
         __syncthreads();   // Pt, Ft and Dt are rewritten by the next panel
     }
 
-    // -A^-1 back in place: each sub-tile, and the mirror of an off-diagonal one
+    if constexpr (COV) {
+        // the block filter rows (each sub-tile's kept rows, and those of the
+        // mirror of an off-diagonal one), their padding columns, and A^-1
+        // when asked for
+        const int off = cv.offsets[mat % cv.nb];
 #pragma unroll
-    for (int u = 0; u < SL; ++u) {
-        const int c = ri_opaque(code[u]), I = c & 15, J = (c >> 4) & 15;
-        if (!(c >> 8)) continue;
+        for (int u = 0; u < SL; ++u) {
+            const int c = ri_opaque(code[u]), I = c & 15, J = (c >> 4) & 15;
+            if (!(c >> 8)) continue;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int i = 16 * I + 4 * v + lk, j = 16 * J + li;
-            if (i < n && j < n) {
-                am[(long long)i * n + j] = make_double2(cre[u][v], cim[u][v]);
-                if (I != J) am[(long long)j * n + i] = make_double2(cre[u][v], -cim[u][v]);
+            for (int v = 0; v < 4; ++v) {
+                const int i = 16 * I + 4 * v + lk, j = 16 * J + li;
+                if (i >= n || j >= n) continue;
+                const double sx = cre[u][v], sy = cim[u][v];
+                if (cv.ainv) {
+                    am[(long long)i * n + j] = make_double2(-sx, -sy);
+                    if (I != J) am[(long long)j * n + i] = make_double2(-sx, sy);
+                }
+                if (i >= off && i < off + cv.B)
+                    ri_store_w(cv, mat, i - off, j, n, make_double2((i == j ? 1.0 : 0.0) + lam * sx, lam * sy));
+                if (I != J && j >= off && j < off + cv.B)
+                    ri_store_w(cv, mat, j - off, i, n, make_double2(lam * sx, -lam * sy));
+            }
+        }
+        const int pad = cv.whi ? ((n + 3) & ~3) - n : cv.w32 ? ((n + 1) & ~1) - n : 0;
+        for (int e = tid; e < cv.B * pad; e += kRiThreads) {
+            const int o = e / pad, col = n + e % pad;
+            const long long row = mat * cv.B + o;
+            if (cv.whi) {
+                cv.whi[row * (n + pad) + col] = 0u;
+                cv.wlo[row * (n + pad) + col] = 0u;
+            } else {
+                cv.w32[row * (n + pad) + col] = make_float2(0.f, 0.f);
+            }
+        }
+    } else {
+        // -A^-1 back in place: each sub-tile, and the mirror of an off-diagonal one
+#pragma unroll
+        for (int u = 0; u < SL; ++u) {
+            const int c = ri_opaque(code[u]), I = c & 15, J = (c >> 4) & 15;
+            if (!(c >> 8)) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = 16 * I + 4 * v + lk, j = 16 * J + li;
+                if (i < n && j < n) {
+                    am[(long long)i * n + j] = make_double2(cre[u][v], cim[u][v]);
+                    if (I != J) am[(long long)j * n + i] = make_double2(cre[u][v], -cim[u][v]);
+                }
             }
         }
     }
@@ -518,9 +586,12 @@ hipError_t launch_resident_inverse(long long nmat, long long mat0, int n, double
 }
 
 hipError_t launch_resident_design(const Plan& p, long long nmat, long long mat0, const float2* hls, double lam,
-                                  double2* amat, hipStream_t st) {
+                                  double2* amat, double2* w64, float2* w32, uint32_t* whi, uint32_t* wlo,
+                                  bool want_ainv, hipStream_t st) {
     if (p.d.Wn <= 144 || !resident_inverse_fits(p.d.Wn)) return hipErrorInvalidValue;
-    const RiCov cv{hls, p.d_starts, p.d.M, p.d.K, p.d.N, p.nb};
+    if ((whi == nullptr) != (wlo == nullptr) || (whi && w32)) return hipErrorInvalidValue;
+    const RiCov cv{hls, p.d_starts, p.d.M, p.d.K, p.d.N, p.nb, p.d_offsets, p.d.B, w64, w32, whi, wlo,
+                   p.d.precision == LMMSE_FP16X3 ? 1 : 0, want_ainv ? 1 : 0};
     return launch_ri(nmat, mat0, p.d.Wn, lam, amat, p.status, &cv, st);
 }
 

@@ -8,9 +8,9 @@
 //      lower tiles only (the upper ones are their mirror), stored as FP64;
 //   2. A = R + lam I;
 //   3. the Hermitian sweep of all Wn pivots: for Wn <= 208 in one launch
-//      with the matrix held on one compute unit, which also forms steps 1
-//      and 2 itself (resident_inverse.hip); wider, in panels of 64 pivots K
-//      (rest R): sweeping a panel at once maps
+//      with the matrix held on one compute unit, which also forms steps 1,
+//      2 and 4 itself (resident_inverse.hip); wider, in panels of 64 pivots
+//      K (rest R): sweeping a panel at once maps
 //          A_KK -> -A_KK^-1,  A_RK -> A_RK A_KK^-1,  A_KR -> A_KK^-1 A_KR,
 //          A_RR -> A_RR - A_RK A_KK^-1 A_KR,
 //      which equals sweeping its pivots one by one.  The panel kernel sweeps
@@ -362,13 +362,8 @@ hipError_t launch_sample_large(const Plan& p, long long nmat, long long mat0, co
     if (nmat == 0) return hipSuccess;
     if (Wn > kMaxSampleWindowLarge) return hipErrorInvalidValue;
     hipError_t e;
-    if (resident_inverse_fits(Wn)) {   // covariance and sweep in one kernel per window
-        if ((e = launch_resident_design(p, nmat, mat0, hls, lam, amat, st)) != hipSuccess) return e;
-        hipLaunchKernelGGL(large_filters_kernel, dim3((unsigned)nmat), dim3(256), 0, st, amat,
-                           p.d_offsets, d.B, Wn, p.nb, lam, w64, w32, whi, wlo,
-                           d.precision == LMMSE_FP16X3 ? 1 : 0, want_ainv ? 1 : 0);
-        return hipGetLastError();
-    }
+    if (resident_inverse_fits(Wn))   // covariance, sweep and filters in one kernel per window
+        return launch_resident_design(p, nmat, mat0, hls, lam, amat, w64, w32, whi, wlo, want_ainv, st);
     // R = X X^H / M
     ZGemmArgs ga{};
     ga.K = d.K;
