@@ -132,7 +132,7 @@ hipError_t launch_sweep_inverse(long long nmat, long long mat0, int n, int K, in
 bool resident_inverse_fits(int n);
 hipError_t launch_resident_inverse(long long nmat, long long mat0, int n, double lam, double2* amat,
                                    int* status, hipStream_t st);
-// The sample design of windows 145..208 wide in the same kernel: R = X X^H / M
+// The sample design of windows 161..208 wide in the same kernel: R = X X^H / M
 // from the LS values (FP32 products and sums, as the batched product), its
 // inverse, and the block filters W = (I - lam A^-1)[off_b rows] into any of
 // w64 / w32 / whi, wlo (the layouts of launch_sample_large); with want_ainv

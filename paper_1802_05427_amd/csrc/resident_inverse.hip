@@ -27,6 +27,18 @@
 //      real products per complex one, FP64 throughout.
 // After the NT panels the sub-tiles hold -A^-1, which is written back in
 // place (both triangles: each off-diagonal sub-tile and its mirror).
+//
+// The sample design of a window (COV): the kernel first forms A = X X^H / M
+// + lam I itself from the LS values (FP32 matrix-core products, as the
+// batched covariance product does them), and at the end writes the window's
+// block filter rows W = I + lam S (S = -A^-1) straight from the registers,
+// and A^-1 only when the backward needs it; the window matrix never goes to
+// memory otherwise.
+//
+// Time: the rank-16 updates are bound by the FP64 matrix cores (one
+// 16 x 16 x 4 product per SIMD every 64 cycles, whichever wave issues it);
+// the one-wave sweep of each diagonal block and the barriers around it are
+// the serial part.
 #include "split.h"
 #include "zgemm.h"
 
@@ -544,8 +556,8 @@ constexpr int kRiNT[] = {4, 8, 10, 11, 12, 13};
 bool resident_inverse_fits(int n) { return n >= 1 && n <= 16 * 13; }
 
 // cov: when not null, A = X X^H / M + lam I is formed from the LS values in
-// the kernel (the window matrices in amat are then output only), for
-// windows wider than 144 subcarriers.
+// the kernel and the block filters written from it (the window matrices in
+// amat are then output only), for windows of 161..208 subcarriers.
 static hipError_t launch_ri(long long nmat, long long mat0, int n, double lam, double2* amat, int* status,
                             const RiCov* cov, hipStream_t st) {
     if (nmat == 0) return hipSuccess;
@@ -562,7 +574,7 @@ static hipError_t launch_ri(long long nmat, long long mat0, int n, double lam, d
         switch (nt) {
 #define LMMSE_RIC(T) \
     case T: hipLaunchKernelGGL((resident_inverse_kernel<T, true>), grid, block, 0, st, amat, n, lam, status, mat0, cv); break;
-            LMMSE_RIC(10) LMMSE_RIC(11) LMMSE_RIC(12) LMMSE_RIC(13)
+            LMMSE_RIC(11) LMMSE_RIC(12) LMMSE_RIC(13)
 #undef LMMSE_RIC
             default:
                 return hipErrorInvalidValue;
@@ -588,7 +600,7 @@ hipError_t launch_resident_inverse(long long nmat, long long mat0, int n, double
 hipError_t launch_resident_design(const Plan& p, long long nmat, long long mat0, const float2* hls, double lam,
                                   double2* amat, double2* w64, float2* w32, uint32_t* whi, uint32_t* wlo,
                                   bool want_ainv, hipStream_t st) {
-    if (p.d.Wn <= 144 || !resident_inverse_fits(p.d.Wn)) return hipErrorInvalidValue;
+    if (p.d.Wn <= kMaxSampleWindowReg || !resident_inverse_fits(p.d.Wn)) return hipErrorInvalidValue;
     if ((whi == nullptr) != (wlo == nullptr) || (whi && w32)) return hipErrorInvalidValue;
     const RiCov cv{hls, p.d_starts, p.d.M, p.d.K, p.d.N, p.nb, p.d_offsets, p.d.B, w64, w32, whi, wlo,
                    p.d.precision == LMMSE_FP16X3 ? 1 : 0, want_ainv ? 1 : 0};

@@ -211,7 +211,7 @@ def _user_R(n, seed):
 @pytest.mark.parametrize("c", [
     dict(M=8, K=2, N=72, N_fft=128, B=12, Wn=24),
     dict(M=128, K=12, N=1200, N_fft=2048, B=100, Wn=150),
-    dict(M=16, K=2, N=800, N_fft=1024, B=100, Wn=200),     # panel sweep (Wn > 160)
+    dict(M=16, K=2, N=800, N_fft=1024, B=100, Wn=200),     # sweep inverse of a workspace copy (Wn > 160)
     dict(M=16, K=2, N=1200, N_fft=2048, B=1200, Wn=1200),  # full band
 ])
 def test_user_correlation(dev, c):

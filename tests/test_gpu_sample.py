@@ -34,14 +34,18 @@ CASES = [
 ]
 
 
-# windows wider than the register-resident sweep (workspace-resident design)
+# windows wider than the register-resident sweep: up to 208 the design held on
+# one compute unit (covariance, 16-pivot panels and filters in one kernel, 11,
+# 12 or 13 blocks of 16), wider the workspace-resident panel sweep
 LARGE = [
     dict(M=20, K=2, N=400, N_fft=512, taps=16, tau=4.0, B=100, Wn=200, slots=2),   # M < Wn
     dict(M=16, K=2, N=3300, N_fft=4096, taps=144, tau=32.0, B=132, Wn=198, slots=1),
-    dict(M=260, K=1, N=480, N_fft=512, taps=16, tau=4.0, B=120, Wn=240, slots=1),  # ragged M
+    dict(M=260, K=1, N=480, N_fft=512, taps=16, tau=4.0, B=120, Wn=240, slots=1),  # ragged M; panel sweep
     dict(M=24, K=1, N=512, N_fft=512, taps=16, tau=4.0, B=128, Wn=256, slots=1),   # widest: 4 panels of 64
-    dict(M=24, K=1, N=600, N_fft=1024, taps=16, tau=4.0, B=150, Wn=162, slots=1),  # narrowest: panels 64, 64, 34
-    dict(M=24, K=1, N=330, N_fft=512, taps=16, tau=4.0, B=55, Wn=165, slots=1),    # odd last panel (37 pivots)
+    dict(M=24, K=1, N=600, N_fft=1024, taps=16, tau=4.0, B=150, Wn=162, slots=1),  # narrowest: 11 blocks
+    dict(M=24, K=1, N=330, N_fft=512, taps=16, tau=4.0, B=55, Wn=165, slots=1),    # 11 blocks, odd B
+    dict(M=40, K=2, N=480, N_fft=512, taps=16, tau=4.0, B=120, Wn=180, slots=1),   # 12 blocks
+    dict(M=24, K=1, N=423, N_fft=512, taps=16, tau=4.0, B=141, Wn=209, slots=1),   # just past 208: panels
 ]
 
 
