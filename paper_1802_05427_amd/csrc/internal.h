@@ -117,6 +117,9 @@ size_t sample_backward_workspace_bytes(const lmmse_plan_desc& d, int slots);
 // workspace-resident one (sample_large.hip) used above it.
 constexpr int kMaxSampleWindowReg = 160;
 constexpr int kMaxSampleWindowLarge = 256;
+// Sample designs of windows wider than this (up to 208) run in the resident
+// kernel (resident_inverse.hip), narrower ones in sample.hip.
+constexpr int kResidentFp64Cov = 128;
 constexpr int kSweepPanel = 64;   // pivots per panel of the workspace-resident sweep
 // Windows wider than kMaxSampleWindowLarge: the push-through form (M x M
 // systems), for up to this many antennas.
@@ -132,12 +135,14 @@ hipError_t launch_sweep_inverse(long long nmat, long long mat0, int n, int K, in
 bool resident_inverse_fits(int n);
 hipError_t launch_resident_inverse(long long nmat, long long mat0, int n, double lam, double2* amat,
                                    int* status, hipStream_t st);
-// The sample design of windows 161..208 wide in the same kernel: R = X X^H / M
-// from the LS values (FP32 products and sums, as the batched product), its
+// The sample design of windows 129..208 wide in the same kernel
+// (resident_design_fits): R = X X^H / M from the LS values (FP64 products and
+// sums up to 160, FP32 ones as the batched product above), its
 // inverse, and the block filters W = (I - lam A^-1)[off_b rows] into any of
 // w64 / w32 / whi, wlo (the layouts of launch_sample_large); with want_ainv
 // A^-1 into amat [nmat][Wn][Wn] (otherwise amat is not touched).  Matrix
 // indices as in launch_sample_large (hls and nmat of one chunk of slots).
+bool resident_design_fits(int Wn);
 hipError_t launch_resident_design(const Plan& p, long long nmat, long long mat0, const float2* hls, double lam,
                                   double2* amat, double2* w64, float2* w32, uint32_t* whi, uint32_t* wlo,
                                   bool want_ainv, hipStream_t st);

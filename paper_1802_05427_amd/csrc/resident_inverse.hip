@@ -323,7 +323,81 @@ __device__ __forceinline__ void ri_covariance(zd4 (&cre)[SL], zd4 (&cim)[SL], co
     }
 }
 
-template <int NT, bool COV>
+// The same with FP64 products and sums on the FP64 matrix cores (the
+// products of FP32 values are exact in FP64): for windows up to 160, whose
+// covariance keeps FP64 sums.  The accumulators are the slots themselves,
+// already in the inverse's layout.
+template <int NT, int SL>
+__device__ __forceinline__ void ri_covariance64(zd4 (&cre)[SL], zd4 (&cim)[SL], const int (&code)[SL],
+                                                const RiCov& cv, long long mat, int n, double lam,
+                                                float2* xs, int tid, int lane) {
+    constexpr int R = 16 * NT;
+    constexpr int PT = (16 * R + kRiThreads - 1) / kRiThreads;
+    const int li = lane & 15, lk = lane >> 4;
+    const int b = (int)(mat % cv.nb);
+    const long long sk = mat / cv.nb;
+    const float2* xw = cv.hls + (sk / cv.K) * ((long long)cv.M * cv.K * cv.N) + (sk % cv.K) * cv.N +
+                       cv.starts[b];
+    const long long ms = (long long)cv.K * cv.N;
+    float2 pre[PT];
+    auto fetch = [&](int m0) {
+#pragma unroll
+        for (int t = 0; t < PT; ++t) {
+            const int e = tid + kRiThreads * t, m = e / R, j = e - m * R;
+            const bool ok = e < 16 * R && j < n && m0 + m < cv.M;
+            pre[t] = xw[ok ? (m0 + m) * ms + j : 0];
+            if (!ok) pre[t] = make_float2(0.f, 0.f);
+        }
+    };
+#pragma unroll
+    for (int u = 0; u < SL; ++u) {
+        cre[u] = zd4{0, 0, 0, 0};
+        cim[u] = zd4{0, 0, 0, 0};
+    }
+    fetch(0);
+    const int nch = (cv.M + 15) / 16;
+    for (int ch = 0; ch < nch; ++ch) {
+        float2* xb = xs + (ch & 1) * 16 * R;
+#pragma unroll
+        for (int t = 0; t < PT; ++t) {
+            const int e = tid + kRiThreads * t;
+            if (e < 16 * R) xb[e] = pre[t];
+        }
+        __syncthreads();
+        if (ch + 1 < nch) fetch(16 * (ch + 1));
+#pragma unroll
+        for (int u = 0; u < SL; ++u) {
+            const int c = ri_opaque(code[u]), I = c & 15, J = (c >> 4) & 15;
+            if (!(c >> 8)) continue;
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                const float2 x1 = xb[(4 * ks + lk) * R + 16 * I + li], x2 = xb[(4 * ks + lk) * R + 16 * J + li];
+                const double ax = x1.x, ay = x1.y, bx = x2.x, by = x2.y;
+                // x1 conj(x2): re = ax bx + ay by, im = ay bx - ax by
+                cre[u] = ri_mma<0>(ax, bx, cre[u]);
+                cim[u] = ri_mma<0>(ay, bx, cim[u]);
+                cre[u] = ri_mma<0>(ay, by, cre[u]);
+                cim[u] = ri_mma<1>(ax, by, cim[u]);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    const double invM = 1.0 / cv.M;
+#pragma unroll
+    for (int u = 0; u < SL; ++u) {
+        const int c = ri_opaque(code[u]), I = c & 15, J = (c >> 4) & 15;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = 16 * I + 4 * v + lk, j = 16 * J + li;
+            const bool ok = (c >> 8) && i < n && j < n;
+            const double dg = i == j ? (ok ? lam : 1.0) : 0.0;   // padding: identity
+            cre[u][v] = (ok ? invM * cre[u][v] : 0.0) + dg;
+            cim[u][v] = ok ? invM * cim[u][v] : 0.0;
+        }
+    }
+}
+
+template <int NT, int COV>
 __global__ __launch_bounds__(kRiThreads) void resident_inverse_kernel(double2* a, int n, double lam,
                                                                       int* status, long long mat0,
                                                                       RiCov cv) {
@@ -361,9 +435,11 @@ __global__ __launch_bounds__(kRiThreads) void resident_inverse_kernel(double2* a
         code[u] = I | s << 4 | lv << 8;
     }
     zd4 cre[SL], cim[SL];
-    if constexpr (COV) {
+    if constexpr (COV == 1) {
         ri_covariance<NT, SL>(cre, cim, code, cv, mat, n, lam, reinterpret_cast<float2*>(lds_all),
                               reinterpret_cast<double2(*)[16][kRiS]>(lds_all + NT * kBlk)[w], tid, lane);
+    } else if constexpr (COV == 2) {
+        ri_covariance64<NT, SL>(cre, cim, code, cv, mat, n, lam, reinterpret_cast<float2*>(lds_all), tid, lane);
     } else {
         // Loads straight into the accumulators (real and imaginary parts as
         // separate 8-byte loads, so no staging registers), all issued before
@@ -497,7 +573,7 @@ __global__ __launch_bounds__(kRiThreads) void resident_inverse_kernel(double2* a
         __syncthreads();   // Pt, Ft and Dt are rewritten by the next panel
     }
 
-    if constexpr (COV) {
+    if constexpr (COV != 0) {
         // the block filter rows (each sub-tile's kept rows, and those of the
         // mirror of an off-diagonal one), their padding columns, and A^-1
         // when asked for
@@ -557,9 +633,10 @@ bool resident_inverse_fits(int n) { return n >= 1 && n <= 16 * 13; }
 
 // cov: when not null, A = X X^H / M + lam I is formed from the LS values in
 // the kernel and the block filters written from it (the window matrices in
-// amat are then output only), for windows of 161..208 subcarriers.
+// amat are then output only): FP64 products and sums (cov64, windows of
+// 129..160) or FP32 ones (161..208).
 static hipError_t launch_ri(long long nmat, long long mat0, int n, double lam, double2* amat, int* status,
-                            const RiCov* cov, hipStream_t st) {
+                            const RiCov* cov, bool cov64, hipStream_t st) {
     if (nmat == 0) return hipSuccess;
     if (!resident_inverse_fits(n)) return hipErrorInvalidValue;
     int nt = 0;
@@ -570,10 +647,13 @@ static hipError_t launch_ri(long long nmat, long long mat0, int n, double lam, d
         }
     const dim3 grid((unsigned)nmat), block(kRiThreads);
     const RiCov cv = cov ? *cov : RiCov{};
-    if (cov) {
+    if (cov && cov64) {
+        if (nt != 10) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((resident_inverse_kernel<10, 2>), grid, block, 0, st, amat, n, lam, status, mat0, cv);
+    } else if (cov) {
         switch (nt) {
 #define LMMSE_RIC(T) \
-    case T: hipLaunchKernelGGL((resident_inverse_kernel<T, true>), grid, block, 0, st, amat, n, lam, status, mat0, cv); break;
+    case T: hipLaunchKernelGGL((resident_inverse_kernel<T, 1>), grid, block, 0, st, amat, n, lam, status, mat0, cv); break;
             LMMSE_RIC(11) LMMSE_RIC(12) LMMSE_RIC(13)
 #undef LMMSE_RIC
             default:
@@ -582,7 +662,7 @@ static hipError_t launch_ri(long long nmat, long long mat0, int n, double lam, d
     } else {
         switch (nt) {
 #define LMMSE_RI(T) \
-    case T: hipLaunchKernelGGL((resident_inverse_kernel<T, false>), grid, block, 0, st, amat, n, lam, status, mat0, cv); break;
+    case T: hipLaunchKernelGGL((resident_inverse_kernel<T, 0>), grid, block, 0, st, amat, n, lam, status, mat0, cv); break;
             LMMSE_RI(4) LMMSE_RI(8) LMMSE_RI(10) LMMSE_RI(11) LMMSE_RI(12) LMMSE_RI(13)
 #undef LMMSE_RI
             default:
@@ -594,17 +674,20 @@ static hipError_t launch_ri(long long nmat, long long mat0, int n, double lam, d
 
 hipError_t launch_resident_inverse(long long nmat, long long mat0, int n, double lam, double2* amat,
                                    int* status, hipStream_t st) {
-    return launch_ri(nmat, mat0, n, lam, amat, status, nullptr, st);
+    return launch_ri(nmat, mat0, n, lam, amat, status, nullptr, false, st);
 }
+
+bool resident_design_fits(int Wn) { return Wn > kResidentFp64Cov && resident_inverse_fits(Wn); }
 
 hipError_t launch_resident_design(const Plan& p, long long nmat, long long mat0, const float2* hls, double lam,
                                   double2* amat, double2* w64, float2* w32, uint32_t* whi, uint32_t* wlo,
                                   bool want_ainv, hipStream_t st) {
-    if (p.d.Wn <= kMaxSampleWindowReg || !resident_inverse_fits(p.d.Wn)) return hipErrorInvalidValue;
+    if (!resident_design_fits(p.d.Wn)) return hipErrorInvalidValue;
     if ((whi == nullptr) != (wlo == nullptr) || (whi && w32)) return hipErrorInvalidValue;
     const RiCov cv{hls, p.d_starts, p.d.M, p.d.K, p.d.N, p.nb, p.d_offsets, p.d.B, w64, w32, whi, wlo,
                    p.d.precision == LMMSE_FP16X3 ? 1 : 0, want_ainv ? 1 : 0};
-    return launch_ri(nmat, mat0, p.d.Wn, lam, amat, p.status, &cv, st);
+    // windows up to 160 keep FP64 sums in their covariance
+    return launch_ri(nmat, mat0, p.d.Wn, lam, amat, p.status, &cv, p.d.Wn <= kMaxSampleWindowReg, st);
 }
 
 }  // namespace lmmse

@@ -530,6 +530,8 @@ hipError_t launch_sample_inverse(const Plan& p, long long nmat, long long mat0, 
     if (p.d.Wn > kMaxSampleWindowReg)
         return launch_sample_large(p, nmat, mat0, hls, lam, ainv, scratch, w64, nullptr, nullptr,
                                    nullptr, true, st);
+    if (resident_design_fits(p.d.Wn))
+        return launch_resident_design(p, nmat, mat0, hls, lam, ainv, w64, nullptr, nullptr, nullptr, true, st);
     SampleArgs sa = base_args(p, lam);
     sa.mat0 = mat0;
     sa.hls = hls;
@@ -615,6 +617,9 @@ hipError_t launch_sample_estimate(const Plan& p, int slots, const float2* hls, d
                                     split ? wlo + m0 * p.d.B * wq : nullptr, false, st);
             if (e != hipSuccess) return e;
         }
+    } else if (resident_design_fits(p.d.Wn)) {   // the window held by one workgroup, no window matrix
+        e = launch_resident_design(p, nmat, 0, hls, lam, nullptr, nullptr, w32, whi, wlo, false, st);
+        if (e != hipSuccess) return e;
     } else {
         SampleArgs sa = base_args(p, lam);
         sa.hls = hls;
