@@ -301,6 +301,19 @@ int lmmse_backward(lmmse_plan_t plan, int slots, const void *h_ls,
                    const void *g, void *d_hls, double *d_tau, double *d_sigma2,
                    void *ws, size_t ws_bytes, void *stream);
 
+/* The same backward (the implicit differentiation of the eq. 13 / eq. 17
+ * block solves, Sec. IV-B) with the design-parameter gradients left on the
+ * device, for training loops that keep tau_rms and sigma2 on the GPU: no
+ * step waits for the host.  d_params, when not NULL, is device memory of
+ * two doubles written on `stream` after the backward's kernels:
+ * d_params[0] = d_tau and d_params[1] = d_sigma2, with the values and NaNs
+ * lmmse_backward returns.  Nothing is synchronised; d_params is the
+ * caller's.  Arguments and errors otherwise as lmmse_backward (d_params
+ * takes the place of requesting both scalars). */
+int lmmse_backward_dev(lmmse_plan_t plan, int slots, const void *h_ls,
+                       const void *g, void *d_hls, void *d_params,
+                       void *ws, size_t ws_bytes, void *stream);
+
 /* ---- estimate without a workspace argument ------------------------------- */
 
 /* For callers that cannot allocate device memory (code under HIP graph

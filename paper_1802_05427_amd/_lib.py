@@ -79,6 +79,8 @@ PROTOTYPES = {
                                        c_void_p]),
     "lmmse_backward": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, P_double,
                                P_double, c_void_p, c_size_t, c_void_p]),
+    "lmmse_backward_dev": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
+                                   c_void_p, c_size_t, c_void_p]),
     "lmmse_sync_status": (c_int, [c_void_p, c_void_p, P_int]),
     "lmmse_comb_validate": (c_int, [P_cdesc]),
     "lmmse_comb_create": (c_int, [P_cdesc, ctypes.POINTER(c_void_p)]),

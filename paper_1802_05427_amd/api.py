@@ -240,12 +240,23 @@ class Plan:
         return out
 
     # ---- backward
-    def backward(self, h_ls, g, want_params: bool = True, out=None, stream=None):
-        """Returns (d_hls, d_tau, d_sigma2); the scalars are None unless requested."""
+    def backward(self, h_ls, g, want_params: bool = True, out=None, stream=None, params_out=None):
+        """Returns (d_hls, d_tau, d_sigma2); the scalars are None unless requested.
+        With params_out (a device float64 tensor of 2 elements) the scalars stay
+        on the device (lmmse_backward_dev): params_out[0] and params_out[1] are
+        returned as tensors and nothing waits for the host."""
         S = self._check_cols(h_ls, "h_ls")
         self._check_cols(g, "g")
         out = torch.empty_like(h_ls) if out is None else out
         ws, wsb = self._workspace(S)
+        if params_out is not None:
+            if (not params_out.is_cuda or params_out.dtype != torch.float64 or params_out.numel() < 2
+                    or not params_out.is_contiguous()):
+                raise ValueError("params_out: contiguous device float64 tensor of 2 elements")
+            check(self._lib.lmmse_backward_dev(self._h, S, _ptr(h_ls), _ptr(g), _ptr(out),
+                                               _ptr(params_out), ws, wsb, _stream_ptr(stream)),
+                  "lmmse_backward_dev")
+            return out, params_out[0], params_out[1]
         dt = ctypes.c_double(math.nan)
         ds = ctypes.c_double(math.nan)
         check(self._lib.lmmse_backward(self._h, S, _ptr(h_ls), _ptr(g), _ptr(out),

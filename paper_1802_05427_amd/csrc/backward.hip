@@ -453,6 +453,22 @@ size_t backward_workspace_bytes(const lmmse_plan_desc& d, int slots) {
     return bw_layout(d, count_classes(d), g).total;
 }
 
+// The parameter gradients of lmmse_backward on the device: out[0] = d_tau
+// (EXPONENTIAL designs, else NaN), out[1] = d_sigma2 = dlam / K (not for
+// caller filters: NaN), the host call's values and arithmetic.
+__global__ void params_out_kernel(const double* __restrict__ dscal, double* __restrict__ out, int tau_ok,
+                                  int sig_ok, double K) {
+    out[0] = tau_ok ? dscal[0] : __builtin_nan("");
+    out[1] = sig_ok ? dscal[1] / K : __builtin_nan("");
+}
+
+hipError_t launch_params_out(const Plan& p, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(params_out_kernel, dim3(1), dim3(1), 0, st, p.dscal, out,
+                       p.d.rsource == LMMSE_R_EXPONENTIAL ? 1 : 0, p.d.rsource == LMMSE_R_USER ? 0 : 1,
+                       (double)p.d.K);
+    return hipGetLastError();
+}
+
 hipError_t launch_backward_fixed(Plan& p, int slots, const float2* hls, const float2* g,
                                  float2* dhls, bool want_params, void* ws, hipStream_t st) {
     const long long ncols = (long long)slots * p.d.M * p.d.K;

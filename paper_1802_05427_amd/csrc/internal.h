@@ -183,6 +183,8 @@ hipError_t launch_covariance_large(const Plan& p, long long nmat, const float2* 
 size_t backward_workspace_bytes(const lmmse_plan_desc& d, int slots);
 hipError_t launch_backward_fixed(Plan& p, int slots, const float2* hls, const float2* g,
                                  float2* dhls, bool want_params, void* ws, hipStream_t st);
+// d_tau, d_sigma2 of the last backward into device out[2] (lmmse_backward_dev).
+hipError_t launch_params_out(const Plan& p, double* out, hipStream_t st);
 hipError_t launch_backward_sample(Plan& p, int slots, const float2* hls, const float2* g,
                                   float2* dhls, double lam, bool want_sigma, void* ws,
                                   hipStream_t st);

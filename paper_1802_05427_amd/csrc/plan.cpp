@@ -520,11 +520,12 @@ int lmmse_estimate_ls(lmmse_plan_t plan, int slots, const void* h_ls, double sig
     return apply_dispatch(plan, slots, (const float2*)h_ls, nullptr, false, (float2*)h_hat, st);
 }
 
-int lmmse_backward(lmmse_plan_t plan, int slots, const void* h_ls, const void* g, void* d_hls,
-                   double* d_tau, double* d_sigma2, void* ws, size_t ws_bytes, void* stream) {
+// The backward's launches (both entry points): d_hls, and the parameter
+// gradients into plan->dscal when want.
+static int backward_launch(lmmse_plan_t plan, int slots, const void* h_ls, const void* g, void* d_hls,
+                           bool want, void* ws, size_t ws_bytes, hipStream_t st) {
     if (!plan || slots < 0 || slots > plan->d.max_slots) return LMMSE_ERR_INVALID_ARG;
     if (slots > 0 && (!h_ls || !g || !d_hls)) return LMMSE_ERR_INVALID_ARG;
-    const bool want = d_tau || d_sigma2;
     // windows wider than 256: no gradient through the sample covariance, and
     // no design-parameter gradients of the designed filters (dX alone is
     // supported for fixed, caller-correlation and caller filters)
@@ -533,8 +534,6 @@ int lmmse_backward(lmmse_plan_t plan, int slots, const void* h_ls, const void* g
         return LMMSE_ERR_UNSUPPORTED;
     const size_t need = backward_workspace_bytes(plan->d, slots);
     if (need && (!ws || ws_bytes < need)) return LMMSE_ERR_WORKSPACE;
-    const hipStream_t st = (hipStream_t)stream;
-    double h[4] = {NAN, NAN, NAN, NAN};
     if (plan->d.rsource == LMMSE_R_SAMPLE) {
         LMMSE_HIP_TRY(launch_backward_sample(*plan, slots, (const float2*)h_ls, (const float2*)g,
                                              (float2*)d_hls, plan->design_sigma2 / plan->d.K, want,
@@ -545,6 +544,16 @@ int lmmse_backward(lmmse_plan_t plan, int slots, const void* h_ls, const void* g
                                             (float2*)d_hls, want && plan->d.rsource != LMMSE_R_USER,
                                             ws, st));
     }
+    return LMMSE_OK;
+}
+
+int lmmse_backward(lmmse_plan_t plan, int slots, const void* h_ls, const void* g, void* d_hls,
+                   double* d_tau, double* d_sigma2, void* ws, size_t ws_bytes, void* stream) {
+    const bool want = d_tau || d_sigma2;
+    const hipStream_t st = (hipStream_t)stream;
+    const int rc = backward_launch(plan, slots, h_ls, g, d_hls, want, ws, ws_bytes, st);
+    if (rc != LMMSE_OK) return rc;
+    double h[4] = {NAN, NAN, NAN, NAN};
     if (want) {
         LMMSE_HIP_TRY(hipStreamSynchronize(st));
         if (plan->d.rsource != LMMSE_R_USER)
@@ -552,6 +561,15 @@ int lmmse_backward(lmmse_plan_t plan, int slots, const void* h_ls, const void* g
         if (d_tau) *d_tau = plan->d.rsource == LMMSE_R_EXPONENTIAL ? h[0] : NAN;
         if (d_sigma2) *d_sigma2 = plan->d.rsource == LMMSE_R_USER ? NAN : h[1] / plan->d.K;
     }
+    return LMMSE_OK;
+}
+
+int lmmse_backward_dev(lmmse_plan_t plan, int slots, const void* h_ls, const void* g, void* d_hls,
+                       void* d_params, void* ws, size_t ws_bytes, void* stream) {
+    const hipStream_t st = (hipStream_t)stream;
+    const int rc = backward_launch(plan, slots, h_ls, g, d_hls, d_params != nullptr, ws, ws_bytes, st);
+    if (rc != LMMSE_OK || !d_params) return rc;
+    LMMSE_HIP_TRY(launch_params_out(*plan, (double*)d_params, st));   // NaN where the host call gives NaN
     return LMMSE_OK;
 }
 

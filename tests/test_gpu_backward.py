@@ -107,3 +107,31 @@ def test_autograd_function(dev):
     assert abs(float(sig.grad) - gsig_o) <= 1e-3 * abs(gsig_o)
     ex = np.linalg.norm(h.grad.cpu().numpy() - dX_o) / np.linalg.norm(dX_o)
     assert ex < 1e-4
+
+
+@pytest.mark.parametrize("rsource", ["exp", "uniform"])
+def test_backward_device_params_match_host(dev, rsource):
+    """lmmse_backward_dev leaves d_tau / d_sigma2 on the device: the same
+    d_hls and the same two scalars (NaN where the host call gives NaN) as
+    lmmse_backward, bit for bit, on two calls in a row."""
+    c = dict(M=16, K=12, N=1200, N_fft=2048, taps=72, tau=4.0, B=100, Wn=150, slots=2)
+    print(f"device params {rsource} {c}", flush=True)
+    sb = make_slot_batch(M=c["M"], K=c["K"], N=c["N"], N_fft=c["N_fft"], taps=c["taps"], tau=c["tau"],
+                         snr_db=10.0, slots=c["slots"], config_id=3)
+    kw = dict(rsource=rsource, taps=c["taps"], tau_rms=6.0) if rsource == "exp" else dict(rsource=rsource, L=144.0)
+    with Plan(M=c["M"], K=c["K"], N=c["N"], N_fft=c["N_fft"], B=c["B"], Wn=c["Wn"], sigma2=1e-2,
+              max_slots=c["slots"], **kw) as plan:
+        h = _t(O.despread(sb.y, sb.pilots).astype(np.complex64), dev)
+        g = _t((sb.H * (2.0 / sb.H.size)).astype(np.complex64), dev)
+        dx_h, t_h, s_h = plan.backward(h, g)
+        par = torch.full((2,), 7.0, dtype=torch.float64, device=dev)
+        for _ in range(2):
+            dx_d, t_d, s_d = plan.backward(h, g, params_out=par)
+            torch.cuda.synchronize()
+            assert torch.equal(dx_d, dx_h)
+            got = par.cpu().numpy()
+            for gv, hv in zip(got, (t_h, s_h)):
+                assert (np.isnan(gv) and np.isnan(hv)) or gv == hv, (got, t_h, s_h)
+            par.fill_(7.0)
+    assert np.isfinite(s_h)
+    assert np.isfinite(t_h) == (rsource == "exp")
