@@ -145,6 +145,46 @@ def test_not_positive_definite_is_reported(dev):
     del c
 
 
+def test_not_positive_definite_is_reported_wide(dev):
+    """The stage-wise design of 200-wide windows (the resident inverse of the
+    given matrices): a window that is not positive definite is reported with
+    its index, the others are designed."""
+    with Plan(M=4, K=2, N=400, N_fft=512, B=100, Wn=200, rsource="sample", max_slots=1) as plan:
+        eye = torch.eye(200, dtype=torch.complex128, device=dev)
+        r = eye.expand(1, 2, 4, 200, 200).contiguous()
+        r[0, 1, 2] = -eye   # (k=1, b=2)
+        w = plan.sample_filters(r, 0.0)
+        st, info = plan.sync_status()
+        assert st == 5 and info == 1 * 4 + 2
+        assert plan.sync_status() == (0, -1)
+        # lam = 0 and A = I: W is the window's kept rows of the identity
+        _, offs = O.window_starts(400, 100, 200)
+        for b in (0, 1):
+            assert torch.equal(w[0, 0, b], eye[offs[b]:offs[b] + 100])
+
+
+@pytest.mark.parametrize("Wn,B,N,N_fft", [(198, 132, 660, 1024), (150, 100, 500, 512)])
+def test_resident_design_reports_a_nan_window(dev, Wn, B, N, N_fft):
+    """The sample estimate whose design holds each window on one compute unit
+    (FP32 covariance sums at 198, FP64 at 150): an LS value that is NaN makes
+    the pivots of the windows holding it fail, which is reported as NOT_PD
+    with one of their indices, and every workgroup still finishes."""
+    M, K = 8, 2
+    with Plan(M=M, K=K, N=N, N_fft=N_fft, B=B, Wn=Wn, rsource="sample", sigma2=0.1, max_slots=1) as plan:
+        g = torch.Generator(device=dev)
+        g.manual_seed(3)
+        h = torch.randn((1, M, K, N), dtype=torch.complex64, device=dev, generator=g)
+        n0 = N // 2
+        h[0, 3, 1, n0] = complex(float("nan"), 0.0)
+        plan.estimate_ls(h, 0.1)
+        st, info = plan.sync_status()
+    starts, _ = O.window_starts(N, B, Wn)
+    nb = N // B
+    expect = {1 * nb + b for b, s0 in enumerate(starts) if s0 <= n0 < s0 + Wn}
+    print(f"  status {st}, window {info}, windows holding the NaN {sorted(expect)}", flush=True)
+    assert st == 5 and info in expect
+
+
 @pytest.mark.parametrize("factor", [1e5, 1e-5])
 @pytest.mark.parametrize("Wn", [60, 200])
 def test_sample_design_is_scale_invariant(dev, factor, Wn):
