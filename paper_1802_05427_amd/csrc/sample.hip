@@ -602,7 +602,12 @@ hipError_t launch_sample_estimate(const Plan& p, int slots, const float2* hls, d
         }
         return hipSuccess;
     }
-    if (p.d.Wn > kMaxSampleWindowReg) {
+    if (resident_design_fits(p.d.Wn)) {
+        // every window of every slot in one launch: the forward keeps no
+        // window matrix, so nothing bounds the launch to a chunk of slots
+        e = launch_resident_design(p, nmat, 0, hls, lam, nullptr, nullptr, w32, whi, wlo, false, st);
+        if (e != hipSuccess) return e;
+    } else if (p.d.Wn > kMaxSampleWindowReg) {
         const int chunk = large_chunk(p.d, slots);
         const long long cm = (long long)chunk * p.d.K * p.nb;
         double2* amat = reinterpret_cast<double2*>((char*)ws + filter_area_bytes(p.d, nmat));
@@ -617,9 +622,6 @@ hipError_t launch_sample_estimate(const Plan& p, int slots, const float2* hls, d
                                     split ? wlo + m0 * p.d.B * wq : nullptr, false, st);
             if (e != hipSuccess) return e;
         }
-    } else if (resident_design_fits(p.d.Wn)) {   // the window held by one workgroup, no window matrix
-        e = launch_resident_design(p, nmat, 0, hls, lam, nullptr, nullptr, w32, whi, wlo, false, st);
-        if (e != hipSuccess) return e;
     } else {
         SampleArgs sa = base_args(p, lam);
         sa.hls = hls;
