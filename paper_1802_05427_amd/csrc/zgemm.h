@@ -89,6 +89,16 @@ struct ZMma<float> {
     __device__ static int row(int v, int lk) { return 4 * lk + v; }
 };
 
+// Workgroup id -> tile index such that each of the 8 XCDs (which take
+// workgroups round-robin) gets a contiguous range of tiles: the output tiles
+// of one batch entry, which read the same operand rows and columns, then run
+// side by side under one L2 instead of spread over all eight.
+__device__ __forceinline__ long long zgemm_tile_order(long long id, long long total) {
+    constexpr long long NX = 8;
+    const long long q = total / NX, r = total % NX, x = id % NX, k = id / NX;
+    return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
 // Bounded to three waves per SIMD (at most 168 registers per lane): two
 // waves per SIMD leave the matrix cores idle while a workgroup stages.
 template <typename TA, typename TB, typename TC, typename R>
@@ -98,7 +108,7 @@ __global__ __launch_bounds__(256, 3) void zgemm_mfma_kernel(ZGemmArgs g) {
     __shared__ CT As[zKC][zT];
     __shared__ CT Bs[zKC][zT];
     const int tid = threadIdx.x;
-    long long t = blockIdx.x;
+    long long t = zgemm_tile_order(blockIdx.x, gridDim.x);
     int tm, tn;
     long long bat;
     if (g.herm) {
