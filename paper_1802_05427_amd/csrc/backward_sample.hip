@@ -95,14 +95,26 @@ __global__ __launch_bounds__(256) void combine_windows_kernel(const float2* dxw,
     // a window that holds n starts within ceil(Wn / B) + 1 blocks of n's block
     const int bc = n / B, halo_blocks = (Wn + B - 1) / B + 1;
     const int blo = max(0, bc - halo_blocks), bhi = min(nb - 1, bc + halo_blocks);
+    // candidates four at a time, every load issued (a window that does not
+    // hold n reads its element 0 and adds nothing), so that a group's loads
+    // are in flight together; the sum runs in window order
     float sx = 0.f, sy = 0.f;
-    for (int b = blo; b <= bhi; ++b) {
-        const int j = n - starts[b];
-        if (j < 0 || j >= Wn) continue;
-        const long long mat = (s * K + k) * nb + b;
-        const float2 v = dxw[(mat * M + m) * Wn + j];
-        sx += v.x;
-        sy += v.y;
+    for (int b0 = blo; b0 <= bhi; b0 += 4) {
+        float2 v[4];
+        bool ok[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int b = min(b0 + u, bhi), j = n - starts[b];
+            ok[u] = b0 + u <= bhi && j >= 0 && j < Wn;
+            const long long mat = (s * K + k) * nb + b;
+            v[u] = dxw[(mat * M + m) * Wn + (ok[u] ? j : 0)];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (ok[u]) {
+                sx += v[u].x;
+                sy += v[u].y;
+            }
     }
     dhls[e] = make_float2(sx, sy);
 }
