@@ -22,49 +22,55 @@
 namespace lmmse {
 
 // Per window: dlam partial = Re tr(Gam) (Gam = -W^H Z as computed so far),
-// then Gam[off + o, :] += Z[o, :], then Gam -> S = (Gam + Gam^H) / M in place.
+// and S = (Gam' + Gam'^H) / M in place of Gam, where Gam' is Gam with Z's rows
+// added to rows off .. off + B - 1.  One pass over 32 x 32 tile pairs (I, J),
+// I >= J: both tiles are loaded with their Z rows (every load issued, element
+// 0 standing in outside, so that a tile's loads are in flight together) and
+// staged in LDS, so that every global access walks a row; the diagonal of
+// Gam is kept aside before Z is added, and summed in the order of a
+// 256-thread tree (Wn <= kMaxSampleWindowLarge = 256).
 __global__ __launch_bounds__(256) void gamma_rows_kernel(double2* gam, const double2* z,
                                                          const int* offsets, double* dlam_w, int B,
                                                          int Wn, int nb, double invM) {
     __shared__ double red[256];
+    __shared__ double dg[kMaxSampleWindowLarge];
+    __shared__ double2 t1[32][33], t2[32][33];
     const long long mat = blockIdx.x;
-    const int off = offsets[mat % nb];
+    const int tid = threadIdx.x, off = offsets[mat % nb];
     double2* gm = gam + mat * Wn * Wn;
     const double2* zm = z + mat * B * Wn;
-    double tr = 0.0;
-    for (int i = threadIdx.x; i < Wn; i += 256) tr += gm[(long long)i * Wn + i].x;
-    red[threadIdx.x] = tr;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) dlam_w[mat] = red[0];
-    // the trace is read before any row is changed
-    for (int e = threadIdx.x; e < B * Wn; e += 256) {
-        const int o = e / Wn, j = e - o * Wn;
-        double2& d = gm[(long long)(off + o) * Wn + j];
-        d.x += zm[e].x;
-        d.y += zm[e].y;
-    }
-    __syncthreads();
-    // S over 32 x 32 tile pairs (I, J), I >= J, both tiles staged in LDS so
-    // that every global access walks a row
-    __shared__ double2 t1[32][33], t2[32][33];
     const int nt = (Wn + 31) / 32;
     for (int I = 0; I < nt; ++I)
         for (int J = 0; J <= I; ++J) {
-            for (int e = threadIdx.x; e < 1024; e += 256) {
-                const int r = e >> 5, c = e & 31;
+            double2 a1[4], a2[4], z1[4], z2[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = tid + 256 * u, r = e >> 5, c = e & 31;
                 const int i1 = 32 * I + r, j1 = 32 * J + c, i2 = 32 * J + r, j2 = 32 * I + c;
-                t1[r][c] = (i1 < Wn && j1 < Wn) ? gm[(long long)i1 * Wn + j1] : make_double2(0.0, 0.0);
-                t2[r][c] = (i2 < Wn && j2 < Wn) ? gm[(long long)i2 * Wn + j2] : make_double2(0.0, 0.0);
+                const bool ok1 = i1 < Wn && j1 < Wn, ok2 = i2 < Wn && j2 < Wn;
+                const bool in1 = ok1 && i1 >= off && i1 < off + B, in2 = ok2 && i2 >= off && i2 < off + B;
+                a1[u] = gm[ok1 ? (long long)i1 * Wn + j1 : 0];
+                a2[u] = gm[ok2 ? (long long)i2 * Wn + j2 : 0];
+                z1[u] = zm[in1 ? (long long)(i1 - off) * Wn + j1 : 0];
+                z2[u] = zm[in2 ? (long long)(i2 - off) * Wn + j2 : 0];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = tid + 256 * u, r = e >> 5, c = e & 31;
+                const int i1 = 32 * I + r, j1 = 32 * J + c, i2 = 32 * J + r, j2 = 32 * I + c;
+                const bool ok1 = i1 < Wn && j1 < Wn, ok2 = i2 < Wn && j2 < Wn;
+                const bool in1 = ok1 && i1 >= off && i1 < off + B, in2 = ok2 && i2 >= off && i2 < off + B;
+                if (I == J && r == c && ok1) dg[i1] = a1[u].x;
+                t1[r][c] = !ok1 ? make_double2(0.0, 0.0)
+                                : in1 ? make_double2(a1[u].x + z1[u].x, a1[u].y + z1[u].y) : a1[u];
+                t2[r][c] = !ok2 ? make_double2(0.0, 0.0)
+                                : in2 ? make_double2(a2[u].x + z2[u].x, a2[u].y + z2[u].y) : a2[u];
             }
             __syncthreads();
-            for (int e = threadIdx.x; e < 1024; e += 256) {
+            for (int e = tid; e < 1024; e += 256) {
                 const int r = e >> 5, c = e & 31;
                 const int i1 = 32 * I + r, j1 = 32 * J + c, i2 = 32 * J + r, j2 = 32 * I + c;
-                // S[i1][j1] = (Gam[i1][j1] + conj(Gam[j1][i1])) / M, Gam[j1][i1] = t2[c][r]
+                // S[i1][j1] = (Gam'[i1][j1] + conj(Gam'[j1][i1])) / M, Gam'[j1][i1] = t2[c][r]
                 if (i1 < Wn && j1 < Wn) {
                     const double2 a = t1[r][c], b = t2[c][r];
                     gm[(long long)i1 * Wn + j1] = make_double2((a.x + b.x) * invM, (a.y - b.y) * invM);
@@ -76,6 +82,15 @@ __global__ __launch_bounds__(256) void gamma_rows_kernel(double2* gam, const dou
             }
             __syncthreads();
         }
+    double tr = 0.0;
+    for (int i = tid; i < Wn; i += 256) tr += dg[i];
+    red[tid] = tr;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) red[tid] += red[tid + w];
+        __syncthreads();
+    }
+    if (tid == 0) dlam_w[mat] = red[0];
 }
 
 // dhls[s, m, k, n] = sum over the windows b that hold n, in increasing b, of
@@ -220,6 +235,7 @@ hipError_t launch_backward_sample(Plan& p, int slots, const float2* hls, const f
                                   float2* dhls, double lam, bool want_sigma, void* ws,
                                   hipStream_t st) {
     const lmmse_plan_desc& d = p.d;
+    if (d.Wn > kMaxSampleWindowLarge) return hipErrorInvalidValue;   // gamma_rows_kernel's diagonal
     if ((long long)slots * d.K * p.nb == 0) return hipSuccess;
     const int chunk = sb_chunk(d, slots);
     const SbLayout L = sb_layout(d, chunk);
