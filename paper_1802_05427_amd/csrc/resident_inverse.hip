@@ -639,6 +639,9 @@ static hipError_t launch_ri(long long nmat, long long mat0, int n, double lam, d
                             const RiCov* cov, bool cov64, hipStream_t st) {
     if (nmat == 0) return hipSuccess;
     if (!resident_inverse_fits(n)) return hipErrorInvalidValue;
+    // one workgroup per matrix in a single grid, whose work-items must stay
+    // below 2^32 (about 8.4 million matrices)
+    if (nmat > (long long)(0xFFFFFFFFu / kRiThreads)) return hipErrorInvalidValue;
     int nt = 0;
     for (int c : kRiNT)
         if (16 * c >= n) {
