@@ -134,7 +134,9 @@ typedef struct lmmse_plan_desc {
     int Wn;          /* input window size                                   */
     int rsource;     /* lmmse_rsource                                       */
     int precision;   /* lmmse_precision                                     */
-    int max_slots;   /* largest S any call on this plan will pass  (>= 1)   */
+    int max_slots;   /* largest S any call on this plan will pass  (>= 1;
+                        max_slots * M * K * N < 2^32 coefficients, as
+                        per-coefficient kernels run one work-item each)   */
     int taps;        /* LMMSE_R_EXPONENTIAL: number of integer taps (>= 1)   */
     double tau_rms;  /* LMMSE_R_EXPONENTIAL: profile decay (> 0)            */
     double L;        /* LMMSE_R_UNIFORM: assumed channel length (> 0)       */

@@ -71,7 +71,9 @@ int validate(const lmmse_plan_desc* d) {
         return LMMSE_ERR_UNSUPPORTED;
     if (d->Wn > kMaxWindow) return LMMSE_ERR_UNSUPPORTED;
     const long long cols = (long long)d->max_slots * d->M * d->K;
-    if (cols * d->N >= (1LL << 40)) return LMMSE_ERR_UNSUPPORTED;
+    // per-coefficient kernels run one work-item per coefficient, and a grid's
+    // work-items stay below 2^32
+    if (cols * d->N >= (1LL << 32)) return LMMSE_ERR_UNSUPPORTED;
     // windows wider than the workspace-resident design: the push-through form
     // (M x M systems), FP32 product only
     if (d->rsource == LMMSE_R_SAMPLE && d->Wn > kMaxSampleWindowLarge &&

@@ -289,6 +289,7 @@ inline hipError_t zgemm(ZGemmArgs g, long long nbat, hipStream_t st) {
     const long long blocks =
         nbat * (g.herm ? (long long)g.tiles_m * (g.tiles_m + 1) / 2 : (long long)g.tiles_m * g.tiles_n);
     if (blocks == 0) return hipSuccess;
+    if (blocks > (long long)(0xFFFFFFFFu / 256)) return hipErrorInvalidValue;   // work-items < 2^32
     hipLaunchKernelGGL((zgemm_mfma_kernel<TA, TB, TC, R>), dim3((unsigned)blocks), dim3(256), 0, st, g);
     return hipGetLastError();
 }

@@ -59,6 +59,8 @@ def _d(**kw):
     dict(rsource="sample", B=300, Wn=300), dict(rsource="sample", B=100, Wn=300),
     dict(rsource="user_r"), dict(rsource="user_r", B=1200, Wn=1200),
     dict(rsource="user_r", precision="bf16x3"),
+    # largest batch of the paper-sized system: 2330 * 128 * 12 * 1200 < 2^32 coefficients
+    dict(max_slots=2330),
 ])
 def test_validate_accepts_workloads(lib, kw):
     d = _d(**kw)
@@ -79,6 +81,8 @@ def test_validate_accepts_workloads(lib, kw):
     (dict(rsource="sample", B=1200, Wn=1200, precision="fp16x3"), _lib.UNSUPPORTED),
     (dict(rsource="sample", B=1200, Wn=1200, M=300), _lib.UNSUPPORTED),
     (dict(rsource=5), _lib.INVALID_ARG), (dict(rsource="user_r", sigma2=0.0), _lib.INVALID_ARG),
+    # one work-item per coefficient: a batch of 2^32 coefficients or more is refused
+    (dict(max_slots=2331), _lib.UNSUPPORTED),
 ])
 def test_validate_rejects(lib, kw, code):
     d = _d(**kw)
