@@ -267,7 +267,8 @@ def large_sample(dev, stream, precision="fp16x3", slots=32, steps=3, warmup=1):
     of a 4096-point FFT, overlapping B=132 in windows of 198, 32 slots, tau_rms
     32 (144 taps), SNR 15 dB; FP64 design per (slot, user, window), split
     filter.  Forward (estimate from the pilot symbols) and one fwd+bwd step
-    (estimate from the LS values, MSE gradient, backward to h_ls and sigma2).
+    (estimate from the LS values keeping each window's FP64 design, MSE
+    gradient, backward to h_ls and sigma2 from the kept design).
     Accuracy: one seeded slot against the FP64 oracle on users 0 and 1."""
     import numpy as np
     import torch
@@ -311,15 +312,18 @@ def large_sample(dev, stream, precision="fp16x3", slots=32, steps=3, warmup=1):
         negcH = H * (-scale)   # MSE gradient = scale o + (-scale H), one pass per step
 
         par = torch.empty(2, dtype=torch.float64, device=dev)
+        # the forward keeps each window's FP64 design for the backward
+        # (lmmse_estimate_ls_keep / lmmse_backward_kept), about 20 GB here
+        kst = torch.empty(pl.design_state_bytes(slots), dtype=torch.uint8, device=dev)
 
         def step():
-            o = pl.estimate_ls(h, sigma2)
+            o = pl.estimate_ls(h, sigma2, keep=kst)
             gr = torch.add(negcH, o, alpha=scale)
-            return pl.backward(h, gr, want_params=True, params_out=par)
+            return pl.backward(h, gr, want_params=True, params_out=par, kept=kst)
         t_fb = time_calls(step, max(1, steps - 1), warmup, stream)
         res["fwd_bwd_ms"] = round(t_fb, 3)
         res["fwd_bwd_per_s"] = round(1e3 / t_fb, 3)
-        del out, h, negcH
+        del out, h, negcH, kst
     del y, H
     torch.cuda.empty_cache()
     # accuracy on one seeded host slot (users 0 and 1 against the oracle)

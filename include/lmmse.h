@@ -316,6 +316,43 @@ int lmmse_backward_dev(lmmse_plan_t plan, int slots, const void *h_ls,
                        const void *g, void *d_hls, void *d_params,
                        void *ws, size_t ws_bytes, void *stream);
 
+/* ---- sample design kept for the backward ---------------------------------- */
+
+/* Bytes of the design a sample-covariance forward can keep for its backward
+ * (eq. 13 per (slot, user, window), Sec. IV-B): for `slots` slots, each
+ * window's FP64 filter rows W (B x Wn) and (R + lam I)^-1 (Wn x Wn), complex
+ * doubles, [nmat][B][Wn] then [nmat][Wn][Wn] with nmat = slots * K * N / B
+ * (1.05 MB per window at B = 132, Wn = 198).  *bytes is 0 where the plan
+ * cannot keep it: not a sample plan, or windows outside 129..208 (the
+ * designs held by one compute unit). */
+int lmmse_design_state_size(lmmse_plan_t plan, int slots, size_t *bytes);
+
+/* lmmse_estimate_ls on a sample plan that also writes each window's FP64
+ * filter rows and inverse into `state` (device memory of
+ * lmmse_design_state_size bytes, the caller's), in the same launch and with
+ * the same arithmetic as the design lmmse_backward recomputes; h_hat is
+ * bit-identical to lmmse_estimate_ls's.  LMMSE_ERR_UNSUPPORTED where
+ * lmmse_design_state_size gives 0, LMMSE_ERR_WORKSPACE for a short state or
+ * ws (ws as for lmmse_estimate_ls). */
+int lmmse_estimate_ls_keep(lmmse_plan_t plan, int slots, const void *h_ls,
+                           double sigma2, void *h_hat, void *state,
+                           size_t state_bytes, void *ws, size_t ws_bytes,
+                           void *stream);
+
+/* lmmse_backward_dev on a sample plan with the design read from `state`
+ * instead of formed again: for training loops that run the forward and then
+ * the backward of the same batch.  The state must come from
+ * lmmse_estimate_ls_keep with the same slots and h_ls, and the plan's design
+ * sigma2 must not have changed since (the caller's contract: nothing checks
+ * it, and another h_ls gives the gradient of another estimate).  The state
+ * is only read, so several backward calls may use it.  Results are
+ * bit-identical to lmmse_backward_dev's.  Errors as lmmse_estimate_ls_keep
+ * and lmmse_backward_dev. */
+int lmmse_backward_kept(lmmse_plan_t plan, int slots, const void *h_ls,
+                        const void *g, void *d_hls, void *d_params,
+                        const void *state, size_t state_bytes, void *ws,
+                        size_t ws_bytes, void *stream);
+
 /* ---- estimate without a workspace argument ------------------------------- */
 
 /* For callers that cannot allocate device memory (code under HIP graph

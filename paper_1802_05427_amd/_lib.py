@@ -81,6 +81,11 @@ PROTOTYPES = {
                                P_double, c_void_p, c_size_t, c_void_p]),
     "lmmse_backward_dev": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
                                    c_void_p, c_size_t, c_void_p]),
+    "lmmse_design_state_size": (c_int, [c_void_p, c_int, P_size_t]),
+    "lmmse_estimate_ls_keep": (c_int, [c_void_p, c_int, c_void_p, c_double, c_void_p, c_void_p,
+                                       c_size_t, c_void_p, c_size_t, c_void_p]),
+    "lmmse_backward_kept": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
+                                    c_void_p, c_size_t, c_void_p, c_size_t, c_void_p]),
     "lmmse_sync_status": (c_int, [c_void_p, c_void_p, P_int]),
     "lmmse_comb_validate": (c_int, [P_cdesc]),
     "lmmse_comb_create": (c_int, [P_cdesc, ctypes.POINTER(c_void_p)]),

@@ -229,30 +229,62 @@ class Plan:
               "lmmse_estimate_noalloc")
         return out
 
-    def estimate_ls(self, h_ls, sigma2: float, out=None, stream=None) -> torch.Tensor:
-        """The estimator from LS estimates, h_ls -> h_hat (records sigma2 as the design noise)."""
+    def estimate_ls(self, h_ls, sigma2: float, out=None, stream=None, keep=None) -> torch.Tensor:
+        """The estimator from LS estimates, h_ls -> h_hat (records sigma2 as the design noise).
+        keep: a device uint8 tensor of design_state_bytes(S) bytes that receives the
+        sample design for backward(..., kept=keep) (lmmse_estimate_ls_keep)."""
         S = self._check_cols(h_ls, "h_ls")
         out = torch.empty_like(h_ls) if out is None else out
         self._check_cols(out, "out")
         ws, wsb = self._workspace(S)
+        if keep is not None:
+            self._check_state(keep)
+            check(self._lib.lmmse_estimate_ls_keep(self._h, S, _ptr(h_ls), float(sigma2), _ptr(out),
+                                                   _ptr(keep), int(keep.numel()), ws, wsb,
+                                                   _stream_ptr(stream)), "lmmse_estimate_ls_keep")
+            return out
         check(self._lib.lmmse_estimate_ls(self._h, S, _ptr(h_ls), float(sigma2), _ptr(out), ws, wsb,
                                           _stream_ptr(stream)), "lmmse_estimate_ls")
         return out
 
+    def design_state_bytes(self, slots: int) -> int:
+        """Bytes of the sample design estimate_ls(..., keep=) keeps (0: not available)."""
+        b = ctypes.c_size_t(0)
+        check(self._lib.lmmse_design_state_size(self._h, int(slots), ctypes.byref(b)),
+              "lmmse_design_state_size")
+        return b.value
+
+    @staticmethod
+    def _check_state(t):
+        if not t.is_cuda or t.dtype != torch.uint8 or not t.is_contiguous():
+            raise ValueError("design state: contiguous device uint8 tensor")
+
     # ---- backward
-    def backward(self, h_ls, g, want_params: bool = True, out=None, stream=None, params_out=None):
+    def backward(self, h_ls, g, want_params: bool = True, out=None, stream=None, params_out=None,
+                 kept=None):
         """Returns (d_hls, d_tau, d_sigma2); the scalars are None unless requested.
         With params_out (a device float64 tensor of 2 elements) the scalars stay
         on the device (lmmse_backward_dev): params_out[0] and params_out[1] are
-        returned as tensors and nothing waits for the host."""
+        returned as tensors and nothing waits for the host.  kept: the design
+        state estimate_ls(h_ls, ..., keep=) filled for this h_ls
+        (lmmse_backward_kept; needs params_out)."""
         S = self._check_cols(h_ls, "h_ls")
         self._check_cols(g, "g")
+        if kept is not None and params_out is None:
+            raise ValueError("kept: the kept-design backward leaves the scalars on the device; pass params_out")
         out = torch.empty_like(h_ls) if out is None else out
         ws, wsb = self._workspace(S)
         if params_out is not None:
             if (not params_out.is_cuda or params_out.dtype != torch.float64 or params_out.numel() < 2
                     or not params_out.is_contiguous()):
                 raise ValueError("params_out: contiguous device float64 tensor of 2 elements")
+            if kept is not None:
+                self._check_state(kept)
+                check(self._lib.lmmse_backward_kept(self._h, S, _ptr(h_ls), _ptr(g), _ptr(out),
+                                                    _ptr(params_out), _ptr(kept), int(kept.numel()),
+                                                    ws, wsb, _stream_ptr(stream)),
+                      "lmmse_backward_kept")
+                return out, params_out[0], params_out[1]
             check(self._lib.lmmse_backward_dev(self._h, S, _ptr(h_ls), _ptr(g), _ptr(out),
                                                _ptr(params_out), ws, wsb, _stream_ptr(stream)),
                   "lmmse_backward_dev")

@@ -233,7 +233,7 @@ size_t sample_backward_workspace_bytes(const lmmse_plan_desc& d, int slots) {
 
 hipError_t launch_backward_sample(Plan& p, int slots, const float2* hls, const float2* g,
                                   float2* dhls, double lam, bool want_sigma, void* ws,
-                                  hipStream_t st) {
+                                  hipStream_t st, const double2* kept_w64, const double2* kept_ainv) {
     const lmmse_plan_desc& d = p.d;
     if (d.Wn > kMaxSampleWindowLarge) return hipErrorInvalidValue;   // gamma_rows_kernel's diagonal
     if ((long long)slots * d.K * p.nb == 0) return hipSuccess;
@@ -257,8 +257,17 @@ hipError_t launch_backward_sample(Plan& p, int slots, const float2* hls, const f
         const float2* hc = hls + s0 * per_slot;
         const float2* gc = g + s0 * per_slot;
 
-        e = launch_sample_inverse(p, nmat, mat0, hc, lam, w64, ainv, (double2*)(w + L.panel), st);
-        if (e != hipSuccess) return e;
+        // the chunk's W rows and A^-1: kept by the forward, or designed again
+        // into the workspace; Gam then goes to the workspace's A^-1 area
+        const double2* wsrc = w64;
+        const double2* asrc = ainv;
+        if (kept_ainv) {
+            wsrc = kept_w64 + mat0 * B * Wn;
+            asrc = kept_ainv + mat0 * Wn * Wn;
+        } else {
+            e = launch_sample_inverse(p, nmat, mat0, hc, lam, w64, ainv, (double2*)(w + L.panel), st);
+            if (e != hipSuccess) return e;
+        }
 
         ZGemmArgs ga{};
         ga.K = d.K;
@@ -275,12 +284,12 @@ hipError_t launch_backward_sample(Plan& p, int slots, const float2* hls, const f
         if ((e = zgemm<float2, float2, double2>(ga, nmat, st)) != hipSuccess) return e;
         // Z = dW A^-1
         ga.A = wview(dw, d, B, Wn, false);
-        ga.B = wview(ainv, d, Wn, Wn, false);
+        ga.B = wview(asrc, d, Wn, Wn, false);
         ga.C = wview(z, d, B, Wn, false);
         ga.kd = Wn;
         if ((e = zgemm<double2, double2, double2>(ga, nmat, st)) != hipSuccess) return e;
-        // Gam = -W^H Z (over A^-1, which is no longer needed)
-        ga.A = wview(w64, d, B, Wn, true);
+        // Gam = -W^H Z (over the workspace's A^-1, which is no longer needed)
+        ga.A = wview(wsrc, d, B, Wn, true);
         ga.B = wview(z, d, B, Wn, false);
         ga.C = wview(ainv, d, Wn, Wn, false);
         ga.m = Wn;
@@ -300,7 +309,7 @@ hipError_t launch_backward_sample(Plan& p, int slots, const float2* hls, const f
         cx.s_blk = (long long)M * Wn;
         cx.s_user = cx.s_blk * p.nb;
         cx.s_slot = cx.s_user * d.K;
-        ga.A = wview(w64, d, B, Wn, true);
+        ga.A = wview(wsrc, d, B, Wn, true);
         ga.B = hview(d, gc, nullptr, B, 0, false);
         ga.C = cx;
         ga.m = Wn;

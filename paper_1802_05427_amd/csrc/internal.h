@@ -102,8 +102,12 @@ hipError_t launch_covariance(const Plan& p, int slots, const float2* hls, double
 // when ainv is not null, A^-1 = (R + lam I)^-1 [nmat][Wn][Wn] (row-major).
 hipError_t launch_batched_filters(const Plan& p, long long nmat, const double2* r_win, double lam,
                                   double2* w_out, double2* ainv, hipStream_t st);
+// keep_w64 / keep_ainv (both or neither; windows resident_design_fits):
+// each window's FP64 filter rows [nmat][B][Wn] and (R + lam I)^-1
+// [nmat][Wn][Wn] as well, for a backward that does not redesign.
 hipError_t launch_sample_estimate(const Plan& p, int slots, const float2* hls, double lam,
-                                  float2* out, void* ws, hipStream_t st);
+                                  float2* out, void* ws, hipStream_t st,
+                                  double2* keep_w64 = nullptr, double2* keep_ainv = nullptr);
 size_t sample_workspace_bytes(const lmmse_plan_desc& d, int slots);
 // Per (slot, user, block) window of the sample design: W (FP64 [nmat][B][Wn])
 // and A^-1 = (R + lam I)^-1 (FP64 [nmat][Wn][Wn], both triangles); scratch:
@@ -185,8 +189,11 @@ hipError_t launch_backward_fixed(Plan& p, int slots, const float2* hls, const fl
                                  float2* dhls, bool want_params, void* ws, hipStream_t st);
 // d_tau, d_sigma2 of the last backward into device out[2] (lmmse_backward_dev).
 hipError_t launch_params_out(const Plan& p, double* out, hipStream_t st);
+// kept_w64 / kept_ainv: the design of launch_sample_estimate's keep buffers
+// for the same h_ls and lam (not recomputed); null: designed again here.
 hipError_t launch_backward_sample(Plan& p, int slots, const float2* hls, const float2* g,
                                   float2* dhls, double lam, bool want_sigma, void* ws,
-                                  hipStream_t st);
+                                  hipStream_t st, const double2* kept_w64 = nullptr,
+                                  const double2* kept_ainv = nullptr);
 
 }  // namespace lmmse

@@ -522,10 +522,46 @@ int lmmse_estimate_ls(lmmse_plan_t plan, int slots, const void* h_ls, double sig
     return apply_dispatch(plan, slots, (const float2*)h_ls, nullptr, false, (float2*)h_hat, st);
 }
 
-// The backward's launches (both entry points): d_hls, and the parameter
-// gradients into plan->dscal when want.
+// The design a sample forward keeps for its backward: W rows [nmat][B][Wn],
+// then A^-1 [nmat][Wn][Wn], FP64 complex; windows the resident design holds.
+static size_t kept_design_bytes(const lmmse_plan_desc& d, int slots) {
+    if (d.rsource != LMMSE_R_SAMPLE || !resident_design_fits(d.Wn) || slots <= 0) return 0;
+    const long long nmat = (long long)slots * d.K * (d.N / d.B);
+    return (size_t)nmat * ((size_t)d.B * d.Wn + (size_t)d.Wn * d.Wn) * sizeof(double2);
+}
+
+int lmmse_design_state_size(lmmse_plan_t plan, int slots, size_t* bytes) {
+    if (!plan || !bytes || slots < 0 || slots > plan->d.max_slots) return LMMSE_ERR_INVALID_ARG;
+    *bytes = kept_design_bytes(plan->d, slots);
+    return LMMSE_OK;
+}
+
+int lmmse_estimate_ls_keep(lmmse_plan_t plan, int slots, const void* h_ls, double sigma2, void* h_hat,
+                           void* state, size_t state_bytes, void* ws, size_t ws_bytes, void* stream) {
+    if (!plan || slots < 0 || slots > plan->d.max_slots) return LMMSE_ERR_INVALID_ARG;
+    if (!(sigma2 > 0.0) || !std::isfinite(sigma2)) return LMMSE_ERR_INVALID_ARG;
+    if (plan->d.rsource != LMMSE_R_SAMPLE || !resident_design_fits(plan->d.Wn))
+        return LMMSE_ERR_UNSUPPORTED;
+    if (slots == 0) return LMMSE_OK;
+    if (!h_ls || !h_hat || !state) return LMMSE_ERR_INVALID_ARG;
+    if (state_bytes < kept_design_bytes(plan->d, slots)) return LMMSE_ERR_WORKSPACE;
+    if (!ws || ws_bytes < sample_workspace_bytes(plan->d, slots)) return LMMSE_ERR_WORKSPACE;
+    plan->design_sigma2 = sigma2;
+    const long long nmat = (long long)slots * plan->d.K * plan->nb;
+    double2* kw = (double2*)state;
+    double2* ka = kw + nmat * plan->d.B * plan->d.Wn;
+    LMMSE_HIP_TRY(launch_sample_estimate(*plan, slots, (const float2*)h_ls, sigma2 / plan->d.K,
+                                         (float2*)h_hat, (char*)ws + hls_bytes(plan->d, slots),
+                                         (hipStream_t)stream, kw, ka));
+    return LMMSE_OK;
+}
+
+// The backward's launches (every entry point): d_hls, and the parameter
+// gradients into plan->dscal when want; kept: a sample plan's design kept by
+// lmmse_estimate_ls_keep (null: designed again).
 static int backward_launch(lmmse_plan_t plan, int slots, const void* h_ls, const void* g, void* d_hls,
-                           bool want, void* ws, size_t ws_bytes, hipStream_t st) {
+                           bool want, void* ws, size_t ws_bytes, hipStream_t st,
+                           const void* kept = nullptr) {
     if (!plan || slots < 0 || slots > plan->d.max_slots) return LMMSE_ERR_INVALID_ARG;
     if (slots > 0 && (!h_ls || !g || !d_hls)) return LMMSE_ERR_INVALID_ARG;
     // windows wider than 256: no gradient through the sample covariance, and
@@ -537,9 +573,12 @@ static int backward_launch(lmmse_plan_t plan, int slots, const void* h_ls, const
     const size_t need = backward_workspace_bytes(plan->d, slots);
     if (need && (!ws || ws_bytes < need)) return LMMSE_ERR_WORKSPACE;
     if (plan->d.rsource == LMMSE_R_SAMPLE) {
+        const long long nmat = (long long)slots * plan->d.K * plan->nb;
+        const double2* kw = (const double2*)kept;
+        const double2* ka = kw ? kw + nmat * plan->d.B * plan->d.Wn : nullptr;
         LMMSE_HIP_TRY(launch_backward_sample(*plan, slots, (const float2*)h_ls, (const float2*)g,
                                              (float2*)d_hls, plan->design_sigma2 / plan->d.K, want,
-                                             ws, st));
+                                             ws, st, kw, ka));
     } else {
         if (!plan->ready) return LMMSE_ERR_NOT_READY;
         LMMSE_HIP_TRY(launch_backward_fixed(*plan, slots, (const float2*)h_ls, (const float2*)g,
@@ -572,6 +611,22 @@ int lmmse_backward_dev(lmmse_plan_t plan, int slots, const void* h_ls, const voi
     const int rc = backward_launch(plan, slots, h_ls, g, d_hls, d_params != nullptr, ws, ws_bytes, st);
     if (rc != LMMSE_OK || !d_params) return rc;
     LMMSE_HIP_TRY(launch_params_out(*plan, (double*)d_params, st));   // NaN where the host call gives NaN
+    return LMMSE_OK;
+}
+
+int lmmse_backward_kept(lmmse_plan_t plan, int slots, const void* h_ls, const void* g, void* d_hls,
+                        void* d_params, const void* state, size_t state_bytes, void* ws,
+                        size_t ws_bytes, void* stream) {
+    if (!plan || slots < 0 || slots > plan->d.max_slots) return LMMSE_ERR_INVALID_ARG;
+    if (plan->d.rsource != LMMSE_R_SAMPLE || !resident_design_fits(plan->d.Wn))
+        return LMMSE_ERR_UNSUPPORTED;
+    if (slots > 0 && (!state || state_bytes < kept_design_bytes(plan->d, slots)))
+        return state ? LMMSE_ERR_WORKSPACE : LMMSE_ERR_INVALID_ARG;
+    const hipStream_t st = (hipStream_t)stream;
+    const int rc = backward_launch(plan, slots, h_ls, g, d_hls, d_params != nullptr, ws, ws_bytes, st,
+                                   state);
+    if (rc != LMMSE_OK || !d_params) return rc;
+    LMMSE_HIP_TRY(launch_params_out(*plan, (double*)d_params, st));
     return LMMSE_OK;
 }
 

@@ -578,9 +578,12 @@ size_t sample_workspace_bytes(const lmmse_plan_desc& d, int slots) {
 }
 
 hipError_t launch_sample_estimate(const Plan& p, int slots, const float2* hls, double lam,
-                                  float2* out, void* ws, hipStream_t st) {
+                                  float2* out, void* ws, hipStream_t st, double2* keep_w64,
+                                  double2* keep_ainv) {
     const long long nmat = (long long)slots * p.d.K * p.nb;
     if (nmat == 0) return hipSuccess;
+    if ((keep_w64 == nullptr) != (keep_ainv == nullptr) || (keep_w64 && !resident_design_fits(p.d.Wn)))
+        return hipErrorInvalidValue;
     const bool split = p.d.precision != LMMSE_FP32;
     const int wp = (p.d.Wn + 1) & ~1, wq = (p.d.Wn + 3) & ~3;
     float2* w32 = split ? nullptr : reinterpret_cast<float2*>(ws);
@@ -605,7 +608,8 @@ hipError_t launch_sample_estimate(const Plan& p, int slots, const float2* hls, d
     if (resident_design_fits(p.d.Wn)) {
         // every window of every slot in one launch: the forward keeps no
         // window matrix, so nothing bounds the launch to a chunk of slots
-        e = launch_resident_design(p, nmat, 0, hls, lam, nullptr, nullptr, w32, whi, wlo, false, st);
+        e = launch_resident_design(p, nmat, 0, hls, lam, keep_ainv, keep_w64, w32, whi, wlo,
+                                   keep_ainv != nullptr, st);
         if (e != hipSuccess) return e;
     } else if (p.d.Wn > kMaxSampleWindowReg) {
         const int chunk = large_chunk(p.d, slots);

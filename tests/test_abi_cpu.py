@@ -100,6 +100,9 @@ def test_null_arguments(lib):
     assert lib.lmmse_estimate(None, 1, None, None, 0.1, None, None, 0, None) == _lib.INVALID_ARG
     assert lib.lmmse_backward(None, 1, None, None, None, None, None, None, 0, None) == _lib.INVALID_ARG
     assert lib.lmmse_backward_dev(None, 1, None, None, None, None, None, 0, None) == _lib.INVALID_ARG
+    assert lib.lmmse_design_state_size(None, 1, None) == _lib.INVALID_ARG
+    assert lib.lmmse_estimate_ls_keep(None, 1, None, 0.1, None, None, 0, None, 0, None) == _lib.INVALID_ARG
+    assert lib.lmmse_backward_kept(None, 1, None, None, None, None, None, 0, None, 0, None) == _lib.INVALID_ARG
     assert lib.lmmse_sync_status(None, None, None) == _lib.INVALID_ARG
 
 

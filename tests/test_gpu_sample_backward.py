@@ -136,3 +136,64 @@ def test_sample_autograd_function(dev):
     assert abs(float(sig.grad) - gsig_o) <= 1e-3 * abs(gsig_o)
     ex = np.linalg.norm(h.grad.cpu().numpy() - dX_o) / np.linalg.norm(dX_o)
     assert ex < 1e-4
+
+
+KEEP_CASES = [
+    # FP32 matrix-core covariance in the resident design (windows 161..208)
+    dict(M=40, K=2, N=396, N_fft=512, taps=16, tau=4.0, B=132, Wn=198, slots=1),
+    # FP64 matrix-core covariance (windows 129..160), two slots
+    dict(M=24, K=2, N=400, N_fft=512, taps=16, tau=4.0, B=100, Wn=150, slots=2),
+]
+
+
+@pytest.mark.parametrize("c", KEEP_CASES)
+def test_kept_design_backward_matches_recomputed(dev, c):
+    """lmmse_estimate_ls_keep / lmmse_backward_kept: the forward's output and the
+    backward's d_hls and parameter gradients equal those of the calls that form
+    the design again, bit for bit (twice: the state is only read), and the kept
+    gradients meet the oracle bars of the recomputing backward."""
+    print(f"kept design {c}", flush=True)
+    sb = make_slot_batch(M=c["M"], K=c["K"], N=c["N"], N_fft=c["N_fft"], taps=c["taps"], tau=c["tau"],
+                         snr_db=10.0, slots=c["slots"], config_id=4)
+    B, Wn, sig, S = c["B"], c["Wn"], 0.05, c["slots"]
+    X32 = O.despread(sb.y, sb.pilots).astype(np.complex64)
+    X = X32.astype(np.complex128)
+    _, G = O.mse_loss_and_grad(_oracle_estimate(X, B, Wn, sig), sb.H)
+    G32 = G.astype(np.complex64)
+    h, g = _t(X32, dev), _t(G32, dev)
+    with Plan(M=c["M"], K=c["K"], N=c["N"], N_fft=c["N_fft"], B=B, Wn=Wn, rsource="sample",
+              sigma2=sig, max_slots=S) as plan:
+        nbytes = plan.design_state_bytes(S)
+        assert nbytes == S * c["K"] * (c["N"] // B) * (B * Wn + Wn * Wn) * 16
+        state = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        o_plain = plan.estimate_ls(h, sig)
+        o_keep = plan.estimate_ls(h, sig, keep=state)
+        p = [torch.empty(2, dtype=torch.float64, device=dev) for _ in range(3)]
+        d1, _, _ = plan.backward(h, g, params_out=p[0])
+        d2, _, _ = plan.backward(h, g, params_out=p[1], kept=state)
+        d3, _, _ = plan.backward(h, g, params_out=p[2], kept=state)
+        st, info = plan.sync_status()
+    assert st == 0, (st, info)
+    assert torch.equal(o_plain, o_keep)
+    assert torch.equal(d1, d2) and torch.equal(d2, d3)
+    a = [t.cpu().numpy() for t in p]
+    np.testing.assert_array_equal(a[0], a[1])
+    np.testing.assert_array_equal(a[1], a[2])
+    dX_o, gsig_o = O.grad_sample_cov(X, G32.astype(np.complex128), B, Wn, sig)
+    ex = np.linalg.norm(d2.cpu().numpy() - dX_o) / np.linalg.norm(dX_o)
+    print(f"  dX rel {ex:.2e}  dsig gpu {a[1][1]:.8e} oracle {gsig_o:.8e}", flush=True)
+    assert np.isnan(a[1][0])
+    assert ex < 1e-5
+    assert abs(a[1][1] - gsig_o) <= 1e-6 * abs(gsig_o)
+
+
+def test_kept_design_needs_a_resident_window(dev):
+    """Windows the register-resident design holds (here 120) keep no state:
+    size 0, and the keeping calls refuse the plan."""
+    from paper_1802_05427_amd._lib import LmmseError
+    with Plan(M=8, K=2, N=240, N_fft=256, B=60, Wn=120, rsource="sample", sigma2=0.05,
+              max_slots=1) as plan:
+        assert plan.design_state_bytes(1) == 0
+        h = torch.zeros(1, 8, 2, 240, dtype=torch.complex64, device=dev)
+        with pytest.raises(LmmseError):
+            plan.estimate_ls(h, 0.05, keep=torch.empty(256, dtype=torch.uint8, device=dev))
