@@ -324,7 +324,8 @@ int lmmse_backward_dev(lmmse_plan_t plan, int slots, const void *h_ls,
  * doubles, [nmat][B][Wn] then [nmat][Wn][Wn] with nmat = slots * K * N / B
  * (1.05 MB per window at B = 132, Wn = 198).  *bytes is 0 where the plan
  * cannot keep it: not a sample plan, or windows outside 129..208 (the
- * designs held by one compute unit). */
+ * designs held by one compute unit).  LMMSE_ERR_INVALID_ARG for a NULL plan
+ * or bytes, or slots outside 0..max_slots. */
 int lmmse_design_state_size(lmmse_plan_t plan, int slots, size_t *bytes);
 
 /* lmmse_estimate_ls on a sample plan that also writes each window's FP64
