@@ -47,13 +47,21 @@ class SampleLmmseFn(torch.autograd.Function):
     window's own covariance over the antennas, so the gradient to h_ls runs
     through R as well as through the filtering.
 
-        h_hat = SampleLmmseFn.apply(h_ls, sigma2, plan)
+        h_hat = SampleLmmseFn.apply(h_ls, sigma2, plan[, keep])
+
+    keep=True keeps each window's FP64 design from the forward for the
+    backward (lmmse_estimate_ls_keep / lmmse_backward_kept: 1.05 MB per
+    198-wide window, released after the backward) where the plan allows it,
+    instead of forming it again; autograd's check of the saved h_ls ties the
+    backward to the forward's LS values.
     """
 
     @staticmethod
-    def forward(ctx, h_ls, sigma2, plan):
+    def forward(ctx, h_ls, sigma2, plan, keep=False):
         sig = float(sigma2)
-        out = plan.estimate_ls(h_ls, sig)
+        nbytes = plan.design_state_bytes(int(h_ls.shape[0])) if keep else 0
+        ctx.state = torch.empty(nbytes, dtype=torch.uint8, device=h_ls.device) if nbytes else None
+        out = plan.estimate_ls(h_ls, sig, keep=ctx.state)
         ctx.save_for_backward(h_ls)
         ctx.plan = plan
         ctx.sigma2 = sig
@@ -65,9 +73,15 @@ class SampleLmmseFn(torch.autograd.Function):
         plan = ctx.plan
         plan.set_design(float("nan"), ctx.sigma2)
         want = bool(ctx.needs_input_grad[1])
-        d_hls, _, d_sig = plan.backward(h_ls, g.contiguous(), want_params=want)
-        gs = torch.tensor(d_sig, dtype=torch.float64) if want else None
-        return (d_hls if ctx.needs_input_grad[0] else None), gs, None
+        if ctx.state is not None:
+            par = torch.empty(2, dtype=torch.float64, device=h_ls.device)
+            d_hls, _, d_sig_t = plan.backward(h_ls, g.contiguous(), params_out=par, kept=ctx.state)
+            ctx.state = None
+            gs = d_sig_t.cpu() if want else None
+        else:
+            d_hls, _, d_sig = plan.backward(h_ls, g.contiguous(), want_params=want)
+            gs = torch.tensor(d_sig, dtype=torch.float64) if want else None
+        return (d_hls if ctx.needs_input_grad[0] else None), gs, None, None
 
 
 def lmmse_filter(h_ls, tau_rms, sigma2, plan):

@@ -187,6 +187,30 @@ def test_kept_design_backward_matches_recomputed(dev, c):
     assert abs(a[1][1] - gsig_o) <= 1e-6 * abs(gsig_o)
 
 
+def test_sample_autograd_function_kept_design(dev):
+    """SampleLmmseFn with keep=True: the same estimate and gradients, bit for
+    bit, as with the design formed again in the backward."""
+    c = KEEP_CASES[1]
+    sb = make_slot_batch(M=c["M"], K=c["K"], N=c["N"], N_fft=c["N_fft"], taps=c["taps"], tau=c["tau"],
+                         snr_db=10.0, slots=c["slots"], config_id=4)
+    X32 = O.despread(sb.y, sb.pilots).astype(np.complex64)
+    H = _t(sb.H.astype(np.complex64), dev)
+    res = []
+    with Plan(M=c["M"], K=c["K"], N=c["N"], N_fft=c["N_fft"], B=c["B"], Wn=c["Wn"], rsource="sample",
+              sigma2=0.05, max_slots=c["slots"]) as plan:
+        assert plan.design_state_bytes(c["slots"]) > 0
+        for keep in (False, True):
+            h = _t(X32, dev).requires_grad_(True)
+            sig = torch.tensor(0.03, dtype=torch.float64, requires_grad=True)
+            out = SampleLmmseFn.apply(h, sig, plan, keep)
+            loss = (out - H).abs().pow(2).sum() / out.numel()
+            loss.backward()
+            res.append((out.detach(), h.grad.detach(), sig.grad.detach()))
+    assert torch.equal(res[0][0], res[1][0])
+    assert torch.equal(res[0][1], res[1][1])
+    assert torch.equal(res[0][2], res[1][2])
+
+
 def test_kept_design_needs_a_resident_window(dev):
     """Windows the register-resident design holds (here 120) keep no state:
     size 0, and the keeping calls refuse the plan."""
