@@ -483,6 +483,18 @@ hipError_t launch_backward_fixed(Plan& p, int slots, const float2* hls, const fl
     double2* zc = (double2*)(w + L.zc);
     double2* gam = (double2*)(w + L.gam);
     double* per = (double*)(w + L.per);
+    // The design-gradient chain (dW partials -> per-class dW -> Z -> scalars)
+    // reads nothing the dX passes write, so it runs on the plan's second
+    // stream beside them, from a fork before the first dX launch to a join
+    // after its last kernel.
+    hipStream_t sd = st;
+    if (want_params) {
+        if (Wn > 16 * kDwMaxWaves) return hipErrorNotSupported;
+        hipError_t e0 = hipEventRecord(p.fork, st);
+        if (e0 == hipSuccess) e0 = hipStreamWaitEvent(p.side, p.fork, 0);
+        if (e0 != hipSuccess) return e0;
+        sd = p.side;
+    }
 
     // W^H bank
     {
@@ -528,8 +540,7 @@ hipError_t launch_backward_fixed(Plan& p, int slots, const float2* hls, const fl
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !want_params) return e;
 
-    // dW partials -> per-class dW (FP64) -> Z -> scalars
-    if (Wn > 16 * kDwMaxWaves) return hipErrorNotSupported;
+    // dW partials -> per-class dW (FP64) -> Z -> scalars, on sd
     DwArgs dw;
     dw.starts = p.d_starts;
     dw.g = g;
@@ -547,7 +558,7 @@ hipError_t launch_backward_fixed(Plan& p, int slots, const float2* hls, const fl
     const dim3 blockw(64 * ((Wn + 15) / 16));
     switch (geo.dwRT) {
 #define LMMSE_DW(R) \
-    case R: hipLaunchKernelGGL((dw_kernel<R>), gridw, blockw, 0, st, dw); break;
+    case R: hipLaunchKernelGGL((dw_kernel<R>), gridw, blockw, 0, sd, dw); break;
         LMMSE_DW(1) LMMSE_DW(2) LMMSE_DW(3) LMMSE_DW(4) LMMSE_DW(5) LMMSE_DW(6) LMMSE_DW(7)
         LMMSE_DW(8) LMMSE_DW(9) LMMSE_DW(10) LMMSE_DW(11) LMMSE_DW(12) LMMSE_DW(13)
 #undef LMMSE_DW
@@ -555,18 +566,22 @@ hipError_t launch_backward_fixed(Plan& p, int slots, const float2* hls, const fl
             return hipErrorInvalidValue;
     }
     const long long tot = (long long)p.n_classes * B * Wn;
-    hipLaunchKernelGGL(dw_reduce_kernel, dim3((unsigned)((tot + 63) / 64)), dim3(256), 0, st, part,
+    hipLaunchKernelGGL(dw_reduce_kernel, dim3((unsigned)((tot + 63) / 64)), dim3(256), 0, sd, part,
                        p.d_classes, dwc, p.n_classes, p.nb, geo.nch, B, Wn);
     const bool per_block = p.d.rsource == LMMSE_R_USER_R;
-    hipLaunchKernelGGL(z_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, dwc, p.ainv,
+    hipLaunchKernelGGL(z_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, sd, dwc, p.ainv,
                        zc, p.n_classes, B, Wn, per_block ? (long long)Wn * Wn : 0LL, per_block ? 1 : 0);
     const long long totg = (long long)p.n_classes * Wn * Wn;
-    hipLaunchKernelGGL(gamma_kernel, dim3((unsigned)((totg + 255) / 256)), dim3(256), 0, st, p.w64, zc,
+    hipLaunchKernelGGL(gamma_kernel, dim3((unsigned)((totg + 255) / 256)), dim3(256), 0, sd, p.w64, zc,
                        gam, p.n_classes, B, Wn);
-    hipLaunchKernelGGL(param_grad_kernel, dim3(p.n_classes * kPgSlices), dim3(256), 0, st, zc, gam,
+    hipLaunchKernelGGL(param_grad_kernel, dim3(p.n_classes * kPgSlices), dim3(256), 0, sd, zc, gam,
                        p.rd, p.d_class_off, per, B, Wn);
-    hipLaunchKernelGGL(param_sum_kernel, dim3(1), dim3(64), 0, st, per, p.dscal, p.n_classes);
-    return hipGetLastError();
+    hipLaunchKernelGGL(param_sum_kernel, dim3(1), dim3(64), 0, sd, per, p.dscal, p.n_classes);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(p.join, sd);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, p.join, 0);
+    return e;
 }
 
 }  // namespace lmmse

@@ -55,6 +55,11 @@ struct Plan {
     float2* twiddle = nullptr;   // [K] exp(+j 2 pi r / K)
     int* status = nullptr;       // [2] device status word: code, info
     double* dscal = nullptr;     // [4] device scratch for the design backward
+    // the fixed backward's design-gradient chain runs on `side` (default
+    // priority) beside the dX passes: fork / join order it against the
+    // caller's stream
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
     bool ready = false;
     bool have_corr = false;      // caller correlation set (its windows in rwin)
     double design_sigma2 = 0.0;

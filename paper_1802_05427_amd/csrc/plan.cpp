@@ -121,6 +121,9 @@ void free_plan(lmmse_plan* p) {
                     p->wlo,      p->twiddle,   p->status,    p->dscal};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
+    if (p->fork) (void)hipEventDestroy(p->fork);
+    if (p->join) (void)hipEventDestroy(p->join);
+    if (p->side) (void)hipStreamDestroy(p->side);
     delete p;
 }
 
@@ -283,6 +286,10 @@ int lmmse_plan_create(const lmmse_plan_desc* desc, lmmse_plan_t* out) {
                   hipMemcpyHostToDevice) ||
         hipMemcpy(p->twiddle, tw.data(), K * sizeof(float2), hipMemcpyHostToDevice) ||
         hipMemcpy(p->status, zero, sizeof(zero), hipMemcpyHostToDevice))
+        return fail(LMMSE_ERR_HIP);
+    if (hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&p->fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->join, hipEventDisableTiming) != hipSuccess)
         return fail(LMMSE_ERR_HIP);
     if (has_bank) {
         const size_t bytes = fixed_bank_f32_elems(*p) * sizeof(float4);
