@@ -298,7 +298,10 @@ int lmmse_estimate_ls(lmmse_plan_t plan, int slots, const void *h_ls,
  * filters): d_hls only.  Windows wider than 256: d_hls only, for fixed,
  * USER_R and USER plans; requesting d_tau / d_sigma2 there, or any sample
  * backward, returns LMMSE_ERR_UNSUPPORTED before anything is launched.  ws:
- * lmmse_workspace_size bytes. */
+ * lmmse_workspace_size bytes.  The design-parameter gradients of a fixed
+ * design run on a stream the plan owns, beside the d_hls passes, ordered
+ * after the work already on `stream` and before the work queued on it after
+ * the call (event fork and join; graph capture of `stream` takes both). */
 int lmmse_backward(lmmse_plan_t plan, int slots, const void *h_ls,
                    const void *g, void *d_hls, double *d_tau, double *d_sigma2,
                    void *ws, size_t ws_bytes, void *stream);
