@@ -41,6 +41,34 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// 64-lane sum with the result in every lane, in a fixed order: within each
+// 16-lane row by DPP moves (the quad swaps 1-0-3-2 and 2-3-0-1, then the
+// half-row and row mirrors, each an exchange with lanes that hold the other
+// half of the partial sum), then the four row sums read from lanes 0, 16, 32
+// and 48.  No LDS round trip, unlike a shuffle.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+__device__ __forceinline__ double lane_value(double v, int lane) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __builtin_bit_cast(double, (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+    v += dpp_move<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+    v += dpp_move<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+    v += dpp_move<0x141>(v);   // row_half_mirror
+    v += dpp_move<0x140>(v);   // row_mirror
+    return ((lane_value(v, 0) + lane_value(v, 16)) + lane_value(v, 32)) + lane_value(v, 48);
+}
+
 __global__ __launch_bounds__(64) void rd_kernel(double2* rd, int n, int rsource, double L, double tau,
                                                 int taps, int N_fft) {
     const int d = blockIdx.x, lane = threadIdx.x;
@@ -117,11 +145,8 @@ __global__ __launch_bounds__(64) void toeplitz_inverse_kernel(const double2* __r
             sr += u.x;
             si += u.y;
         }
-#pragma unroll
-        for (int m = 32; m >= 1; m >>= 1) {
-            sr += __shfl_xor(sr, m);
-            si += __shfl_xor(si, m);
-        }
+        sr = wave_sum_dpp(sr);
+        si = wave_sum_dpp(si);
         const double2 delta = make_double2(av[k].x + sr, av[k].y + si);
         const double2 kap = make_double2(-delta.x / P, -delta.y / P);
         for (int i = 1 + tid; i < k; i += 64) nxt[i] = zadd(cur[i], zmul(kap, zconj(cur[k - i])));
