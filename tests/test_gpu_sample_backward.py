@@ -221,3 +221,41 @@ def test_kept_design_needs_a_resident_window(dev):
         h = torch.zeros(1, 8, 2, 240, dtype=torch.complex64, device=dev)
         with pytest.raises(LmmseError):
             plan.estimate_ls(h, 0.05, keep=torch.empty(256, dtype=torch.uint8, device=dev))
+
+
+def test_kept_design_error_paths(dev):
+    """The keeping calls through the C ABI: a state shorter than
+    lmmse_design_state_size is LMMSE_ERR_WORKSPACE and a missing one
+    LMMSE_ERR_INVALID_ARG (nothing launched), and a fixed-design plan keeps
+    nothing (size 0, LMMSE_ERR_UNSUPPORTED)."""
+    import ctypes
+
+    from paper_1802_05427_amd import _lib
+    P = lambda t: ctypes.c_void_p(t.data_ptr())   # noqa: E731
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    h = torch.zeros(1, 24, 2, 400, dtype=torch.complex64, device=dev)
+    out = torch.empty_like(h)
+    par = torch.empty(2, dtype=torch.float64, device=dev)
+    with Plan(M=24, K=2, N=400, N_fft=512, B=100, Wn=150, rsource="sample", sigma2=0.05,
+              max_slots=1) as plan:
+        lib = plan._lib
+        need = plan.design_state_bytes(1)
+        assert need > 0
+        short = torch.empty(need - 256, dtype=torch.uint8, device=dev)
+        ws, wsb = plan._workspace(1)
+        assert lib.lmmse_estimate_ls_keep(plan._h, 1, P(h), 0.05, P(out), P(short), need - 256, ws, wsb,
+                                          stream) == _lib.WORKSPACE
+        assert lib.lmmse_estimate_ls_keep(plan._h, 1, P(h), 0.05, P(out), None, 0, ws, wsb,
+                                          stream) == _lib.INVALID_ARG
+        assert lib.lmmse_backward_kept(plan._h, 1, P(h), P(h), P(out), P(par), P(short), need - 256, ws,
+                                       wsb, stream) == _lib.WORKSPACE
+        assert lib.lmmse_backward_kept(plan._h, 1, P(h), P(h), P(out), P(par), None, 0, ws, wsb,
+                                       stream) == _lib.INVALID_ARG
+    with Plan(M=24, K=2, N=400, N_fft=512, B=100, Wn=150, rsource="exp", taps=16, tau_rms=4.0,
+              sigma2=0.05, max_slots=1) as fixed:
+        assert fixed.design_state_bytes(1) == 0
+        big = torch.empty(need, dtype=torch.uint8, device=dev)
+        ws, wsb = fixed._workspace(1)
+        assert fixed._lib.lmmse_backward_kept(fixed._h, 1, P(h), P(h), P(out), P(par), P(big), need, ws,
+                                              wsb, stream) == _lib.UNSUPPORTED
+    torch.cuda.synchronize()
