@@ -232,9 +232,9 @@ __device__ __forceinline__ void ri_store_w(const RiCov& cv, long long mat, int o
             split_c<true>(wf, h, l);
         else
             split_c<false>(wf, h, l);
-        const int wq = (n + 3) & ~3;
-        cv.whi[row * wq + col] = h;
-        cv.wlo[row * wq + col] = l;
+        const long long i = split_w_index(mat * cv.B * (long long)((n + 15) & ~15), cv.B, o, col);
+        cv.whi[i] = h;
+        cv.wlo[i] = l;
     }
 }
 
@@ -597,13 +597,14 @@ __global__ __launch_bounds__(kRiThreads) void resident_inverse_kernel(double2* a
                     ri_store_w(cv, mat, j - off, i, n, make_double2(lam * sx, -lam * sy));
             }
         }
-        const int pad = cv.whi ? ((n + 3) & ~3) - n : cv.w32 ? ((n + 1) & ~1) - n : 0;
+        const int pad = cv.whi ? ((n + 15) & ~15) - n : cv.w32 ? ((n + 1) & ~1) - n : 0;
         for (int e = tid; e < cv.B * pad; e += kRiThreads) {
             const int o = e / pad, col = n + e % pad;
             const long long row = mat * cv.B + o;
             if (cv.whi) {
-                cv.whi[row * (n + pad) + col] = 0u;
-                cv.wlo[row * (n + pad) + col] = 0u;
+                const long long i = split_w_index(mat * cv.B * (long long)(n + pad), cv.B, o, col);
+                cv.whi[i] = 0u;
+                cv.wlo[i] = 0u;
             } else {
                 cv.w32[row * (n + pad) + col] = make_float2(0.f, 0.f);
             }

@@ -48,8 +48,8 @@ struct SampleArgs {
     double2* w64;           // optional: W [mat][B][Wn]
     float2* w32;            // optional: W [mat][B][Wp], Wp = Wn rounded up to even (pad 0)
     double2* ainv;          // optional: A^-1 [mat][Wn][Wn] (row-major, both triangles)
-    uint32_t* whi;          // optional: split W, hi parts [mat][B][Wq] packed (re, im) 16-bit
-    uint32_t* wlo;          // and lo parts (FP16: scaled by 2^11); Wq = Wn rounded up to 4
+    uint32_t* whi;          // optional: split W, hi parts packed (re, im) 16-bit, chunk-major
+    uint32_t* wlo;          // (split_w_index) and lo parts (FP16: scaled by 2^11)
     int split_fp16;         // split format: FP16 (else BF16)
     const int* starts;
     const int* offsets;
@@ -258,7 +258,7 @@ __global__ __launch_bounds__(1024) void sample_design_kernel(SampleArgs a) {
 
     // A now holds -A^-1: W[o][j] = delta(off + o, j) + lam (-A^-1)[off + o][j]
     const int off = a.offsets[b];
-    const int wp = (n + 1) & ~1, wq = (n + 3) & ~3;
+    const int wp = (n + 1) & ~1, w16 = (n + 15) & ~15;
 #pragma unroll
     for (int P = 0; P < NBK; ++P)
 #pragma unroll
@@ -285,7 +285,7 @@ __global__ __launch_bounds__(1024) void sample_design_kernel(SampleArgs a) {
                     wr[col] = make_float2((float)w.x, (float)w.y);
                     if (col == 0 && wp > n) wr[n] = make_float2(0.f, 0.f);   // pad column
                 }
-                if (a.whi) store_split_w(a.whi, a.wlo, (mat * a.B + o) * wq, col, n, wq, w,
+                if (a.whi) store_split_w(a.whi, a.wlo, mat * a.B * (long long)w16, a.B, o, col, n, w16, w,
                                          a.split_fp16);
             }
         }
@@ -554,11 +554,12 @@ static int large_chunk(const lmmse_plan_desc& d, int slots) {
 static size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Compact filters of every (slot, user, block): FP32 [mat][B][Wp] (Wp = Wn
-// rounded up to even), or hi and lo parts [mat][B][Wq] each (Wq = Wn
-// rounded up to 4) of packed 16-bit pairs.
+// rounded up to even), or hi and lo parts of packed 16-bit pairs, B x W16
+// per window (W16 = Wn rounded up to 16) in the chunk-major order of
+// split_w_index.
 static size_t filter_area_bytes(const lmmse_plan_desc& d, long long nmat) {
     if (d.precision == LMMSE_FP32) return up256((size_t)nmat * d.B * ((d.Wn + 1) & ~1) * sizeof(float2));
-    return up256(2 * (size_t)nmat * d.B * ((d.Wn + 3) & ~3) * sizeof(uint32_t));
+    return up256(2 * (size_t)nmat * d.B * ((d.Wn + 15) & ~15) * sizeof(uint32_t));
 }
 
 size_t sample_workspace_bytes(const lmmse_plan_desc& d, int slots) {
@@ -585,7 +586,7 @@ hipError_t launch_sample_estimate(const Plan& p, int slots, const float2* hls, d
     if ((keep_w64 == nullptr) != (keep_ainv == nullptr) || (keep_w64 && !resident_design_fits(p.d.Wn)))
         return hipErrorInvalidValue;
     const bool split = p.d.precision != LMMSE_FP32;
-    const int wp = (p.d.Wn + 1) & ~1, wq = (p.d.Wn + 3) & ~3;
+    const int wp = (p.d.Wn + 1) & ~1, wq = (p.d.Wn + 15) & ~15;   // split parts: W16
     float2* w32 = split ? nullptr : reinterpret_cast<float2*>(ws);
     uint32_t* whi = split ? reinterpret_cast<uint32_t*>(ws) : nullptr;
     uint32_t* wlo = split ? whi + nmat * p.d.B * wq : nullptr;

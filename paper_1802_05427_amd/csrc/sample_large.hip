@@ -252,7 +252,7 @@ __global__ __launch_bounds__(256) void large_filters_kernel(double2* a, const in
     const long long mat = blockIdx.x;
     double2* am = a + mat * Wn * Wn;
     const int off = offsets[mat % nb];
-    const int wp = (Wn + 1) & ~1;
+    const int wp = (Wn + 1) & ~1, w16 = (Wn + 15) & ~15;
     for (int e = threadIdx.x; e < B * wp; e += 256) {
         const int o = e / wp, j = e - o * wp;
         if (j >= Wn) {
@@ -263,7 +263,7 @@ __global__ __launch_bounds__(256) void large_filters_kernel(double2* a, const in
         const double2 w = make_double2((off + o == j ? 1.0 : 0.0) + lam * s.x, lam * s.y);
         if (w64) w64[(mat * B + o) * Wn + j] = w;
         if (w32) w32[(mat * B + o) * wp + j] = make_float2((float)w.x, (float)w.y);
-        if (whi) store_split_w(whi, wlo, (mat * B + o) * ((Wn + 3) & ~3), j, Wn, (Wn + 3) & ~3, w, fp16);
+        if (whi) store_split_w(whi, wlo, mat * B * (long long)w16, B, o, j, Wn, w16, w, fp16);
     }
     if (negate) {
         __syncthreads();   // every read of S above is done

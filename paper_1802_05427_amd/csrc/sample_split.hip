@@ -8,10 +8,11 @@
 // Workgroup: 4 waves x 2 column tiles = 128 antennas of one window, RT
 // 16-row tiles of the real embedding of one row group, the window streamed in
 // chunks of 16 complex rows (the 32 reals of one MFMA's K).
-//  * filter parts: the design writes them compact, [mat][B][Wq] packed
-//    (re, im) 16-bit pairs.  A chunk's rows are copied global-to-LDS (four
-//    16-byte slots of 4 complex entries per row and part) into one of two
-//    buffers; lane (i16, kq) of a tile reads slot kq of its output row and
+//  * filter parts: the design writes them compact and chunk-major, packed
+//    (re, im) 16-bit pairs, the 16 columns of one chunk of all B rows of a
+//    window in one contiguous block (split_w_index).  A chunk's rows are
+//    copied global-to-LDS (four 16-byte slots of 4 complex entries per row and
+//    part, whole 128-byte lines) into one of two buffers; lane (i16, kq) of a tile reads slot kq of its output row and
 //    forms its embedded operand in registers: (re, -im) pairs for the real
 //    output row, (im, re) for the imaginary one;
 //  * LS values: one chunk ahead in registers, split into hi / lo when written
@@ -23,7 +24,7 @@ namespace lmmse {
 
 struct SampleSplitArgs {
     const float2* hls;
-    const uint32_t* whi;   // [mat][B][Wq]
+    const uint32_t* whi;   // per window B x Wq, chunk-major (Wq = Wn rounded up to 16)
     const uint32_t* wlo;
     const int* starts;
     float2* out;
@@ -49,10 +50,10 @@ constexpr int ss_slots() { return (RT * 32 + 63) / 64 * 64; }
 
 // Filter parts of chunk cc for output rows o0 .. o0 + 8 RT - 1 into LDS: slot
 // 4 ol + (kq ^ (ol & 3)) of each part buffer holds entries 16 cc + 4 kq ..
-// +3 of row o0 + ol.  Rows past B repeat row B - 1 (discarded outputs);
-// slots past the row read slot 0 (they meet zero LS values).
+// +3 of row o0 + ol, read from the chunk's contiguous block.  Rows past B
+// repeat row B - 1 (discarded outputs); the columns past Wn are zero.
 template <int RT>
-__device__ __forceinline__ void split_copy_w(const uint32_t* whi, const uint32_t* wlo, int B, int Wq,
+__device__ __forceinline__ void split_copy_w(const uint32_t* whi, const uint32_t* wlo, int B,
                                              int o0, int cc, int wave, int lane, float4* dhi,
                                              float4* dlo) {
     constexpr int NV = ss_slots<RT>();
@@ -64,9 +65,7 @@ __device__ __forceinline__ void split_copy_w(const uint32_t* whi, const uint32_t
             if (base < NV) {
                 const int sl = base + lane, ol = sl >> 2, kq = (sl & 3) ^ (ol & 3);
                 const int o = min(o0 + ol, B - 1);
-                int j = 16 * cc + 4 * kq;
-                if (j >= Wq) j = 0;
-                const uint32_t* src = (part ? wlo : whi) + (unsigned)(o * Wq + j);
+                const uint32_t* src = (part ? wlo : whi) + (unsigned)((cc * B + o) * 16 + 4 * kq);
                 float4* dst = (part ? dlo : dhi) + base;
                 __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst,
                                                  16, 0, 0);
@@ -146,7 +145,7 @@ __device__ __forceinline__ void ss_step(const SampleSplitCtx& x, int cc, uint32_
         bl[ct] = xl4[x.kq * sXP + c];
     }
     if (cc + 1 < x.nchunks)
-        split_copy_w<RT>(x.whi, x.wlo, x.a.B, x.a.Wq, x.o0, cc + 1, x.wave, x.lane, hnext, lnext);
+        split_copy_w<RT>(x.whi, x.wlo, x.a.B, x.o0, cc + 1, x.wave, x.lane, hnext, lnext);
     const int im = x.l16 & 1;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
@@ -204,7 +203,7 @@ __global__ __launch_bounds__(sThreads, 2) void apply_sample_split_kernel(SampleS
 #pragma unroll
         for (int ct = 0; ct < sCT; ++ct) acc[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
     SampleSplitRaw raw;
-    split_copy_w<RT>(x.whi, x.wlo, a.B, a.Wq, x.o0, 0, wave, lane, hA, lA);
+    split_copy_w<RT>(x.whi, x.wlo, a.B, x.o0, 0, wave, lane, hA, lA);
     ss_load_x(a, x.xbase, x.xstride, x.m0, 0, tid, raw);
     __builtin_amdgcn_s_waitcnt(0x0F70);
     __syncthreads();
@@ -248,7 +247,7 @@ hipError_t launch_apply_sample_split(const Plan& p, long long nmat, const float2
     a.N = p.d.N;
     a.B = p.d.B;
     a.Wn = p.d.Wn;
-    a.Wq = (p.d.Wn + 3) & ~3;
+    a.Wq = (p.d.Wn + 15) & ~15;
     a.nb = p.nb;
     a.rgroups = p.srgroups;
     a.G16 = p.G16;

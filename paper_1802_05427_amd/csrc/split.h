@@ -69,22 +69,32 @@ __device__ __forceinline__ float4 scale2048_f16(const float4& a) {
     return __builtin_bit_cast(float4, h);
 }
 
-// Filter entry (row base + col) of a split compact filter [rows][Wq], and
-// at col 0 the zero pad entries Wn..Wq-1 of the row.
-__device__ __forceinline__ void store_split_w(uint32_t* whi, uint32_t* wlo, long long row, int col,
-                                              int Wn, int Wq, double2 w, int fp16) {
+// Per-window split filter parts, chunk-major: entry (o, col) of the window
+// whose block starts at wbase (window index x B x W16) sits at
+// wbase + ((col / 16) B + o) 16 + col % 16, so that the 16 columns of one
+// chunk of all B rows are one contiguous block; W16 = Wn rounded up to 16.
+__device__ __forceinline__ long long split_w_index(long long wbase, int B, int o, int col) {
+    return wbase + ((long long)(col >> 4) * B + o) * 16 + (col & 15);
+}
+
+// Entry (o, col) of a window's split filter parts, and at col 0 the zero pad
+// entries Wn..W16-1 of row o.
+__device__ __forceinline__ void store_split_w(uint32_t* whi, uint32_t* wlo, long long wbase, int B, int o,
+                                              int col, int Wn, int W16, double2 w, int fp16) {
     uint32_t h, l;
     const float2 wf = make_float2((float)w.x, (float)w.y);
     if (fp16)
         split_c<true>(wf, h, l);
     else
         split_c<false>(wf, h, l);
-    whi[row + col] = h;
-    wlo[row + col] = l;
+    const long long i = split_w_index(wbase, B, o, col);
+    whi[i] = h;
+    wlo[i] = l;
     if (col == 0)
-        for (int c = Wn; c < Wq; ++c) {
-            whi[row + c] = 0u;
-            wlo[row + c] = 0u;
+        for (int c = Wn; c < W16; ++c) {
+            const long long k = split_w_index(wbase, B, o, c);
+            whi[k] = 0u;
+            wlo[k] = 0u;
         }
 }
 

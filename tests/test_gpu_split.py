@@ -76,6 +76,7 @@ def test_split_estimate_matches_oracle(dev, prec, cfg, snr):
     dict(M=130, K=2, N=300, N_fft=512, taps=16, tau=4.0, B=100, Wn=150, slots=1),   # 2 antenna groups
     dict(M=20, K=2, N=400, N_fft=512, taps=16, tau=4.0, B=100, Wn=200, slots=1),    # wide window
     dict(M=40, K=2, N=3300, N_fft=4096, taps=144, tau=32.0, B=132, Wn=198, slots=1),
+    dict(M=20, K=2, N=480, N_fft=512, taps=16, tau=4.0, B=120, Wn=240, slots=1),    # panel-swept design
 ])
 @pytest.mark.parametrize("snr", [0.0, 20.0])
 def test_split_sample_estimate_matches_oracle(dev, prec, cfg, snr):
