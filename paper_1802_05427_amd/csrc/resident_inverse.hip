@@ -224,7 +224,9 @@ struct RiCov {
 __device__ __forceinline__ void ri_store_w(const RiCov& cv, long long mat, int o, int col, int n, double2 w) {
     const long long row = mat * cv.B + o;
     if (cv.w64) cv.w64[row * n + col] = w;
-    if (cv.w32) cv.w32[row * ((n + 1) & ~1) + col] = make_float2((float)w.x, (float)w.y);
+    if (cv.w32)   // FP32 filters: the chunk-major order of the split parts
+        cv.w32[split_w_index(mat * cv.B * (long long)((n + 15) & ~15), cv.B, o, col)] =
+            make_float2((float)w.x, (float)w.y);
     if (cv.whi) {
         uint32_t h, l;
         const float2 wf = make_float2((float)w.x, (float)w.y);
@@ -597,16 +599,15 @@ __global__ __launch_bounds__(kRiThreads) void resident_inverse_kernel(double2* a
                     ri_store_w(cv, mat, j - off, i, n, make_double2(lam * sx, -lam * sy));
             }
         }
-        const int pad = cv.whi ? ((n + 15) & ~15) - n : cv.w32 ? ((n + 1) & ~1) - n : 0;
+        const int pad = (cv.whi || cv.w32) ? ((n + 15) & ~15) - n : 0;
         for (int e = tid; e < cv.B * pad; e += kRiThreads) {
             const int o = e / pad, col = n + e % pad;
-            const long long row = mat * cv.B + o;
+            const long long i = split_w_index(mat * cv.B * (long long)(n + pad), cv.B, o, col);
             if (cv.whi) {
-                const long long i = split_w_index(mat * cv.B * (long long)(n + pad), cv.B, o, col);
                 cv.whi[i] = 0u;
                 cv.wlo[i] = 0u;
             } else {
-                cv.w32[row * (n + pad) + col] = make_float2(0.f, 0.f);
+                cv.w32[i] = make_float2(0.f, 0.f);
             }
         }
     } else {

@@ -46,7 +46,8 @@ struct SampleArgs {
     const double2* r_in;    // optional [mat][Wn][Wn] (row-major), used instead of hls
     double2* r_out;         // optional: R (before lam) [mat][Wn][Wn]
     double2* w64;           // optional: W [mat][B][Wn]
-    float2* w32;            // optional: W [mat][B][Wp], Wp = Wn rounded up to even (pad 0)
+    float2* w32;            // optional: W, B x W16 per window in the chunk-major order of
+                            // split_w_index (W16 = Wn rounded up to 16, pad 0)
     double2* ainv;          // optional: A^-1 [mat][Wn][Wn] (row-major, both triangles)
     uint32_t* whi;          // optional: split W, hi parts packed (re, im) 16-bit, chunk-major
     uint32_t* wlo;          // (split_w_index) and lo parts (FP16: scaled by 2^11)
@@ -281,9 +282,10 @@ __global__ __launch_bounds__(1024) void sample_design_kernel(SampleArgs a) {
                 const double2 w = make_double2((row == col ? 1.0 : 0.0) + lam_s * v.x, lam_s * vy);
                 if (a.w64) a.w64[(mat * a.B + o) * n + col] = w;
                 if (a.w32) {
-                    float2* wr = a.w32 + (mat * a.B + o) * wp;
-                    wr[col] = make_float2((float)w.x, (float)w.y);
-                    if (col == 0 && wp > n) wr[n] = make_float2(0.f, 0.f);   // pad column
+                    const long long wb = mat * a.B * (long long)w16;
+                    a.w32[split_w_index(wb, a.B, o, col)] = make_float2((float)w.x, (float)w.y);
+                    if (col == 0)   // pad columns
+                        for (int c = n; c < w16; ++c) a.w32[split_w_index(wb, a.B, o, c)] = make_float2(0.f, 0.f);
                 }
                 if (a.whi) store_split_w(a.whi, a.wlo, mat * a.B * (long long)w16, a.B, o, col, n, w16, w,
                                          a.split_fp16);
@@ -296,7 +298,8 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 struct SampleApplyArgs {
     const float2* hls;
-    const float2* w32;      // [mat][B][Wp] compact complex filters, Wp = Wn rounded up to even
+    const float2* w32;      // compact complex filters, B x Wp per window in the chunk-major
+                            // order of split_w_index, Wp = Wn rounded up to 16
     const int* starts;
     float2* out;
     long long n_tiles;
@@ -316,11 +319,11 @@ constexpr int pXP = pCols + 1;           // LS chunk row stride (16-byte slots),
 // loads: 16-byte slot s of the buffer holds W[o][16cc + 2jp .. +1] (one
 // complex pair) with o = s / 8 and jp = (s % 8) ^ (o % 8), a swizzle that
 // makes the 8 rows a lane group reads at one jp fall into distinct banks.
-// Rows are Wp (even) entries long, so every pair is 16-byte aligned and in
-// the row.  Rows past B and pairs past the row read a valid pair instead;
-// they only meet zero LS values or produce discarded outputs.
+// The window's filters are chunk-major (the 16 columns of chunk cc of all B
+// rows one contiguous block, whole 128-byte rows, zero past Wn).  Rows past B
+// read row B - 1 and produce discarded outputs.
 template <int RT>
-__device__ __forceinline__ void sample_copy_w(const float2* wmat, int B, int Wp, int o0, int cc,
+__device__ __forceinline__ void sample_copy_w(const float2* wmat, int B, int o0, int cc,
                                               int wave, int lane, float4* wdst) {
     constexpr int NV = RT * 64;   // 8 RT rows x 8 slots
 #pragma unroll
@@ -329,9 +332,7 @@ __device__ __forceinline__ void sample_copy_w(const float2* wmat, int B, int Wp,
         if (base < NV) {
             const int sl = base + lane, ol = sl >> 3, jp = (sl & 7) ^ (ol & 7);
             const int o = min(o0 + ol, B - 1);
-            int j = 16 * cc + 2 * jp;
-            if (j >= Wp) j = 0;
-            const float2* src = wmat + (unsigned)(o * Wp + j);
+            const float2* src = wmat + (unsigned)((cc * B + o) * 16 + 2 * jp);   // chunk-major
             __builtin_amdgcn_global_load_lds(
                 src, (__attribute__((address_space(3))) void*)(wdst + base), 16, 0, 0);
         }
@@ -405,7 +406,7 @@ __device__ __forceinline__ void sample_step(const SampleCtx& x, int cc, float4* 
     sample_mfma_group<RT>(acc, xv, wcur, 0, x.l16, x.q);
 #pragma unroll
     for (int ct = 0; ct < pCT; ++ct) xv[ct] = xs4[(4 + x.q) * pXP + (x.wave * pCT + ct) * 16 + x.l16];
-    if (cc + 1 < x.nchunks) sample_copy_w<RT>(x.wmat, x.a.B, x.a.Wp, x.o0, cc + 1, x.wave, x.lane, wnext);
+    if (cc + 1 < x.nchunks) sample_copy_w<RT>(x.wmat, x.a.B, x.o0, cc + 1, x.wave, x.lane, wnext);
     if (16 * cc + 8 < x.a.Wn) sample_mfma_group<RT>(acc, xv, wcur, 1, x.l16, x.q);
     __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's copies have landed
     __syncthreads();
@@ -445,7 +446,7 @@ __global__ __launch_bounds__(pThreads, 2) void apply_sample_kernel(SampleApplyAr
 #pragma unroll
         for (int ct = 0; ct < pCT; ++ct) acc[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
     SampleRaw raw;
-    sample_copy_w<RT>(x.wmat, a.B, a.Wp, x.o0, 0, wave, lane, wA);
+    sample_copy_w<RT>(x.wmat, a.B, x.o0, 0, wave, lane, wA);
     sample_load_x(a, x.xbase, x.xstride, x.m0, 0, tid, raw);
     __builtin_amdgcn_s_waitcnt(0x0F70);
     __syncthreads();
@@ -553,12 +554,11 @@ static int large_chunk(const lmmse_plan_desc& d, int slots) {
 
 static size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Compact filters of every (slot, user, block): FP32 [mat][B][Wp] (Wp = Wn
-// rounded up to even), or hi and lo parts of packed 16-bit pairs, B x W16
-// per window (W16 = Wn rounded up to 16) in the chunk-major order of
-// split_w_index.
+// Compact filters of every (slot, user, block): FP32 complex values, or hi
+// and lo parts of packed 16-bit pairs, B x W16 per window (W16 = Wn rounded
+// up to 16) in the chunk-major order of split_w_index.
 static size_t filter_area_bytes(const lmmse_plan_desc& d, long long nmat) {
-    if (d.precision == LMMSE_FP32) return up256((size_t)nmat * d.B * ((d.Wn + 1) & ~1) * sizeof(float2));
+    if (d.precision == LMMSE_FP32) return up256((size_t)nmat * d.B * ((d.Wn + 15) & ~15) * sizeof(float2));
     return up256(2 * (size_t)nmat * d.B * ((d.Wn + 15) & ~15) * sizeof(uint32_t));
 }
 
@@ -586,7 +586,7 @@ hipError_t launch_sample_estimate(const Plan& p, int slots, const float2* hls, d
     if ((keep_w64 == nullptr) != (keep_ainv == nullptr) || (keep_w64 && !resident_design_fits(p.d.Wn)))
         return hipErrorInvalidValue;
     const bool split = p.d.precision != LMMSE_FP32;
-    const int wp = (p.d.Wn + 1) & ~1, wq = (p.d.Wn + 15) & ~15;   // split parts: W16
+    const int wp = (p.d.Wn + 15) & ~15, wq = wp;   // W16 for both filter formats
     float2* w32 = split ? nullptr : reinterpret_cast<float2*>(ws);
     uint32_t* whi = split ? reinterpret_cast<uint32_t*>(ws) : nullptr;
     uint32_t* wlo = split ? whi + nmat * p.d.B * wq : nullptr;
@@ -649,7 +649,7 @@ hipError_t launch_sample_estimate(const Plan& p, int slots, const float2* hls, d
     aa.N = p.d.N;
     aa.B = p.d.B;
     aa.Wn = p.d.Wn;
-    aa.Wp = (p.d.Wn + 1) & ~1;
+    aa.Wp = (p.d.Wn + 15) & ~15;
     aa.nb = p.nb;
     aa.rgroups = p.rgroups;
     aa.G16 = p.G16;

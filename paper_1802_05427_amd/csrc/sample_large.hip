@@ -252,17 +252,20 @@ __global__ __launch_bounds__(256) void large_filters_kernel(double2* a, const in
     const long long mat = blockIdx.x;
     double2* am = a + mat * Wn * Wn;
     const int off = offsets[mat % nb];
-    const int wp = (Wn + 1) & ~1, w16 = (Wn + 15) & ~15;
-    for (int e = threadIdx.x; e < B * wp; e += 256) {
-        const int o = e / wp, j = e - o * wp;
+    // FP32 and split filters: B x W16 per window in the chunk-major order of
+    // split_w_index, the pad columns Wn..W16-1 zero
+    const int w16 = (Wn + 15) & ~15;
+    const long long wb = mat * B * (long long)w16;
+    for (int e = threadIdx.x; e < B * w16; e += 256) {
+        const int o = e / w16, j = e - o * w16;
         if (j >= Wn) {
-            if (w32) w32[(mat * B + o) * wp + j] = make_float2(0.f, 0.f);
+            if (w32) w32[split_w_index(wb, B, o, j)] = make_float2(0.f, 0.f);
             continue;
         }
         const double2 s = am[(long long)(off + o) * Wn + j];
         const double2 w = make_double2((off + o == j ? 1.0 : 0.0) + lam * s.x, lam * s.y);
         if (w64) w64[(mat * B + o) * Wn + j] = w;
-        if (w32) w32[(mat * B + o) * wp + j] = make_float2((float)w.x, (float)w.y);
+        if (w32) w32[split_w_index(wb, B, o, j)] = make_float2((float)w.x, (float)w.y);
         if (whi) store_split_w(whi, wlo, mat * B * (long long)w16, B, o, j, Wn, w16, w, fp16);
     }
     if (negate) {
